@@ -1,0 +1,289 @@
+"""Pins for the CPU oracle: each check rests on something other than the
+oracle itself -- brute force with an independent formulation, textbook
+Eulerian numbers, published RNG outputs, exact invariants and planted
+recovery."""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def _eulerian_table(golden_dir):
+    rows = {}
+    with open(os.path.join(golden_dir, "eulerian_numbers.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            n, vals = line.split(":")
+            rows[int(n)] = [int(v) for v in vals.split()]
+    return rows
+
+
+def _brute_support(X, series, approx, neg):
+    """Independent formulation: order the series' cells of each row by
+    (value, column index) with Python's sort, read off the induced
+    permutation, and count its descents and ascents."""
+    k = len(series)
+    t = ((k - 1) * (1000 - approx)) // 1000
+    out = []
+    for row in X:
+        order = sorted(range(k), key=lambda j: (float(row[series[j]]), series[j]))
+        rank = [0] * k
+        for pos, j in enumerate(order):
+            rank[j] = pos
+        desc = sum(rank[j] > rank[j + 1] for j in range(k - 1))
+        asc = (k - 1) - desc
+        out.append(int(desc <= t or (neg and asc <= t)))
+    return np.array(out, dtype=np.uint8)
+
+
+def _all_series(C, kmax):
+    for k in range(2, kmax + 1):
+        yield from itertools.permutations(range(C), k)
+
+
+@pytest.mark.parametrize("kind", ["random", "ties"])
+@pytest.mark.parametrize("approx,neg", [(1000, 0), (1000, 1), (850, 1), (700, 0), (500, 1),
+                                        (0, 0)])
+def test_brute_force_all_series(kind, approx, neg):
+    C, R = 6, 8
+    if kind == "random":
+        X = synth.random_matrix(R, C, seed=11)
+    else:
+        X = synth.tie_matrix(R, C, levels=3, seed=12)
+    seqs = [list(s) for s in _all_series(C, C)]
+    p = oracle.make_params(approx_permille=approx, negative_trends=neg, min_rows=1,
+                           k_score_min=2)
+    ev = oracle.evaluate(X, seqs, params=p)
+    for i, s in enumerate(seqs):
+        want = _brute_support(X, s, approx, neg)
+        np.testing.assert_array_equal(ev.support[i], want, err_msg=str(s))
+        assert ev.count[i] == want.sum()
+
+
+def test_eulerian_closed_form(golden_dir):
+    A = _eulerian_table(golden_dir)
+    for k in range(2, 8):
+        perms = np.array(list(itertools.permutations(range(k))), dtype=np.float32)
+        for approx in (1000, 900, 850, 700, 500, 300, 0):
+            t = ((k - 1) * (1000 - approx)) // 1000
+            for neg in (0, 1):
+                p = oracle.make_params(approx_permille=approx, negative_trends=neg,
+                                       min_rows=1, k_score_min=2)
+                ev = oracle.evaluate(perms, [list(range(k))], params=p)
+                # rows = all permutations; a row's descents along the series
+                # are the descents of the permutation's inverse, which has the
+                # same descent distribution
+                want = sum(A[k][d] for d in range(k)
+                           if d <= t or (neg and (k - 1 - d) <= t))
+                assert ev.count[0] == want, (k, approx, neg)
+
+
+def test_eulerian_printed_examples():
+    """k=5: t=0 -> 1 (2 with reversed trends); t=1 -> 27 (54); k=6, t=1 -> 58 (116)."""
+    for k, approx, want in ((5, 1000, (1, 2)), (5, 700, (27, 54)), (6, 800, (58, 116))):
+        perms = np.array(list(itertools.permutations(range(k))), dtype=np.float32)
+        got = []
+        for neg in (0, 1):
+            p = oracle.make_params(approx_permille=approx, negative_trends=neg, min_rows=1,
+                                   k_score_min=2)
+            got.append(int(oracle.evaluate(perms, [list(range(k))], params=p).count[0]))
+        assert tuple(got) == want
+
+
+def test_two_column_special_cases():
+    X = synth.random_matrix(50, 7, seed=3)
+    X[5, 2] = X[5, 4]  # a tie: the smaller column index comes first
+    p0 = oracle.make_params(negative_trends=0, min_rows=1, k_score_min=2)
+    p1 = oracle.make_params(negative_trends=1, min_rows=1, k_score_min=2)
+    seqs = [[2, 4], [4, 2], [0, 6]]
+    e0 = oracle.evaluate(X, seqs, params=p0)
+    e1 = oracle.evaluate(X, seqs, params=p1)
+    for i, (a, b) in enumerate(seqs):
+        want = (X[:, a] < X[:, b]) | ((X[:, a] == X[:, b]) & (a < b))
+        np.testing.assert_array_equal(e0.support[i].astype(bool), want)
+        assert e1.count[i] == X.shape[0]
+
+
+def test_invariants():
+    rng = np.random.default_rng(5)
+    X = synth.random_matrix(40, 9, seed=6)
+    seqs = [list(rng.permutation(9)[:int(rng.integers(2, 10))]) for _ in range(60)]
+    base = dict(min_rows=1, k_score_min=2)
+    for neg in (0, 1):
+        p = oracle.make_params(approx_permille=800, negative_trends=neg, **base)
+        ev = oracle.evaluate(X, seqs, params=p)
+        # row permutation permutes supports
+        perm = rng.permutation(X.shape[0])
+        evp = oracle.evaluate(X[perm], seqs, params=p)
+        np.testing.assert_array_equal(evp.support, ev.support[:, perm])
+        # within-row ranks (index tie-break) leave every support unchanged
+        ranks = np.argsort(np.argsort(X, axis=1, kind="stable"), axis=1).astype(np.float32)
+        np.testing.assert_array_equal(oracle.evaluate(ranks, seqs, params=p).support,
+                                      ev.support)
+        # column relabelling (tie-free matrix)
+        cp = rng.permutation(X.shape[1])
+        inv = np.argsort(cp)
+        Xc = X[:, cp]
+        seqs_c = [[int(inv[c]) for c in s] for s in seqs]
+        np.testing.assert_array_equal(oracle.evaluate(Xc, seqs_c, params=p).support,
+                                      ev.support)
+        # count is the size of the support
+        np.testing.assert_array_equal(ev.count, ev.support.sum(axis=1))
+    # reversed trends: support = support(I) | support(reverse I) without them
+    p0 = oracle.make_params(approx_permille=800, negative_trends=0, **base)
+    p1 = oracle.make_params(approx_permille=800, negative_trends=1, **base)
+    e_fwd = oracle.evaluate(X, seqs, params=p0)
+    e_rev = oracle.evaluate(X, [s[::-1] for s in seqs], params=p0)
+    e_neg = oracle.evaluate(X, seqs, params=p1)
+    np.testing.assert_array_equal(e_neg.support, e_fwd.support | e_rev.support)
+    np.testing.assert_array_equal(oracle.evaluate(X, [s[::-1] for s in seqs], params=p1).support,
+                                  e_neg.support)
+    # the count never falls as the tolerance grows
+    prev = None
+    for approx in (1000, 900, 800, 600, 400, 0):
+        c = oracle.evaluate(X, seqs, params=oracle.make_params(approx_permille=approx,
+                                                               negative_trends=1, **base)).count
+        if prev is not None:
+            assert np.all(c >= prev)
+        prev = c
+
+
+def test_fitness_identities():
+    case = synth.workload_matrix(0)
+    X = case.X
+    planted = [int(c) for c in case.truth[0].cols]
+    p = oracle.make_params(negative_trends=0)
+    ev = oracle.evaluate(X, [planted, planted[:3], [0, 1]], params=p)
+    # empty archive: no penalty
+    np.testing.assert_array_equal(ev.fitness, ev.score)
+    for i in range(3):
+        if ev.score[i] > 0:
+            k = [5, 3, 2][i]
+            # the size score is an exact integer multiple of 2^k
+            assert ev.score[i] == float(ev.count[i]) * 2.0 ** k
+    # an archived copy of the individual covers all its cells: penalised
+    arch = oracle.Archive(ev.support[:1].copy(), [planted])
+    ev2 = oracle.evaluate(X, [planted], archive=arch, params=p)
+    assert ev2.overlap[0, 0] == ev.count[0]
+    assert ev2.fitness[0] == ev.score[0] / 2
+    # full overlap is allowed at theta = 1000 per mille
+    ev3 = oracle.evaluate(X, [planted], archive=arch,
+                          params=oracle.make_params(negative_trends=0, overlap_permille=1000))
+    assert ev3.fitness[0] == ev.score[0]
+    # a member sharing no rows never penalises
+    arch0 = oracle.Archive(np.zeros_like(ev.support[:1]), [planted])
+    assert oracle.evaluate(X, [planted], archive=arch0, params=p).fitness[0] == ev.score[0]
+    # each overlapping member halves again
+    arch2 = oracle.Archive(np.repeat(ev.support[:1], 3, axis=0), [planted, planted, planted])
+    assert oracle.evaluate(X, [planted], archive=arch2, params=p).fitness[0] == ev.score[0] / 8
+
+
+def test_invalid_series_rejected():
+    X = synth.random_matrix(10, 5, seed=1)
+    for bad in ([1], [0, 0], [0, 5], list(range(5)) + [0]):
+        with pytest.raises(ValueError):
+            oracle.evaluate(X, [bad])
+
+
+def test_splitmix64_known_answers(golden_dir):
+    with open(os.path.join(golden_dir, "splitmix64_seed0.txt")) as f:
+        want = [int(l, 16) for l in f if l.strip() and not l.startswith("#")]
+    assert oracle.splitmix64_stream(0, len(want)) == want
+
+
+def test_uniform_draw_distribution():
+    bounds = [7] * 70000
+    xs = np.array(oracle.uniform_stream(123, bounds))
+    assert xs.min() == 0 and xs.max() == 6
+    counts = np.bincount(xs, minlength=7)
+    chi2 = ((counts - 10000.0) ** 2 / 10000.0).sum()
+    assert chi2 < 30  # 6 dof, p ~ 4e-5
+    # a power-of-two bound rejects nothing: the low bits of the raw stream
+    raw = oracle.splitmix64_stream(9, 100)
+    assert oracle.uniform_stream(9, [256] * 100) == [r & 255 for r in raw]
+    assert oracle.uniform_stream(9, [1] * 5) == [0] * 5
+
+
+def test_generator_determinism():
+    a = synth.workload_matrix(0)
+    b = synth.workload_matrix(0)
+    assert a.sha256() == b.sha256()
+    assert a.X.shape == (100, 20) and a.X.dtype == np.float32
+    t = a.truth[0]
+    assert t.rows.size == 10 and t.cols.size == 5
+    vals = a.X[np.ix_(t.rows, t.cols)]
+    assert np.all(np.diff(vals, axis=1) > 0)
+
+
+def _c0_params(**kw):
+    w = synth.workload(0)
+    d = dict(approx_permille=850, negative_trends=w.negative_trends, overlap_permille=750,
+             min_rows=5, k_min=w.k_min, k_max=w.k_max, archive_size=w.archive_size,
+             n_out=w.n_out, population=w.population, generations=w.generations,
+             max_tabu_hits=100000, tournament=4, max_attempts=1000)
+    d.update(kw)
+    return oracle.make_params(**d)
+
+
+def test_run_planted_recovery():
+    """Planted recovery: a 100 x 20 uniform matrix with one strictly increasing
+    30-row x 5-column plant, run with the tiny workload's loop settings. The
+    top bicluster must be the planted series with every planted row, for most
+    (data seed, run seed) pairs. (The tiny workload's own 10-row plant is not
+    a recovery case: under the n * 2^k size score its 2-4 column sub-series
+    rank below the best random pairs, so the search stalls on those.)"""
+    ok = 0
+    for ds in range(5):
+        case = synth.planted_matrix(100, 20, background="uniform", n_planted=1,
+                                    rows_range=(30, 30), cols_range=(5, 5), sigma=0.0,
+                                    strict=True, seed=1100 + ds)
+        t = case.truth[0]
+        follows = np.all(np.diff(case.X[:, t.cols], axis=1) > 0, axis=1)
+        for seed in range(synth.GA_SEED, synth.GA_SEED + 4):
+            res = oracle.run(case.X, _c0_params(), seed=seed)
+            assert res.evaluations == int(res.trace[:, 0].sum())
+            top = res.biclusters[0]
+            if np.array_equal(top.cols, t.cols):
+                # rows of the found bicluster: exactly those increasing
+                # along the series (checked here with numpy, not the oracle)
+                np.testing.assert_array_equal(top.rows, np.flatnonzero(follows))
+                assert set(t.rows.tolist()) <= set(top.rows.tolist())
+                ok += 1
+    assert ok >= 14, ok
+
+
+def test_run_deterministic():
+    case = synth.workload_matrix(0)
+    a = oracle.run(case.X, _c0_params(generations=20, n_out=5), seed=77)
+    b = oracle.run(case.X, _c0_params(generations=20, n_out=5), seed=77)
+    assert a.generations == b.generations and a.tabu_hits == b.tabu_hits
+    np.testing.assert_array_equal(a.trace, b.trace)
+    for x, y in zip(a.biclusters, b.biclusters):
+        np.testing.assert_array_equal(x.rows, y.rows)
+        np.testing.assert_array_equal(x.cols, y.cols)
+
+
+def test_run_finds_best_on_tiny_matrix():
+    """8 x 5 matrix: enumerate every series; the loop must reach the best
+    size score within 50 generations (a soft check of the search)."""
+    X = synth.random_matrix(8, 5, seed=21)
+    seqs = [list(s) for s in _all_series(5, 5)]
+    p = _c0_params(k_min=2, k_max=5, population=40, generations=50, min_rows=2, n_out=1)
+    best = oracle.evaluate(X, seqs, params=p).score.max()
+    res = oracle.run(X, p, seed=5)
+    assert res.biclusters[0].score == best
+
+
+def test_run_stops_on_tabu_hits():
+    X = synth.random_matrix(8, 4, seed=2)
+    p = _c0_params(k_min=2, k_max=4, population=10, generations=1000, max_tabu_hits=30)
+    res = oracle.run(X, p, seed=1)
+    assert res.stop_reason in (2, 3)
+    assert res.generations < 1000
+    if res.stop_reason == 2:
+        assert res.tabu_hits == 30
