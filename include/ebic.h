@@ -1,0 +1,175 @@
+/*
+ * ebic.h -- C ABI of the MI355X (gfx950) EBIC evaluation library.
+ *
+ * EBIC (evolutionary biclustering; arXiv 2105.01196, "EBIC.JL - an Efficient
+ * Implementation of Evolutionary Biclustering Algorithm in Julia") searches a
+ * numeric matrix for biclusters: a set of rows together with an ordered series
+ * of columns such that every row follows the series' increasing order
+ * (Sec. 2.3, EBIC paragraph). Each individual of the evolutionary search is
+ * such a column series; scoring an individual means counting the rows that
+ * follow its trend (Sec. 2.4, steps 2-3 and 7), then turning that count into
+ * a fitness with a size score and a penalty for overlapping biclusters
+ * already on the top-rank list. The final step reports the supporting row
+ * indices of the top-rank list (Sec. 2.4, step 9).
+ *
+ * Definitions used throughout (the paper prints no formula; these are the
+ * readings this library implements):
+ *   row order    column a precedes column b in row r when X[r,a] < X[r,b], or
+ *                X[r,a] == X[r,b] and a < b (IEEE compare, so -0 == +0);
+ *   up-steps     u_r = #{ j < k-1 : c_j precedes c_{j+1} in row r };
+ *   tolerance    t(k) = floor((k-1) * (1000 - approx_permille) / 1000);
+ *   support      r fits when (k-1-u_r) <= t(k), or, with negative trends on,
+ *                u_r <= t(k); n = number of fitting rows;
+ *   size score   s = n * 2^k when n >= min_rows and k >= k_score_min, else 0;
+ *   overlap      for archive member j: h_j = rows shared with the member's
+ *                support, g_j = columns shared with its series; the member
+ *                overlaps when 1000*h_j*g_j > overlap_permille*n*k (64-bit);
+ *   fitness      s * 2^-m, m = number of overlapping members (exact FP64).
+ *
+ * Conventions:
+ *   - Every pointer named d_* is device memory owned by the caller; h_* is
+ *     host memory owned by the caller. The library keeps no reference to
+ *     either after a call returns, except where stated.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls marked "asynchronous" only enqueue work on it.
+ *   - Return values are EBIC_OK (0), EBIC_PENDING (1) or a negative EBIC_ERR_*
+ *     code; ebic_last_error() gives a message for the calling thread. No C++
+ *     exception crosses this interface.
+ *   - Rows are padded to a multiple of 64 (rows_pad); a support bitmap holds
+ *     W = rows_pad/64 64-bit words, bit (r % 64) of word (r / 64) for row r.
+ *     Bits of padding rows are always 0.
+ */
+#ifndef EBIC_H
+#define EBIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EBIC_VERSION 100 /* 0.1.0 */
+
+#define EBIC_OK 0
+#define EBIC_PENDING 1
+#define EBIC_ERR_INVALID_ARG (-1)
+#define EBIC_ERR_NONFINITE (-2)
+#define EBIC_ERR_OOM (-3)
+#define EBIC_ERR_DEVICE (-4)
+#define EBIC_ERR_CAPACITY (-5)
+
+#define EBIC_MAX_K 512        /* longest series                          */
+#define EBIC_MAX_ARCHIVE 64   /* largest top-rank list                   */
+#define EBIC_MAX_COLS 16384   /* widest matrix                           */
+#define EBIC_MAX_ROWS (1 << 26)  /* and cols * rows_pad < 2^31 */
+
+/* Method parameters; integers only, so that every result is exact. The
+ * paper names negative trends on/off, the approximate-trend threshold, the
+ * allowed overlap, the number of iterations and the number of biclusters as
+ * its parameters (Sec. 2.4, last paragraph). */
+typedef struct ebic_params {
+    int32_t approx_permille;   /* approximate-trend threshold a, 0..1000 (1000 = exact) */
+    int32_t negative_trends;   /* 0/1: rows following the reversed series also fit    */
+    int32_t overlap_permille;  /* allowed overlap theta, 0..1000                      */
+    int32_t min_rows;          /* fewer fitting rows score 0                           */
+    int32_t k_score_min;       /* fewer columns score 0                                */
+    int32_t k_min, k_max;      /* series lengths the search may create (ebic_run)      */
+    int32_t archive_size;      /* top-rank list capacity K (ebic_run), <= 64           */
+    int32_t n_out;             /* biclusters returned by ebic_run                      */
+    int32_t population;        /* individuals per generation (ebic_run)                */
+    int32_t generations;       /* populations evaluated at most (ebic_run)             */
+    int32_t max_tabu_hits;     /* rejected mutants that end the run (ebic_run)         */
+    int32_t tournament;        /* tournament size (ebic_run)                           */
+    int32_t max_attempts;      /* mutation attempts per population slot (ebic_run)     */
+} ebic_params;
+
+/* A prepared matrix (ebic_matrix_prepare). */
+typedef struct ebic_matrix {
+    const uint16_t *d_ranks;   /* cols x rows_pad, column-major: the position of
+                                  each cell in its row's order (0..cols-1)        */
+    int32_t rows, cols, rows_pad;
+    const uint32_t *d_pairs;   /* optional pair table (ebic_pairs_prepare) or NULL */
+} ebic_matrix;
+
+/* A population in compressed (CSR) form, as the paper sends it to the GPU
+ * (Sec. 2.4, step 2): individual i is d_cols[d_offsets[i] .. d_offsets[i+1]). */
+typedef struct ebic_population {
+    int32_t size;              /* P >= 0 */
+    int32_t length;            /* entries in d_cols; offsets beyond it mark the
+                                  individual invalid */
+    const int32_t *d_offsets;  /* P + 1 */
+    const uint16_t *d_cols;    /* column indices, series order */
+} ebic_population;
+
+/* The top-rank list the overlap penalty is taken against. */
+typedef struct ebic_archive {
+    int32_t size;              /* K, 0..EBIC_MAX_ARCHIVE */
+    int32_t length;            /* entries in d_cols */
+    const uint64_t *d_support; /* K x W support bitmaps */
+    const int32_t *d_offsets;  /* K + 1, CSR of the members' series */
+    const uint16_t *d_cols;
+} ebic_archive;
+
+/* Outputs of an evaluation; all device arrays owned by the caller. */
+typedef struct ebic_eval_out {
+    double *d_fitness;         /* P: s * 2^-m; -1.0 for an invalid individual     */
+    int32_t *d_count;          /* P: n; -1 for an invalid individual              */
+    uint64_t *d_support;       /* P x W support bitmaps, or NULL                   */
+    int32_t *d_overlap;        /* P x K rows shared with each member (h), or NULL */
+} ebic_eval_out;
+
+int ebic_version(void);
+const char *ebic_last_error(void);
+
+/* Bytes of the prepared rank matrix: cols * rows_pad * 2. */
+size_t ebic_matrix_bytes(int32_t rows, int32_t cols);
+
+/* Matrix ingest. Reads a float32 rows x cols row-major matrix d_x and writes
+ * m->d_ranks (ebic_matrix_bytes(rows, cols) bytes, caller-owned): for every
+ * row, the rank of each column in the row order defined above. Comparing two
+ * columns' ranks is then exactly the row order of the paper's trend test,
+ * which the evaluators read in column-major order. The paper keeps the matrix
+ * on the GPU for the whole run and sends only populations per generation
+ * (Sec. 2.4, step 2). Fills *m. Synchronous on `stream` (it waits for the
+ * finiteness check). Errors: EBIC_ERR_INVALID_ARG for null pointers or sizes
+ * outside 1..EBIC_MAX_ROWS x 2..EBIC_MAX_COLS; EBIC_ERR_NONFINITE if any value
+ * is NaN or infinite (m->d_ranks is then unspecified). */
+int ebic_matrix_prepare(const float *d_x, int32_t rows, int32_t cols, uint16_t *d_ranks,
+                        ebic_matrix *m, void *stream);
+
+/* Population upload: validates a host CSR population (every series has
+ * 2..EBIC_MAX_K distinct columns below `cols`) and copies it into the
+ * caller's device arrays d_offsets (P+1 int32) and d_cols (offsets[P]
+ * uint16). Sec. 2.4, step 2 ("compressing the whole population and sending
+ * it on GPU"). Synchronous. EBIC_ERR_INVALID_ARG on an invalid series (nothing
+ * is copied). */
+int ebic_population_upload(const int32_t *h_offsets, const uint16_t *h_cols, int32_t size,
+                           int32_t cols, int32_t *d_offsets, uint16_t *d_cols, void *stream);
+
+/* Plain evaluation, one launch for one population (Sec. 2.4, steps 2-3 and 7:
+ * score every individual, counting its trend-preserving rows). For each
+ * individual: support bitmap, n, h per archive member and fitness, as defined
+ * above. Asynchronous. Host-side errors (EBIC_ERR_INVALID_ARG, nothing
+ * enqueued): null required pointers, archive size outside 0..64, parameters
+ * out of range. An individual whose length is outside 2..EBIC_MAX_K, or
+ * whose columns are out of range or repeated, is marked invalid on the device
+ * (count -1, fitness -1.0, support and overlap 0) and never read out of
+ * bounds. */
+int ebic_evaluate(const ebic_matrix *m, const ebic_population *pop, const ebic_archive *arch,
+                  const ebic_params *p, const ebic_eval_out *out, void *stream);
+
+/* Support compaction (Sec. 2.4, step 9: the trend-preserving rows' indices of
+ * the top-rank list). For each of n_sel selected individuals sel[i] of a
+ * P x W support array, writes its row indices in ascending order to
+ * d_rows[d_row_offsets[i] .. d_row_offsets[i+1]). d_row_offsets (n_sel + 1,
+ * caller-computed from the counts) bounds every write: an individual with more
+ * rows than its slot is cut to the slot. Asynchronous. */
+int ebic_support_rows(const uint64_t *d_support, int32_t size, int32_t words,
+                      const int32_t *d_sel, int32_t n_sel, const int32_t *d_row_offsets,
+                      int32_t *d_rows, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EBIC_H */

@@ -1,0 +1,203 @@
+// C ABI entry points: argument validation, error reporting, launches.
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <vector>
+
+#include "internal.h"
+
+namespace ebic {
+
+namespace {
+thread_local char t_error[512] = "";
+}
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(t_error, sizeof t_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+void clear_error() { t_error[0] = 0; }
+
+int check_hip(hipError_t e, const char *what) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(EBIC_ERR_OOM, "%s: %s", what, hipGetErrorString(e));
+    return fail(EBIC_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_eval_params(const ebic_params *p) {
+    if (!p) return fail(EBIC_ERR_INVALID_ARG, "params is NULL");
+    if (p->approx_permille < 0 || p->approx_permille > 1000)
+        return fail(EBIC_ERR_INVALID_ARG, "approx_permille %d outside 0..1000", p->approx_permille);
+    if (p->overlap_permille < 0 || p->overlap_permille > 1000)
+        return fail(EBIC_ERR_INVALID_ARG, "overlap_permille %d outside 0..1000",
+                    p->overlap_permille);
+    if (p->negative_trends != 0 && p->negative_trends != 1)
+        return fail(EBIC_ERR_INVALID_ARG, "negative_trends must be 0 or 1");
+    if (p->min_rows < 0 || p->k_score_min < 0)
+        return fail(EBIC_ERR_INVALID_ARG, "min_rows and k_score_min must be >= 0");
+    return EBIC_OK;
+}
+
+int device_flag(int **flag) {
+    static std::mutex mu;
+    static std::vector<int *> flags;
+    int dev = 0;
+    EBIC_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    if ((int)flags.size() <= dev) flags.resize(dev + 1, nullptr);
+    if (!flags[dev]) {
+        void *p = nullptr;
+        EBIC_HIP(hipMalloc(&p, 256));
+        flags[dev] = static_cast<int *>(p);
+    }
+    *flag = flags[dev];
+    return EBIC_OK;
+}
+
+static int check_matrix(const ebic_matrix *m) {
+    if (!m || !m->d_ranks) return fail(EBIC_ERR_INVALID_ARG, "matrix or its ranks is NULL");
+    if (m->rows < 1 || m->rows > EBIC_MAX_ROWS || m->cols < 2 || m->cols > EBIC_MAX_COLS ||
+        m->rows_pad != rows_padded(m->rows) || (int64_t)m->cols * m->rows_pad > INT32_MAX)
+        return fail(EBIC_ERR_INVALID_ARG, "matrix shape %d x %d (rows_pad %d) not supported",
+                    m->rows, m->cols, m->rows_pad);
+    return EBIC_OK;
+}
+
+static int check_archive(const ebic_archive *a) {
+    if (!a) return EBIC_OK;
+    if (a->size < 0 || a->size > EBIC_MAX_ARCHIVE)
+        return fail(EBIC_ERR_INVALID_ARG, "archive size %d outside 0..%d", a->size,
+                    EBIC_MAX_ARCHIVE);
+    if (a->size > 0 && (!a->d_support || !a->d_offsets || !a->d_cols || a->length < 0))
+        return fail(EBIC_ERR_INVALID_ARG, "archive arrays are NULL");
+    return EBIC_OK;
+}
+
+}  // namespace ebic
+
+using namespace ebic;
+
+extern "C" {
+
+int ebic_version(void) { return EBIC_VERSION; }
+
+const char *ebic_last_error(void) { return t_error; }
+
+size_t ebic_matrix_bytes(int32_t rows, int32_t cols) {
+    if (rows < 1 || cols < 1) return 0;
+    return (size_t)cols * rows_padded(rows) * sizeof(uint16_t);
+}
+
+int ebic_matrix_prepare(const float *d_x, int32_t rows, int32_t cols, uint16_t *d_ranks,
+                        ebic_matrix *m, void *stream) {
+    clear_error();
+    if (!d_x || !d_ranks || !m) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
+    if (rows < 1 || rows > EBIC_MAX_ROWS || cols < 2 || cols > EBIC_MAX_COLS ||
+        (int64_t)cols * rows_padded(rows) > INT32_MAX)
+        return fail(EBIC_ERR_INVALID_ARG, "matrix shape %d x %d not supported", rows, cols);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int *flag = nullptr;
+    int rc = device_flag(&flag);
+    if (rc) return rc;
+    rc = launch_prepare(d_x, rows, cols, d_ranks, flag, s);
+    if (rc) return rc;
+    int bad = 0;
+    EBIC_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    EBIC_HIP(hipStreamSynchronize(s));
+    if (bad) return fail(EBIC_ERR_NONFINITE, "matrix holds NaN or infinite values");
+    m->d_ranks = d_ranks;
+    m->rows = rows;
+    m->cols = cols;
+    m->rows_pad = rows_padded(rows);
+    m->d_pairs = nullptr;
+    return EBIC_OK;
+}
+
+int ebic_population_upload(const int32_t *h_offsets, const uint16_t *h_cols, int32_t size,
+                           int32_t cols, int32_t *d_offsets, uint16_t *d_cols, void *stream) {
+    clear_error();
+    if (size < 0 || !h_offsets || !d_offsets || (size > 0 && (!h_cols || !d_cols)))
+        return fail(EBIC_ERR_INVALID_ARG, "NULL argument or negative size");
+    if (h_offsets[0] != 0) return fail(EBIC_ERR_INVALID_ARG, "offsets[0] must be 0");
+    std::vector<uint8_t> seen((size_t)cols > 0 ? cols : 1, 0);
+    for (int32_t i = 0; i < size; i++) {
+        const int32_t b = h_offsets[i], e = h_offsets[i + 1], k = e - b;
+        if (k < 2 || k > EBIC_MAX_K)
+            return fail(EBIC_ERR_INVALID_ARG, "individual %d has %d columns", i, k);
+        int bad = 0;
+        for (int32_t q = b; q < e; q++) {
+            const uint16_t c = h_cols[q];
+            if (c >= cols || seen[c]) bad = 1;
+            if (c < cols) seen[c] = 1;
+        }
+        for (int32_t q = b; q < e; q++)
+            if (h_cols[q] < cols) seen[h_cols[q]] = 0;
+        if (bad)
+            return fail(EBIC_ERR_INVALID_ARG, "individual %d repeats a column or exceeds %d", i,
+                        cols);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    EBIC_HIP(hipMemcpyAsync(d_offsets, h_offsets, sizeof(int32_t) * (size + 1),
+                            hipMemcpyHostToDevice, s));
+    if (size > 0 && h_offsets[size] > 0)
+        EBIC_HIP(hipMemcpyAsync(d_cols, h_cols, sizeof(uint16_t) * h_offsets[size],
+                                hipMemcpyHostToDevice, s));
+    EBIC_HIP(hipStreamSynchronize(s));
+    return EBIC_OK;
+}
+
+int ebic_evaluate(const ebic_matrix *m, const ebic_population *pop, const ebic_archive *arch,
+                  const ebic_params *p, const ebic_eval_out *out, void *stream) {
+    clear_error();
+    int rc = check_matrix(m);
+    if (rc) return rc;
+    if ((rc = check_eval_params(p)) || (rc = check_archive(arch))) return rc;
+    if (!pop || pop->size < 0 || (pop->size > 0 && (!pop->d_offsets || !pop->d_cols)))
+        return fail(EBIC_ERR_INVALID_ARG, "population is NULL or malformed");
+    if (!out || (pop->size > 0 && (!out->d_fitness || !out->d_count)))
+        return fail(EBIC_ERR_INVALID_ARG, "fitness and count outputs are required");
+    EvalJob j{};
+    j.ranks = m->d_ranks;
+    j.rows = m->rows;
+    j.cols = m->cols;
+    j.rows_pad = m->rows_pad;
+    j.words = m->rows_pad / 64;
+    j.pairs = m->d_pairs;
+    j.pop_size = pop->size;
+    j.pop_len = pop->length;
+    j.pop_off = pop->d_offsets;
+    j.pop_cols = pop->d_cols;
+    j.arch_size = arch ? arch->size : 0;
+    j.arch_len = arch ? arch->length : 0;
+    j.arch_support = arch ? arch->d_support : nullptr;
+    j.arch_off = arch ? arch->d_offsets : nullptr;
+    j.arch_cols = arch ? arch->d_cols : nullptr;
+    j.approx_permille = p->approx_permille;
+    j.negative_trends = p->negative_trends;
+    j.overlap_permille = p->overlap_permille;
+    j.min_rows = p->min_rows;
+    j.k_score_min = p->k_score_min;
+    j.fitness = out->d_fitness;
+    j.count = out->d_count;
+    j.support = out->d_support;
+    j.overlap = out->d_overlap;
+    return launch_evaluate_plain(j, static_cast<hipStream_t>(stream));
+}
+
+int ebic_support_rows(const uint64_t *d_support, int32_t size, int32_t words,
+                      const int32_t *d_sel, int32_t n_sel, const int32_t *d_row_offsets,
+                      int32_t *d_rows, void *stream) {
+    clear_error();
+    if (size < 0 || words < 1 || n_sel < 0 ||
+        (n_sel > 0 && (!d_support || !d_sel || !d_row_offsets || !d_rows)))
+        return fail(EBIC_ERR_INVALID_ARG, "NULL argument or bad size");
+    return launch_support_rows(d_support, size, words, d_sel, n_sel, d_row_offsets, d_rows,
+                               static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

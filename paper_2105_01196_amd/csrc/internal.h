@@ -1,0 +1,67 @@
+// Internal declarations shared by the library's translation units (not part
+// of the public interface; see include/ebic.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "ebic.h"
+
+namespace ebic {
+
+constexpr int kWave = 64;
+
+// Thread-local error message behind ebic_last_error().
+int fail(int code, const char *fmt, ...);
+void clear_error();
+
+// Maps a HIP error to EBIC_ERR_DEVICE with a message naming the call.
+int check_hip(hipError_t e, const char *what);
+
+#define EBIC_HIP(call)                                            \
+    do {                                                          \
+        hipError_t e_ = (call);                                   \
+        if (e_ != hipSuccess) return ::ebic::check_hip(e_, #call); \
+    } while (0)
+
+inline int32_t rows_padded(int32_t rows) { return (rows + 63) / 64 * 64; }
+
+inline int tolerance(int k, int approx_permille) {
+    return (int)(((int64_t)(k - 1) * (1000 - approx_permille)) / 1000);
+}
+
+// Host-side validation of the evaluation parameters.
+int check_eval_params(const ebic_params *p);
+
+// Per-device 4-byte status word in device memory (allocated once per device
+// on first use, kept until the process ends).
+int device_flag(int **flag);
+
+// Arguments of one evaluation, as the kernels see them.
+struct EvalJob {
+    const uint16_t *ranks;
+    int32_t rows, cols, rows_pad, words;
+    const uint32_t *pairs;
+    int32_t pop_size, pop_len;
+    const int32_t *pop_off;
+    const uint16_t *pop_cols;
+    int32_t arch_size, arch_len;
+    const uint64_t *arch_support;
+    const int32_t *arch_off;
+    const uint16_t *arch_cols;
+    int32_t approx_permille, negative_trends, overlap_permille, min_rows, k_score_min;
+    double *fitness;
+    int32_t *count;
+    uint64_t *support;
+    int32_t *overlap;
+};
+
+int launch_evaluate_plain(const EvalJob &job, hipStream_t stream);
+int launch_support_rows(const uint64_t *support, int32_t size, int32_t words, const int32_t *sel,
+                        int32_t n_sel, const int32_t *row_off, int32_t *rows, hipStream_t stream);
+int launch_prepare(const float *x, int32_t rows, int32_t cols, uint16_t *ranks, int *flag,
+                   hipStream_t stream);
+
+}  // namespace ebic

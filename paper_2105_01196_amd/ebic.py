@@ -1,0 +1,333 @@
+"""Python binding of the EBIC HIP library (``libebic.so``, C ABI in
+include/ebic.h). Argument marshalling only: every step of the evaluation runs
+in the library's kernels. PyTorch supplies device memory and streams.
+
+The library must be built (``python -m paper_2105_01196_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libebic.so")
+
+EBIC_OK = 0
+EBIC_PENDING = 1
+EBIC_ERR_INVALID_ARG = -1
+EBIC_ERR_NONFINITE = -2
+EBIC_ERR_OOM = -3
+EBIC_ERR_DEVICE = -4
+EBIC_ERR_CAPACITY = -5
+EBIC_MAX_K = 512
+EBIC_MAX_ARCHIVE = 64
+EBIC_MAX_COLS = 16384
+
+
+class EbicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"ebic error {code}: {msg}")
+        self.code = code
+
+
+_i32, _vp = ctypes.c_int32, ctypes.c_void_p
+
+
+class ebic_params(ctypes.Structure):
+    _fields_ = [(n, _i32) for n in (
+        "approx_permille", "negative_trends", "overlap_permille", "min_rows", "k_score_min",
+        "k_min", "k_max", "archive_size", "n_out", "population", "generations",
+        "max_tabu_hits", "tournament", "max_attempts")]
+
+
+class ebic_matrix(ctypes.Structure):
+    _fields_ = [("d_ranks", _vp), ("rows", _i32), ("cols", _i32), ("rows_pad", _i32),
+                ("d_pairs", _vp)]
+
+
+class ebic_population(ctypes.Structure):
+    _fields_ = [("size", _i32), ("length", _i32), ("d_offsets", _vp), ("d_cols", _vp)]
+
+
+class ebic_archive(ctypes.Structure):
+    _fields_ = [("size", _i32), ("length", _i32), ("d_support", _vp), ("d_offsets", _vp),
+                ("d_cols", _vp)]
+
+
+class ebic_eval_out(ctypes.Structure):
+    _fields_ = [("d_fitness", _vp), ("d_count", _vp), ("d_support", _vp), ("d_overlap", _vp)]
+
+
+# Every symbol include/ebic.h declares, with its ctypes signature.
+_SIGNATURES = {
+    "ebic_version": (ctypes.c_int, []),
+    "ebic_last_error": (ctypes.c_char_p, []),
+    "ebic_matrix_bytes": (ctypes.c_size_t, [_i32, _i32]),
+    "ebic_matrix_prepare": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(ebic_matrix),
+                                           _vp]),
+    "ebic_population_upload": (ctypes.c_int, [_vp, _vp, _i32, _i32, _vp, _vp, _vp]),
+    "ebic_evaluate": (ctypes.c_int, [ctypes.POINTER(ebic_matrix),
+                                     ctypes.POINTER(ebic_population),
+                                     ctypes.POINTER(ebic_archive), ctypes.POINTER(ebic_params),
+                                     ctypes.POINTER(ebic_eval_out), _vp]),
+    "ebic_support_rows": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -m paper_2105_01196_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise EbicError(rc, lib().ebic_last_error().decode())
+    return rc
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _dev(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _to_device_bytes(a: np.ndarray, device) -> torch.Tensor:
+    a = np.ascontiguousarray(a)
+    if a.nbytes == 0:
+        return torch.empty(8, dtype=torch.uint8, device=device)
+    return torch.from_numpy(a.view(np.uint8).reshape(-1)).to(device)
+
+
+DEFAULT_PARAMS = dict(approx_permille=850, negative_trends=0, overlap_permille=750,
+                      min_rows=5, k_score_min=2, k_min=2, k_max=8, archive_size=20, n_out=1,
+                      population=200, generations=50, max_tabu_hits=100000, tournament=4,
+                      max_attempts=1000)
+
+
+def make_params(**kw) -> ebic_params:
+    d = dict(DEFAULT_PARAMS)
+    if "negative_trends" in kw and "k_score_min" not in kw:
+        d["k_score_min"] = 3 if kw["negative_trends"] else 2
+    d.update(kw)
+    return ebic_params(**d)
+
+
+def ebic_version() -> int:
+    return lib().ebic_version()
+
+
+def ebic_matrix_bytes(rows: int, cols: int) -> int:
+    return int(lib().ebic_matrix_bytes(rows, cols))
+
+
+@dataclasses.dataclass
+class Matrix:
+    """A prepared matrix: the rank array in device memory and its view."""
+    ranks: torch.Tensor
+    view: ebic_matrix
+    pairs: Optional[torch.Tensor] = None
+
+    @property
+    def rows(self) -> int:
+        return self.view.rows
+
+    @property
+    def cols(self) -> int:
+        return self.view.cols
+
+    @property
+    def words(self) -> int:
+        return self.view.rows_pad // 64
+
+
+def ebic_matrix_prepare(x: torch.Tensor, stream=None) -> Matrix:
+    """Ingest a float32 rows x cols matrix already on the GPU."""
+    assert x.is_cuda and x.dtype == torch.float32 and x.dim() == 2
+    x = x.contiguous()
+    R, C = x.shape
+    nbytes = ebic_matrix_bytes(R, C)
+    ranks = torch.empty(max(nbytes, 2), dtype=torch.uint8, device=x.device)
+    view = ebic_matrix()
+    _check(lib().ebic_matrix_prepare(x.data_ptr(), R, C, ranks.data_ptr(), ctypes.byref(view),
+                                      _stream(stream)))
+    return Matrix(ranks, view)
+
+
+@dataclasses.dataclass
+class Population:
+    offsets: torch.Tensor
+    cols: torch.Tensor
+    view: ebic_population
+
+    @property
+    def size(self) -> int:
+        return self.view.size
+
+
+def csr(seqs: Sequence[Sequence[int]]):
+    lens = np.array([len(s) for s in seqs], dtype=np.int64)
+    off = np.zeros(len(seqs) + 1, dtype=np.int32)
+    off[1:] = np.cumsum(lens)
+    cols = (np.concatenate([np.asarray(s, dtype=np.uint16) for s in seqs])
+            if len(seqs) else np.zeros(0, np.uint16)).astype(np.uint16)
+    return off, cols
+
+
+def ebic_population_upload(seqs_or_csr, cols: int, device="cuda", stream=None) -> Population:
+    """Validate a population (list of series, or (offsets, cols) CSR arrays)
+    and copy it to the GPU."""
+    if isinstance(seqs_or_csr, tuple):
+        off, cc = seqs_or_csr
+    else:
+        off, cc = csr(seqs_or_csr)
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    cc = np.ascontiguousarray(cc, dtype=np.uint16)
+    P = off.size - 1
+    d_off = torch.empty(max(off.nbytes, 8), dtype=torch.uint8, device=device)
+    d_cols = torch.empty(max(cc.nbytes, 8), dtype=torch.uint8, device=device)
+    _check(lib().ebic_population_upload(off.ctypes.data, cc.ctypes.data if cc.size else None, P,
+                                        cols, d_off.data_ptr(), d_cols.data_ptr(),
+                                        _stream(stream)))
+    view = ebic_population(P, int(cc.size), d_off.data_ptr(), d_cols.data_ptr())
+    return Population(d_off, d_cols, view)
+
+
+def population_raw(off: np.ndarray, cc: np.ndarray, device="cuda") -> Population:
+    """Copy a CSR population to the GPU without host validation (the device
+    kernels guard every access and mark malformed individuals invalid)."""
+    d_off = _to_device_bytes(np.asarray(off, np.int32), device)
+    d_cols = _to_device_bytes(np.asarray(cc, np.uint16), device)
+    view = ebic_population(int(np.asarray(off).size - 1), int(np.asarray(cc).size),
+                           d_off.data_ptr(), d_cols.data_ptr())
+    return Population(d_off, d_cols, view)
+
+
+@dataclasses.dataclass
+class Archive:
+    support: torch.Tensor     # int64 K x W (bit pattern of uint64 words)
+    offsets: torch.Tensor
+    cols: torch.Tensor
+    view: ebic_archive
+
+    @property
+    def size(self) -> int:
+        return self.view.size
+
+
+def make_archive(support_words: np.ndarray, series: Sequence[Sequence[int]],
+                 device="cuda") -> Archive:
+    """Archive from host support bitmaps (K x W uint64) and member series."""
+    K = len(series)
+    sw = np.ascontiguousarray(support_words, dtype=np.uint64).reshape(K, -1)
+    d_sup = torch.from_numpy(sw.view(np.int64).copy()).to(device) if K else \
+        torch.zeros(1, dtype=torch.int64, device=device)
+    off, cc = csr(series)
+    d_off = _to_device_bytes(off, device)
+    d_cols = _to_device_bytes(cc, device)
+    view = ebic_archive(K, int(cc.size), d_sup.data_ptr(), d_off.data_ptr(), d_cols.data_ptr())
+    return Archive(d_sup, d_off, d_cols, view)
+
+
+def archive_from_device(support: torch.Tensor, sel: Sequence[int], pop_series,
+                        device="cuda") -> Archive:
+    sw = support[list(sel)].contiguous() if len(sel) else torch.zeros(1, dtype=torch.int64,
+                                                                       device=device)
+    series = [pop_series[i] for i in sel]
+    off, cc = csr(series)
+    d_off = _to_device_bytes(off, device)
+    d_cols = _to_device_bytes(cc, device)
+    view = ebic_archive(len(sel), int(cc.size), sw.data_ptr(), d_off.data_ptr(), d_cols.data_ptr())
+    return Archive(sw, d_off, d_cols, view)
+
+
+@dataclasses.dataclass
+class EvalOut:
+    fitness: torch.Tensor             # float64 P
+    count: torch.Tensor               # int32 P
+    support: Optional[torch.Tensor]   # int64 P x W (uint64 bit patterns)
+    overlap: Optional[torch.Tensor]   # int32 P x K
+    view: ebic_eval_out
+
+
+def alloc_eval_out(P: int, words: int, K: int, support=True, overlap=True,
+                   device="cuda") -> EvalOut:
+    fit = torch.empty(max(P, 1), dtype=torch.float64, device=device)
+    cnt = torch.empty(max(P, 1), dtype=torch.int32, device=device)
+    sup = torch.empty((max(P, 1), words), dtype=torch.int64, device=device) if support else None
+    ov = torch.empty((max(P, 1), max(K, 1)), dtype=torch.int32, device=device) \
+        if overlap and K > 0 else None
+    view = ebic_eval_out(fit.data_ptr(), cnt.data_ptr(), _dev(sup), _dev(ov))
+    return EvalOut(fit, cnt, sup, ov, view)
+
+
+def ebic_evaluate(m: Matrix, pop: Population, archive: Optional[Archive] = None,
+                  params: Optional[ebic_params] = None, out: Optional[EvalOut] = None,
+                  support=True, overlap=True, stream=None) -> EvalOut:
+    """Plain evaluation of one population (one launch). Asynchronous on the
+    stream; results are ready after a synchronize."""
+    params = params or make_params()
+    K = archive.size if archive is not None else 0
+    if out is None:
+        out = alloc_eval_out(pop.size, m.words, K, support, overlap, device=m.ranks.device)
+    arch_view = archive.view if archive is not None else ebic_archive(0, 0, None, None, None)
+    _check(lib().ebic_evaluate(ctypes.byref(m.view), ctypes.byref(pop.view),
+                               ctypes.byref(arch_view), ctypes.byref(params),
+                               ctypes.byref(out.view), _stream(stream)))
+    return out
+
+
+def ebic_support_rows(support: torch.Tensor, sel: Sequence[int], counts: Sequence[int],
+                      stream=None) -> List[np.ndarray]:
+    """Row indices (ascending) of the selected individuals' supports."""
+    P, W = support.shape
+    dev = support.device
+    sel_a = np.asarray(sel, dtype=np.int32)
+    off = np.zeros(sel_a.size + 1, dtype=np.int32)
+    off[1:] = np.cumsum(np.asarray(counts, dtype=np.int64))
+    d_sel = torch.from_numpy(sel_a).to(dev) if sel_a.size else torch.zeros(1, dtype=torch.int32,
+                                                                           device=dev)
+    d_off = torch.from_numpy(off).to(dev)
+    rows = torch.empty(max(int(off[-1]), 1), dtype=torch.int32, device=dev)
+    _check(lib().ebic_support_rows(support.data_ptr(), P, W, d_sel.data_ptr(), int(sel_a.size),
+                                   d_off.data_ptr(), rows.data_ptr(), _stream(stream)))
+    torch.cuda.synchronize(dev)
+    h = rows.cpu().numpy()
+    return [h[off[i]:off[i + 1]].copy() for i in range(sel_a.size)]
+
+
+def support_to_flags(words: torch.Tensor, rows: int) -> np.ndarray:
+    """P x W support words (device or host) -> P x rows 0/1 flags on the host."""
+    w = words.cpu().numpy().view(np.uint64) if isinstance(words, torch.Tensor) else words
+    bits = np.unpackbits(w.view(np.uint8).reshape(w.shape[0], -1), axis=1, bitorder="little")
+    return bits[:, :rows]
+
+
+def flags_to_support(flags: np.ndarray, words: int) -> np.ndarray:
+    """K x R 0/1 flags -> K x W uint64 words (bit r%64 of word r//64)."""
+    K, R = flags.shape
+    padded = np.zeros((K, words * 64), dtype=np.uint8)
+    padded[:, :R] = flags
+    return np.packbits(padded, axis=1, bitorder="little").view(np.uint64).reshape(K, words)

@@ -1,0 +1,78 @@
+"""CPU checks of the C ABI: the library loads and exports every function
+include/ebic.h declares (no compute call; no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(ebic_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for n in ("ebic_matrix_prepare", "ebic_evaluate", "ebic_support_rows", "ebic_version",
+              "ebic_last_error", "ebic_population_upload", "ebic_matrix_bytes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2105_01196_amd import ebic
+    L = ebic.lib()
+    missing = [n for n in sorted(_declared()) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_2105_01196_amd import ebic
+    assert _declared() <= set(ebic._SIGNATURES), _declared() - set(ebic._SIGNATURES)
+
+
+def test_host_only_calls():
+    from paper_2105_01196_amd import ebic
+    assert ebic.ebic_version() == 100
+    assert ebic.ebic_matrix_bytes(100, 20) == 20 * 128 * 2
+    assert ebic.ebic_matrix_bytes(0, 20) == 0
+
+
+def test_population_validation_rejects_on_host():
+    """Host-side validation runs before any device call."""
+    import numpy as np
+    from paper_2105_01196_amd import ebic
+    L = ebic.lib()
+    for off, cols in (([0, 1], [3]), ([0, 2], [3, 3]), ([0, 2], [3, 20]), ([1, 3], [0, 1])):
+        o = np.array(off, np.int32)
+        c = np.array(cols, np.uint16)
+        rc = L.ebic_population_upload(o.ctypes.data, c.ctypes.data, 1, 10, 0x1000, 0x1000, None)
+        assert rc == ebic.EBIC_ERR_INVALID_ARG
+        assert L.ebic_last_error()
+
+
+def test_evaluate_rejects_bad_arguments_on_host():
+    from paper_2105_01196_amd import ebic
+    L = ebic.lib()
+    m = ebic.ebic_matrix(0x1000, 100, 20, 128, None)
+    pop = ebic.ebic_population(0, 0, None, None)
+    out = ebic.ebic_eval_out(None, None, None, None)
+    arch = ebic.ebic_archive(65, 0, 0x1000, 0x1000, 0x1000)
+    p = ebic.make_params()
+    assert L.ebic_evaluate(ctypes.byref(m), ctypes.byref(pop), ctypes.byref(arch),
+                           ctypes.byref(p), ctypes.byref(out), None) == ebic.EBIC_ERR_INVALID_ARG
+    bad_m = ebic.ebic_matrix(0x1000, 100, 20, 100, None)  # rows_pad not a multiple of 64
+    arch0 = ebic.ebic_archive(0, 0, None, None, None)
+    assert L.ebic_evaluate(ctypes.byref(bad_m), ctypes.byref(pop), ctypes.byref(arch0),
+                           ctypes.byref(p), ctypes.byref(out), None) == ebic.EBIC_ERR_INVALID_ARG
+    bad_p = ebic.make_params(approx_permille=1001)
+    assert L.ebic_evaluate(ctypes.byref(m), ctypes.byref(pop), ctypes.byref(arch0),
+                           ctypes.byref(bad_p), ctypes.byref(out), None) == ebic.EBIC_ERR_INVALID_ARG
