@@ -89,7 +89,7 @@ typedef struct ebic_matrix {
     const uint16_t *d_ranks;   /* cols x rows_pad, column-major: the position of
                                   each cell in its row's order (0..cols-1)        */
     int32_t rows, cols, rows_pad;
-    const uint32_t *d_pairs;   /* optional pair table (ebic_pairs_prepare) or NULL */
+    const uint64_t *d_pairs;   /* optional pair table (ebic_pairs_prepare) or NULL */
 } ebic_matrix;
 
 /* A population in compressed (CSR) form, as the paper sends it to the GPU
@@ -100,6 +100,10 @@ typedef struct ebic_population {
                                   individual invalid */
     const int32_t *d_offsets;  /* P + 1 */
     const uint16_t *d_cols;    /* column indices, series order */
+    const int32_t *d_order;    /* optional processing order for the batched
+                                  evaluator: a permutation of 0..P-1, longest
+                                  series first balances the load; NULL = 0..P-1.
+                                  Results never depend on it. */
 } ebic_population;
 
 /* The top-rank list the overlap penalty is taken against. */
@@ -158,6 +162,53 @@ int ebic_population_upload(const int32_t *h_offsets, const uint16_t *h_cols, int
  * bounds. */
 int ebic_evaluate(const ebic_matrix *m, const ebic_population *pop, const ebic_archive *arch,
                   const ebic_params *p, const ebic_eval_out *out, void *stream);
+
+/* Bytes of the pair-comparison table: C(C-1)/2 pairs x rows_pad/8. */
+size_t ebic_pairs_bytes(int32_t rows, int32_t cols);
+
+/* Pair-comparison table (used by the batched evaluator). For every
+ * unordered column pair lo < hi, the support-style bitmap (W words) of the
+ * rows in which lo precedes hi, at d_pairs[pair * W + word] with
+ * pair = lo*C - lo*(lo+1)/2 + (hi-lo-1). A series step c_j -> c_{j+1} keeps
+ * the increasing trend (Sec. 2.3) exactly in the rows of its pair's bitmap,
+ * inverted when c_j > c_{j+1}, so the trend test reduces to bitwise work.
+ * d_pairs (ebic_pairs_bytes bytes) is caller-owned; sets m->d_pairs.
+ * Asynchronous. EBIC_ERR_INVALID_ARG for a NULL or unprepared matrix. */
+int ebic_pairs_prepare(ebic_matrix *m, uint64_t *d_pairs, void *stream);
+
+/* One evaluation job of a batch: a matrix, a population, the archive it is
+ * penalised against, the parameters and the outputs (as for ebic_evaluate;
+ * out.d_support may be NULL, the batch then keeps its own scratch). */
+typedef struct ebic_job {
+    ebic_matrix matrix;
+    ebic_population population;
+    ebic_archive archive;
+    ebic_params params;
+    ebic_eval_out out;
+} ebic_job;
+
+#define EBIC_BATCH_GRAPH 1   /* replay the launch as a prebuilt HIP graph */
+#define EBIC_BATCH_GATHER 2  /* ignore pair tables, use the gather form    */
+
+typedef struct ebic_batch ebic_batch;
+
+/* Batched evaluation (Sec. 2.4, steps 2-3 and 7, for several populations
+ * at once): every individual of every job in one launch of the evaluation
+ * kernel plus one launch of the reduction kernel, each job with its own
+ * matrix (pair-table form when the matrix has a table, else the gather
+ * form), archive and parameters. Results are identical, bit for bit, to
+ * ebic_evaluate on each job alone. create copies the job table to the
+ * device (the caller's buffers are referenced, not copied: they must stay
+ * valid until destroy; their contents may change between runs); run enqueues
+ * one evaluation of all jobs on `stream` (asynchronous); destroy frees the
+ * batch. Errors: EBIC_ERR_INVALID_ARG (as ebic_evaluate, per job),
+ * EBIC_ERR_OOM, EBIC_ERR_DEVICE. Runs of one batch must not overlap. */
+int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_batch **out);
+int ebic_batch_run(ebic_batch *b, void *stream);
+int ebic_batch_destroy(ebic_batch *b);
+
+/* One-shot batched evaluation: create, run, wait, destroy. Synchronous. */
+int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream);
 
 /* Support compaction (Sec. 2.4, step 9: the trend-preserving rows' indices of
  * the top-rank list). For each of n_sel selected individuals sel[i] of a

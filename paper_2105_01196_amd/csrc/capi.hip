@@ -189,6 +189,58 @@ int ebic_evaluate(const ebic_matrix *m, const ebic_population *pop, const ebic_a
     return launch_evaluate_plain(j, static_cast<hipStream_t>(stream));
 }
 
+size_t ebic_pairs_bytes(int32_t rows, int32_t cols) {
+    if (rows < 1 || cols < 2) return 0;
+    return (size_t)cols * (cols - 1) / 2 * (rows_padded(rows) / 8);
+}
+
+int ebic_pairs_prepare(ebic_matrix *m, uint64_t *d_pairs, void *stream) {
+    clear_error();
+    int rc = check_matrix(m);
+    if (rc) return rc;
+    if (!d_pairs) return fail(EBIC_ERR_INVALID_ARG, "pair table is NULL");
+    rc = launch_build_pairs(m->d_ranks, m->cols, m->rows_pad, d_pairs,
+                            static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    m->d_pairs = d_pairs;
+    return EBIC_OK;
+}
+
+int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_batch **out) {
+    clear_error();
+    if (!out) return fail(EBIC_ERR_INVALID_ARG, "out is NULL");
+    Batch *b = nullptr;
+    int rc = batch_create(jobs, njobs, flags, &b);
+    if (rc) return rc;
+    *out = reinterpret_cast<ebic_batch *>(b);
+    return EBIC_OK;
+}
+
+int ebic_batch_run(ebic_batch *b, void *stream) {
+    clear_error();
+    return batch_run(reinterpret_cast<Batch *>(b), static_cast<hipStream_t>(stream));
+}
+
+int ebic_batch_destroy(ebic_batch *b) {
+    clear_error();
+    return batch_destroy(reinterpret_cast<Batch *>(b));
+}
+
+int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream) {
+    clear_error();
+    Batch *b = nullptr;
+    int rc = batch_create(jobs, njobs, 0, &b);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = batch_run(b, s);
+    if (rc == EBIC_OK) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
+    }
+    batch_destroy(b);
+    return rc;
+}
+
 int ebic_support_rows(const uint64_t *d_support, int32_t size, int32_t words,
                       const int32_t *d_sel, int32_t n_sel, const int32_t *d_row_offsets,
                       int32_t *d_rows, void *stream) {

@@ -10,6 +10,7 @@
 // archive words gives the rows shared with each archived bicluster. The
 // workgroup then reduces these and computes the fitness itself, so the
 // launch needs no atomics and no zeroed outputs.
+#include "device.h"
 #include "internal.h"
 
 namespace ebic {
@@ -17,51 +18,6 @@ namespace {
 
 constexpr int kEvalWaves = 4;
 constexpr int kEvalThreads = kEvalWaves * kWave;
-
-__device__ inline int tol(int k, int approx) {
-    return (int)(((long long)(k - 1) * (1000 - approx)) / 1000);
-}
-
-// Buffer resource over `bytes` bytes at `p`: loads through it take the
-// per-lane offset in a VGPR and a wave-uniform offset in an SGPR, and the
-// hardware returns 0 for any offset past the end.
-__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
-                                             0x00020000);
-}
-
-__device__ inline int load_rank(__amdgpu_buffer_rsrc_t rs, int lane_off, int col_off) {
-    return __builtin_amdgcn_raw_buffer_load_b16(rs, lane_off, col_off, 0);
-}
-
-// Rows of one 64-row block that follow the series. s_off holds each
-// column's byte offset in the rank matrix; lane_off is this lane's row
-// offset. Early exit once every row of the block has broken both trends
-// beyond the tolerance.
-__device__ inline uint64_t block_support(__amdgpu_buffer_rsrc_t rs, const int32_t *s_off, int k,
-                                         int t, int neg, int lane_off, bool valid_row) {
-    int prev = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[0]));
-    int up = 0;
-    int j = 1;
-    for (; j + 3 < k; j += 4) {
-        const int a = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j]));
-        const int b = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j + 1]));
-        const int c = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j + 2]));
-        const int d = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j + 3]));
-        up += (prev < a) + (a < b) + (b < c) + (c < d);
-        prev = d;
-        const int done = j + 3;  // steps examined so far
-        const bool dead = !valid_row || ((done - up > t) && (!neg || up > t));
-        if (__ballot(!dead) == 0) return 0;
-    }
-    for (; j < k; j++) {
-        const int cur = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j]));
-        up += prev < cur;
-        prev = cur;
-    }
-    const bool fit = valid_row && (((k - 1 - up) <= t) || (neg && up <= t));
-    return __ballot(fit);
-}
 
 __global__ void __launch_bounds__(kEvalThreads) evaluate_plain_kernel(EvalJob a) {
     __shared__ int32_t s_off[EBIC_MAX_K];

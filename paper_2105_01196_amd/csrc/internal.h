@@ -43,7 +43,7 @@ int device_flag(int **flag);
 struct EvalJob {
     const uint16_t *ranks;
     int32_t rows, cols, rows_pad, words;
-    const uint32_t *pairs;
+    const uint64_t *pairs;
     int32_t pop_size, pop_len;
     const int32_t *pop_off;
     const uint16_t *pop_cols;
@@ -63,5 +63,12 @@ int launch_support_rows(const uint64_t *support, int32_t size, int32_t words, co
                         int32_t n_sel, const int32_t *row_off, int32_t *rows, hipStream_t stream);
 int launch_prepare(const float *x, int32_t rows, int32_t cols, uint16_t *ranks, int *flag,
                    hipStream_t stream);
+int launch_build_pairs(const uint16_t *ranks, int32_t cols, int32_t rows_pad, uint64_t *table,
+                       hipStream_t stream);
+
+struct Batch;
+int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out);
+int batch_run(Batch *b, hipStream_t stream);
+int batch_destroy(Batch *b);
 
 }  // namespace ebic

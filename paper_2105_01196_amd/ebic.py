@@ -52,7 +52,8 @@ class ebic_matrix(ctypes.Structure):
 
 
 class ebic_population(ctypes.Structure):
-    _fields_ = [("size", _i32), ("length", _i32), ("d_offsets", _vp), ("d_cols", _vp)]
+    _fields_ = [("size", _i32), ("length", _i32), ("d_offsets", _vp), ("d_cols", _vp),
+                ("d_order", _vp)]
 
 
 class ebic_archive(ctypes.Structure):
@@ -63,6 +64,14 @@ class ebic_archive(ctypes.Structure):
 class ebic_eval_out(ctypes.Structure):
     _fields_ = [("d_fitness", _vp), ("d_count", _vp), ("d_support", _vp), ("d_overlap", _vp)]
 
+
+class ebic_job(ctypes.Structure):
+    _fields_ = [("matrix", ebic_matrix), ("population", ebic_population),
+                ("archive", ebic_archive), ("params", ebic_params), ("out", ebic_eval_out)]
+
+
+EBIC_BATCH_GRAPH = 1
+EBIC_BATCH_GATHER = 2
 
 # Every symbol include/ebic.h declares, with its ctypes signature.
 _SIGNATURES = {
@@ -77,6 +86,13 @@ _SIGNATURES = {
                                      ctypes.POINTER(ebic_archive), ctypes.POINTER(ebic_params),
                                      ctypes.POINTER(ebic_eval_out), _vp]),
     "ebic_support_rows": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
+    "ebic_pairs_bytes": (ctypes.c_size_t, [_i32, _i32]),
+    "ebic_pairs_prepare": (ctypes.c_int, [ctypes.POINTER(ebic_matrix), _vp, _vp]),
+    "ebic_batch_create": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _i32,
+                                         ctypes.POINTER(_vp)]),
+    "ebic_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "ebic_batch_destroy": (ctypes.c_int, [_vp]),
+    "ebic_evaluate_batched": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _vp]),
 }
 
 _lib = None
@@ -181,6 +197,7 @@ class Population:
     offsets: torch.Tensor
     cols: torch.Tensor
     view: ebic_population
+    order: Optional[torch.Tensor] = None
 
     @property
     def size(self) -> int:
@@ -211,7 +228,7 @@ def ebic_population_upload(seqs_or_csr, cols: int, device="cuda", stream=None) -
     _check(lib().ebic_population_upload(off.ctypes.data, cc.ctypes.data if cc.size else None, P,
                                         cols, d_off.data_ptr(), d_cols.data_ptr(),
                                         _stream(stream)))
-    view = ebic_population(P, int(cc.size), d_off.data_ptr(), d_cols.data_ptr())
+    view = ebic_population(P, int(cc.size), d_off.data_ptr(), d_cols.data_ptr(), None)
     return Population(d_off, d_cols, view)
 
 
@@ -221,8 +238,26 @@ def population_raw(off: np.ndarray, cc: np.ndarray, device="cuda") -> Population
     d_off = _to_device_bytes(np.asarray(off, np.int32), device)
     d_cols = _to_device_bytes(np.asarray(cc, np.uint16), device)
     view = ebic_population(int(np.asarray(off).size - 1), int(np.asarray(cc).size),
-                           d_off.data_ptr(), d_cols.data_ptr())
+                           d_off.data_ptr(), d_cols.data_ptr(), None)
     return Population(d_off, d_cols, view)
+
+
+def set_order(pop: Population, order: Optional[np.ndarray], device="cuda") -> None:
+    """Attach a processing order (a permutation of 0..P-1) for the batched
+    evaluator, or clear it with None."""
+    if order is None:
+        pop.view.d_order = None
+        pop.order = None
+        return
+    d = torch.from_numpy(np.ascontiguousarray(order, dtype=np.int32)).to(device)
+    pop.order = d
+    pop.view.d_order = d.data_ptr()
+
+
+def longest_first(seqs) -> np.ndarray:
+    """Order that puts the longest series first (stable)."""
+    lens = np.array([len(s) for s in seqs])
+    return np.argsort(-lens, kind="stable").astype(np.int32)
 
 
 @dataclasses.dataclass
@@ -297,6 +332,74 @@ def ebic_evaluate(m: Matrix, pop: Population, archive: Optional[Archive] = None,
                                ctypes.byref(arch_view), ctypes.byref(params),
                                ctypes.byref(out.view), _stream(stream)))
     return out
+
+
+def ebic_pairs_bytes(rows: int, cols: int) -> int:
+    return int(lib().ebic_pairs_bytes(rows, cols))
+
+
+def ebic_pairs_prepare(m: Matrix, stream=None) -> Matrix:
+    """Build the pair-comparison table of a prepared matrix (device memory
+    from torch) and attach it to the matrix view."""
+    nbytes = ebic_pairs_bytes(m.rows, m.cols)
+    table = torch.empty(max(nbytes // 8, 1), dtype=torch.int64, device=m.ranks.device)
+    _check(lib().ebic_pairs_prepare(ctypes.byref(m.view), table.data_ptr(), _stream(stream)))
+    m.pairs = table
+    return m
+
+
+@dataclasses.dataclass
+class Job:
+    """One job of a batch; keeps the tensors its view points at alive."""
+    matrix: Matrix
+    pop: Population
+    archive: Optional[Archive]
+    params: ebic_params
+    out: EvalOut
+
+    def view(self) -> ebic_job:
+        arch = self.archive.view if self.archive is not None else \
+            ebic_archive(0, 0, None, None, None)
+        return ebic_job(self.matrix.view, self.pop.view, arch, self.params, self.out.view)
+
+
+def make_job(m: Matrix, pop: Population, archive: Optional[Archive] = None,
+             params: Optional[ebic_params] = None, support=True, overlap=True) -> Job:
+    params = params or make_params()
+    K = archive.size if archive is not None else 0
+    out = alloc_eval_out(pop.size, m.words, K, support, overlap, device=m.ranks.device)
+    return Job(m, pop, archive, params, out)
+
+
+class Batch:
+    """A batch of jobs evaluated by one launch (ebic_batch_*)."""
+
+    def __init__(self, jobs: Sequence[Job], graph: bool = False, gather: bool = False):
+        self.jobs = list(jobs)
+        self._views = (ebic_job * len(self.jobs))(*[j.view() for j in self.jobs])
+        flags = (EBIC_BATCH_GRAPH if graph else 0) | (EBIC_BATCH_GATHER if gather else 0)
+        h = _vp()
+        _check(lib().ebic_batch_create(self._views, len(self.jobs), flags, ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None) -> None:
+        _check(lib().ebic_batch_run(self.handle, _stream(stream)))
+
+    def close(self) -> None:
+        if self.handle:
+            lib().ebic_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def ebic_evaluate_batched(jobs: Sequence[Job], stream=None) -> None:
+    views = (ebic_job * len(jobs))(*[j.view() for j in jobs])
+    _check(lib().ebic_evaluate_batched(views, len(jobs), _stream(stream)))
 
 
 def ebic_support_rows(support: torch.Tensor, sel: Sequence[int], counts: Sequence[int],
