@@ -1,18 +1,23 @@
 """Benchmark of the EBIC evaluation hot path on one MI355X.
 
-One step = one generation's evaluation of the whole population: for every
-individual, the trend check over all rows, the row reduction into support
-bitmaps and counts, the overlap with a 20-member archive and the FP64
-fitness. Inputs (prepared matrix, population, archive) are resident in HBM
-before the timed region. Prints one JSON line.
+One step = one generation's evaluation of every individual of the batch:
+the trend check over all rows, the row reduction into support bitmaps and
+counts, the overlap with each population's 20-member archive and the FP64
+fitness. Inputs (prepared matrix and its pair table, populations, archives)
+are resident in HBM before the timed region. Prints one JSON line.
 
-Workload (default): 10,000 x 500 float32 log-normal matrix with 10 planted
-trend biclusters, 4,096 individuals of 3-64 columns (10% planted series),
-negative trends on, approximate-trend threshold 850 per mille, archive of 20.
+Workload (default, "batched-10000x500"): 10,000 x 500 float32 log-normal
+matrix with 10 planted trend biclusters; 4 independent populations of 1,024
+individuals of 3-64 columns (10% planted series) = 4,096 evaluations per
+step, all in one launch of the batched evaluator; negative trends on,
+approximate-trend threshold 850 per mille. The plain path (one launch per
+population) is timed on the same inputs for the batched-vs-plain ratio, and
+both outputs are compared bit for bit.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -20,17 +25,24 @@ import time
 
 import numpy as np
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_eval_items_kernel.txt")
+KERNEL_SOURCES = ["paper_2105_01196_amd/csrc/batched.hip", "paper_2105_01196_amd/csrc/device.h"]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", type=int, default=2, help="workload index 1..3")
-    ap.add_argument("--mode", choices=["plain"], default="plain")
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", type=int, default=2, help="matrix workload index 1..3")
+    ap.add_argument("--populations", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain-path leg")
+    ap.add_argument("--overlap", action="store_true",
+                    help="also write each individual's per-member overlap counts (the "
+                         "penalty itself never needs this output)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of rocprofv3) and exit")
@@ -48,12 +60,32 @@ def copy_probe(mib: int):
     print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
 
 
-def algorithmic_bytes(R: int, ks: np.ndarray, K: int) -> float:
-    """Bytes one evaluation moves in the plain definition: every cell of the
-    individual's R x k float32 submatrix once, its CSR entry (offset + k
-    indices) and its outputs (support bitmap, count, fitness, K overlaps)."""
-    P = ks.size
-    return float(4.0 * R * ks.sum() + 4.0 * P + 2.0 * ks.sum() + P * (R / 8.0 + 12 + 4 * K))
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the evaluation kernel from the committed
+    rocprofv3 counter summary, or None when the kernel source changed since
+    the counters were taken."""
+    try:
+        fields = {}
+        with open(TRAFFIC_FILE) as f:
+            for line in f:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+        if fields.get("source_sha256_16") != kernel_source_hash():
+            return None
+        if fields.get("workload") != workload:
+            return None
+        return float(fields["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def main():
@@ -66,16 +98,18 @@ def main():
               "is single-GPU here", file=sys.stderr)
         sys.exit(2)
     import torch
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    sys.path.insert(0, ROOT)
     import synth
     from paper_2105_01196_amd import ebic as E
 
     wi = args.workload
     w = synth.workload(wi)
     case = synth.workload_matrix(wi)
-    seqs = synth.workload_population(wi, case)
-    ks = np.array([len(s) for s in seqs], dtype=np.int64)
-    P, R = len(seqs), case.R
+    R, C = case.R, case.C
+    npop = args.populations
+    per = w.population // npop
+    pops_seqs = [synth.workload_population(wi, case, P=per, seed=synth.POP_SEED + wi + 10 * j)
+                 for j in range(npop)]
     K = 20
     params = E.make_params(approx_permille=850, negative_trends=1, overlap_permille=750,
                            min_rows=5)
@@ -83,37 +117,70 @@ def main():
     stream = torch.cuda.current_stream(dev)
     x = torch.from_numpy(case.X).to(dev)
     m = E.ebic_matrix_prepare(x)
-    pop = E.ebic_population_upload(seqs, case.C)
-    # archive: the 20 best individuals of a first evaluation
-    first = E.ebic_evaluate(m, pop, None, params)
     torch.cuda.synchronize()
-    fit = first.fitness.cpu().numpy()[:P]
-    top = [int(i) for i in np.argsort(-fit, kind="stable")[:K]]
-    arch = E.archive_from_device(first.support, top, seqs)
-    out = E.alloc_eval_out(P, m.words, K)
-
-    def step():
-        E.ebic_evaluate(m, pop, arch, params, out=out, stream=stream)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        ev0[s].record(stream)
-        step()
-        ev1[s].record(stream)
+    E.ebic_pairs_prepare(m)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in zip(ev0, ev1)]))
-    ms_per_step = wall * 1e3 / args.steps
-    value = P / (ms_per_step / 1e3)
-    alg = algorithmic_bytes(R, ks, K)
-    achieved = alg / (kern_ms / 1e3) / 1e9
-    cells = float(R * ks.sum())
+    table_ms = (time.perf_counter() - t0) * 1e3
 
+    pops, archs, plain_outs, jobs = [], [], [], []
+    for seqs in pops_seqs:
+        pop = E.ebic_population_upload(seqs, C)
+        first = E.ebic_evaluate(m, pop, None, params)
+        torch.cuda.synchronize()
+        fit = first.fitness.cpu().numpy()[:len(seqs)]
+        top = [int(i) for i in np.argsort(-fit, kind="stable")[:K]]
+        arch = E.archive_from_device(first.support, top, seqs)
+        E.set_order(pop, E.longest_first(seqs))
+        pops.append(pop)
+        archs.append(arch)
+        plain_outs.append(E.alloc_eval_out(len(seqs), m.words, K, overlap=args.overlap))
+        jobs.append(E.make_job(m, pop, arch, params, overlap=args.overlap))
+    batch = E.Batch(jobs)
+    P = sum(len(s) for s in pops_seqs)
+    ks = np.array([len(s) for seqs in pops_seqs for s in seqs], dtype=np.int64)
+
+    def plain_step():
+        for pop, arch, out in zip(pops, archs, plain_outs):
+            E.ebic_evaluate(m, pop, arch, params, out=out, stream=stream)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / steps
+
+    # batched (the measured path)
+    for _ in range(args.warmup):
+        batch.run(stream)
+    batch.profile(args.steps)
+    ms_batched = timed(lambda: batch.run(stream), args.steps)
+    a_ms, b_ms = batch.timings(args.steps)
+    batch.profile(0)
+    kern_a = float(a_ms.mean())
+    kern_b = float(b_ms.mean())
+
+    plain = None
+    if not args.no_plain:
+        for _ in range(args.warmup):
+            plain_step()
+        ms_plain = timed(plain_step, max(args.steps // 4, 5))
+        same = all(torch.equal(o.count, j.out.count) and torch.equal(o.fitness, j.out.fitness)
+                   and torch.equal(o.support, j.out.support)
+                   and (o.overlap is None or torch.equal(o.overlap, j.out.overlap))
+                   for o, j in zip(plain_outs, jobs))
+        plain = {"value": P / (ms_plain / 1e3), "ms_per_step": ms_plain,
+                 "launches_per_step": npop, "bit_exact_vs_batched": bool(same)}
+
+    value = P / (ms_batched / 1e3)
+    # Algorithmic bytes of the evaluation kernel: per individual, one R-bit
+    # pair bitmap per step ((k-1) R/8), its CSR entry (4 + 2k) and its
+    # support bitmap written (R/8).
+    alg = float(((ks - 1) * R / 8.0 + 4 + 2 * ks + R / 8.0).sum())
+    achieved = alg / (kern_a / 1e3) / 1e9
+    traffic = measured_traffic(w.name)
     line = {
         "metric": "individual evaluations/s and % peak HBM GB/s (batched vs plain, bit-exact)",
         "value": value,
@@ -121,45 +188,52 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": ms_batched,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u16",
+        "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": w.name, "rows": R, "cols": case.C, "population": P,
-                   "k_range": [w.k_min, w.k_max], "archive": K, "negative_trends": 1,
-                   "approx_permille": 850, "path": args.mode},
-        "cells_per_s": cells / (kern_ms / 1e3),
-        "kernel_ms": kern_ms,
+        "config": {"workload": w.name, "rows": R, "cols": C, "populations": npop,
+                   "individuals": P, "k_range": [w.k_min, w.k_max], "archive": K,
+                   "negative_trends": 1, "approx_permille": 850, "overlap_output": args.overlap,
+                   "path": "batched, pair table, one launch"},
+        "cells_per_s": float(R * ks.sum()) / (ms_batched / 1e3),
+        "kernel_ms": {"eval_items_kernel": kern_a, "epilogue_kernel": kern_b},
+        "pair_table": {"bytes": int(m.pairs.numel() * 8), "build_ms": table_ms},
+        "plain": plain,
+        "speedup_vs_plain": (plain["ms_per_step"] / ms_batched) if plain else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic, "kernel": "eval_items_kernel",
+                     "source_sha256_16": kernel_source_hash()},
     }
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(case.X, seqs, args)
+        line["cpu_baseline"] = cpu_baseline(case.X, pops_seqs[0])
     print(json.dumps(line), flush=True)
+    batch.close()
 
 
-def cpu_baseline(X, seqs, args):
+def cpu_baseline(X, seqs):
     """The oracle, as it stands, on a bounded sample of the same workload."""
     import oracle
     threads = min(os.cpu_count() or 1, 16)
     p = oracle.make_params(approx_permille=850, negative_trends=1, overlap_permille=750,
                            min_rows=5, k_score_min=3)
-    n = min(len(seqs), 1024)
-    sample = seqs[:n]
+    sample = list(seqs)
     t0 = time.perf_counter()
     reps = 0
     while True:
         oracle.evaluate(X, sample, params=p, nthreads=threads)
         reps += 1
-        if time.perf_counter() - t0 > 8.0 or reps >= 20:
+        if time.perf_counter() - t0 > 4.0 or reps >= 20:
             break
     dt = time.perf_counter() - t0
-    return {"value": reps * n / dt, "unit": "individual evaluations/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"first {n} individuals of the same population, {reps} passes, "
-                      f"empty archive, {threads} OpenMP threads"}
+    return {"value": reps * len(sample) / dt, "unit": "individual evaluations/s",
+            "cores": threads, "kind": "oracle",
+            "sample": f"one population of {len(sample)} individuals of the same workload, "
+                      f"{reps} passes, empty archive, {threads} OpenMP threads, "
+                      f"{dt:.1f} s wall"}
 
 
 if __name__ == "__main__":

@@ -207,6 +207,15 @@ int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_b
 int ebic_batch_run(ebic_batch *b, void *stream);
 int ebic_batch_destroy(ebic_batch *b);
 
+/* Kernel timing of a batch (metrics). ebic_batch_profile(b, n) makes the
+ * next n runs record HIP events around the evaluation kernel and the
+ * reduction kernel (n = 0 turns it off; graph-backed batches record around
+ * the whole graph, reported as evaluation time). ebic_batch_timings waits
+ * for the recorded runs and writes up to *n per-run times in milliseconds
+ * (ms_reduce may be NULL); *n returns the number written. */
+int ebic_batch_profile(ebic_batch *b, int32_t n);
+int ebic_batch_timings(ebic_batch *b, float *ms_eval, float *ms_reduce, int32_t *n);
+
 /* One-shot batched evaluation: create, run, wait, destroy. Synchronous. */
 int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream);
 

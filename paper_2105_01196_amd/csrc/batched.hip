@@ -13,6 +13,7 @@
 // words into the count, the rows shared with each archive member, and the
 // FP64 fitness. The paper sends the whole population to the GPU at once
 // (Sec. 2.4, step 2); here several populations share the launch.
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -23,10 +24,12 @@ namespace ebic {
 
 struct DevJob {
     const uint16_t *ranks;
-    const uint32_t *pairs;
+    const uint64_t *pairs;
     int32_t rows, cols, rows_pad, w32, w64;
     int32_t mode;     // 1 = pair table, 0 = gather
-    int32_t nchunks;  // items per individual
+    int32_t nchunks;  // 2048-row chunks per individual
+    int32_t cpi;      // chunks per item (one wave walks them in turn)
+    int32_t ipi;      // items per individual = ceil(nchunks / cpi)
     int32_t pop_size, pop_len;
     int64_t item_begin;  // first item of this job in the batch
     int64_t ind_begin;   // first individual of this job in the batch
@@ -48,64 +51,80 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
-constexpr int kItemRows = 2048;  // 64 lanes x 32 rows, or 32 blocks x 64 rows
+constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
+#ifndef EBIC_KBATCH
+#define EBIC_KBATCH 2
+#endif
+#ifndef EBIC_THERMO_MAX
+#define EBIC_THERMO_MAX 8
+#endif
+#ifndef EBIC_INLINE_COUNTERS
+#define EBIC_INLINE_COUNTERS 1
+#endif
+#if EBIC_INLINE_COUNTERS
+#define EBIC_COUNTER_FN __device__ __forceinline__
+#else
+#define EBIC_COUNTER_FN __device__ __noinline__
+#endif
+constexpr int kBatch = EBIC_KBATCH;  // pair-bitmap loads in flight per wave
+constexpr int kSupRegs = 8;      // support words kept in registers (64 x 8 words)
+constexpr int kMembCols = 2048;  // widest matrix whose member masks fit in LDS
 
-__device__ inline int find_job(const DevJob *jobs, int njobs, int64_t x, bool by_item) {
-    int lo = 0, hi = njobs - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) / 2;
-        const int64_t b = by_item ? jobs[mid].item_begin : jobs[mid].ind_begin;
-        if (b <= x) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+// Job of a flat index: count the job starts at or below it. The starts sit
+// in a compact array, so the loads are independent scalar loads.
+__device__ inline int find_job(const int64_t *__restrict__ begins, int njobs, int64_t x) {
+    int j = 0;
+    for (int q = 1; q < njobs; q++) j += begins[q] <= x;
+    return j;
 }
 
 // Thermometer counters of steps against the increasing trend (D) and against
-// the decreasing trend (U), T = t+1 planes each; returns the fit word.
+// the decreasing trend (U), T = t+1 planes each, over the 64 rows of this
+// lane's word; returns the fit word.
 template <int T, bool NEG>
-__device__ uint32_t pairs_thermo(const uint32_t *__restrict__ pairs, int64_t w32,
-                                 const int32_t *s_pd, int k, int w, bool active) {
-    uint32_t D[T], U[T];
+EBIC_COUNTER_FN uint64_t pairs_thermo(const uint64_t *__restrict__ pairs, int64_t w64,
+                                      const int32_t *s_pd, int k, int w, bool active) {
+    uint64_t D[T], U[T];
 #pragma unroll
     for (int m = 0; m < T; m++) D[m] = U[m] = 0;
     int j = 1;
     while (j < k) {
-        const int n = (k - j) < 4 ? (k - j) : 4;
-        uint32_t x[4];
+        const int n = (k - j) < kBatch ? (k - j) : kBatch;
+        uint64_t x[kBatch];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
+        for (int q = 0; q < kBatch; q++) {
             x[q] = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
-                const uint32_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w32;
-                const uint32_t bits = active ? vec[w] : 0u;
+                const uint64_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w64;
+                const uint64_t bits = active ? vec[w] : 0ull;
                 x[q] = pd < 0 ? ~bits : bits;  // 1 = up-step in this row
             }
         }
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            if (q >= n) break;
-            const uint32_t up = x[q], down = ~x[q];
+        for (int q = 0; q < kBatch; q++) {
+            if (q < n) {  // uniform; no break, so the loop unrolls fully
+                const uint64_t up = x[q], down = ~x[q];
 #pragma unroll
-            for (int m = T - 1; m >= 1; m--) {
-                D[m] |= D[m - 1] & down;
-                if (NEG) U[m] |= U[m - 1] & up;
+                for (int m = T - 1; m >= 1; m--) {
+                    D[m] |= D[m - 1] & down;
+                    if (NEG) U[m] |= U[m - 1] & up;
+                }
+                D[0] |= down;
+                if (NEG) U[0] |= up;
             }
-            D[0] |= down;
-            if (NEG) U[0] |= up;
         }
         j += n;
-        const uint32_t dead = D[T - 1] & (NEG ? U[T - 1] : ~0u);
-        if (__ballot(active && dead != ~0u) == 0) break;
+        const uint64_t dead = D[T - 1] & (NEG ? U[T - 1] : ~0ull);
+        if (__ballot(active && dead != ~0ull) == 0) break;
     }
-    return ~D[T - 1] | (NEG ? ~U[T - 1] : 0u);
+    return ~D[T - 1] | (NEG ? ~U[T - 1] : 0ull);
 }
 
-// Bit-sliced compare of the 9-bit per-row counts b[] with a constant:
-// returns rows with count < c in *lt and count == c in *eq.
-__device__ inline void cmp_const(const uint32_t *b, int c, uint32_t *lt, uint32_t *eq) {
-    uint32_t l = 0, e = ~0u;
+// Bit-sliced compare of the 9-bit per-row counts b[] with a wave-uniform
+// value c (0 <= c < 512): rows with count < c in *lt, count == c in *eq.
+__device__ __forceinline__ void cmp_const(const uint64_t *b, int c, uint64_t *lt, uint64_t *eq) {
+    uint64_t l = 0, e = ~0ull;
 #pragma unroll
     for (int p = 8; p >= 0; p--) {
         if ((c >> p) & 1) {
@@ -119,29 +138,58 @@ __device__ inline void cmp_const(const uint32_t *b, int c, uint32_t *lt, uint32_
     *eq = e;
 }
 
-// Exact bit-sliced count of up-steps (9 planes, k <= 512) for large
-// tolerances; returns the fit word.
+// Exact bit-sliced count of up-steps (9 planes, k <= 512) for larger
+// tolerances; returns the fit word. Early exit once every row has more than
+// t steps against each trend (ups > t and downs = steps - ups > t).
 template <bool NEG>
-__device__ uint32_t pairs_binary(const uint32_t *__restrict__ pairs, int64_t w32,
-                                 const int32_t *s_pd, int k, int t, int w, bool active) {
-    uint32_t b[9];
+EBIC_COUNTER_FN uint64_t pairs_binary(const uint64_t *__restrict__ pairs, int64_t w64,
+                                      const int32_t *s_pd, int k, int t, int w, bool active) {
+    uint64_t b[9];
 #pragma unroll
     for (int p = 0; p < 9; p++) b[p] = 0;
-    for (int j = 1; j < k; j++) {
-        const int pd = __builtin_amdgcn_readfirstlane(s_pd[j]);
-        const uint32_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w32;
-        const uint32_t bits = active ? vec[w] : 0u;
-        uint32_t carry = pd < 0 ? ~bits : bits;
+    int j = 1;
+    while (j < k) {
+        const int n = (k - j) < kBatch ? (k - j) : kBatch;
+        uint64_t x[kBatch];
 #pragma unroll
-        for (int p = 0; p < 9; p++) {
-            const uint32_t c2 = b[p] & carry;
-            b[p] ^= carry;
-            carry = c2;
+        for (int q = 0; q < kBatch; q++) {
+            x[q] = 0;
+            if (q < n) {
+                const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
+                const uint64_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w64;
+                const uint64_t bits = active ? vec[w] : 0ull;
+                x[q] = pd < 0 ? ~bits : bits;
+            }
         }
+#pragma unroll
+        for (int q = 0; q < kBatch; q++) {
+            if (q < n) {
+                uint64_t carry = x[q];
+#pragma unroll
+                for (int p = 0; p < 9; p++) {
+                    const uint64_t c2 = b[p] & carry;
+                    b[p] ^= carry;
+                    carry = c2;
+                }
+            }
+        }
+        j += n;
+        uint64_t lt, eq;
+        cmp_const(b, t, &lt, &eq);
+        uint64_t dead = ~(lt | eq);  // ups > t: the decreasing trend is broken
+        if (!NEG) dead = ~0ull;
+        const int cd = (j - 1) - t;  // steps so far minus t
+        if (cd <= 0) {
+            dead = 0;  // no row can have more than t steps against the increase yet
+        } else {
+            cmp_const(b, cd, &lt, &eq);
+            dead &= lt;  // ups < steps - t: the increasing trend is broken
+        }
+        if (__ballot(active && dead != ~0ull) == 0) break;
     }
-    uint32_t lt, eq;
+    uint64_t lt, eq;
     cmp_const(b, k - 1 - t, &lt, &eq);
-    uint32_t fit = ~lt;  // ups >= k-1-t  <=>  downs <= t
+    uint64_t fit = ~lt;  // ups >= k-1-t  <=>  downs <= t
     if (NEG) {
         cmp_const(b, t, &lt, &eq);
         fit |= lt | eq;  // ups <= t
@@ -150,29 +198,41 @@ __device__ uint32_t pairs_binary(const uint32_t *__restrict__ pairs, int64_t w32
 }
 
 template <bool NEG>
-__device__ uint32_t pairs_dispatch(const uint32_t *pairs, int64_t w32, const int32_t *s_pd, int k,
-                                   int t, int w, bool active) {
+__device__ __forceinline__ uint64_t pairs_dispatch(const uint64_t *pairs, int64_t w64,
+                                                   const int32_t *s_pd, int k, int t, int w,
+                                                   bool active) {
     switch (t) {
 #define EBIC_T(TT) \
-    case TT - 1: return pairs_thermo<TT, NEG>(pairs, w32, s_pd, k, w, active);
-        EBIC_T(1) EBIC_T(2) EBIC_T(3) EBIC_T(4) EBIC_T(5) EBIC_T(6) EBIC_T(7) EBIC_T(8)
-        EBIC_T(9) EBIC_T(10) EBIC_T(11) EBIC_T(12) EBIC_T(13) EBIC_T(14) EBIC_T(15) EBIC_T(16)
+    case TT - 1: return pairs_thermo<TT, NEG>(pairs, w64, s_pd, k, w, active);
+        EBIC_T(1) EBIC_T(2) EBIC_T(3) EBIC_T(4)
+#if EBIC_THERMO_MAX > 4
+        EBIC_T(5) EBIC_T(6) EBIC_T(7) EBIC_T(8)
+#endif
+#if EBIC_THERMO_MAX > 8
+        EBIC_T(9) EBIC_T(10) EBIC_T(11) EBIC_T(12)
+#endif
+#if EBIC_THERMO_MAX > 12
+        EBIC_T(13) EBIC_T(14) EBIC_T(15) EBIC_T(16)
+#endif
 #undef EBIC_T
-        default: return pairs_binary<NEG>(pairs, w32, s_pd, k, t, w, active);
+        default: return pairs_binary<NEG>(pairs, w64, s_pd, k, t, w, active);
     }
 }
 
 __global__ void __launch_bounds__(kThreads)
-    eval_items_kernel(const DevJob *__restrict__ jobs, int32_t njobs, int64_t total_items) {
+    eval_items_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ item_begins,
+                      int32_t njobs, int64_t total_items) {
     __shared__ int32_t s_buf[kWaves][EBIC_MAX_K];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t item = (int64_t)blockIdx.x * kWaves + wave;
     if (item >= total_items) return;
-    const DevJob &J = jobs[find_job(jobs, njobs, item, true)];
+    const DevJob &J = jobs[find_job(item_begins, njobs, item)];
     const int64_t local = item - J.item_begin;
-    const int32_t oi = (int32_t)(local / J.nchunks), chunk = (int32_t)(local % J.nchunks);
+    const int32_t oi = (int32_t)(local / J.ipi), grp = (int32_t)(local % J.ipi);
     const int32_t ind = J.order ? J.order[oi] : oi;
     if (ind < 0 || ind >= J.pop_size) return;
+    const int32_t ch0 = grp * J.cpi;
+    const int32_t ch1 = ch0 + J.cpi < J.nchunks ? ch0 + J.cpi : J.nchunks;
     const int32_t beg = J.pop_off[ind], end = J.pop_off[ind + 1];
     const int k = end - beg;
     int32_t *s = s_buf[wave];
@@ -199,47 +259,91 @@ __global__ void __launch_bounds__(kThreads)
         bad = __ballot(lbad) != 0;
     }
     if (bad) {  // malformed: kernel B marks it invalid; never read out of bounds
-        const int32_t w0 = chunk * 32;
-        if (lane < 32 && w0 + lane < J.w64) J.support[(int64_t)ind * J.w64 + w0 + lane] = 0;
+        for (int32_t ch = ch0; ch < ch1; ch++) {
+            const int32_t w = ch * 64 + lane;
+            if (w < J.w64) J.support[(int64_t)ind * J.w64 + w] = 0;
+        }
         return;
     }
     const int t = tol(k, J.approx_permille);
     const bool neg = J.negative_trends != 0;
-    if (J.mode == 1) {
-        const int w = chunk * 64 + lane;  // this lane's 32-row dword
-        const bool active = w < J.w32;
-        uint32_t fit = neg ? pairs_dispatch<true>(J.pairs, J.w32, s, k, t, w, active)
-                           : pairs_dispatch<false>(J.pairs, J.w32, s, k, t, w, active);
-        const int r0 = w * 32;
-        if (r0 + 32 > J.rows) fit &= r0 >= J.rows ? 0u : ((1u << (J.rows - r0)) - 1u);
-        if (active) reinterpret_cast<uint32_t *>(J.support)[(int64_t)ind * J.w32 + w] = fit;
-    } else {
-        const __amdgpu_buffer_rsrc_t rs =
-            make_rsrc(J.ranks, (uint32_t)((size_t)J.cols * J.rows_pad * 2));
-        int lo = 0, hi = 0;
-        const int b0 = chunk * 32;
-        for (int b = 0; b < 32 && b0 + b < J.w64; b++) {
-            const int r = (b0 + b) * kWave + lane;
-            const uint64_t word = block_support(rs, s, k, t, neg, r * 2, r < J.rows);
-            lo = writelane((int)(uint32_t)word, b, lo);
-            hi = writelane((int)(uint32_t)(word >> 32), b, hi);
+    for (int32_t chunk = ch0; chunk < ch1; chunk++) {
+        const int w = chunk * 64 + lane;  // this lane's 64-row word
+        if (J.mode == 1) {
+            const bool active = w < J.w64;
+            uint64_t fit = neg ? pairs_dispatch<true>(J.pairs, J.w64, s, k, t, w, active)
+                               : pairs_dispatch<false>(J.pairs, J.w64, s, k, t, w, active);
+            const int r0 = w * 64;
+            if (r0 + 64 > J.rows) fit &= r0 >= J.rows ? 0ull : ((1ull << (J.rows - r0)) - 1ull);
+            if (active) J.support[(int64_t)ind * J.w64 + w] = fit;
+        } else {
+            const __amdgpu_buffer_rsrc_t rs =
+                make_rsrc(J.ranks, (uint32_t)((size_t)J.cols * J.rows_pad * 2));
+            int lo = 0, hi = 0;
+            const int b0 = chunk * 64;
+            for (int b = 0; b < 64 && b0 + b < J.w64; b++) {
+                const int r = (b0 + b) * kWave + lane;
+                const uint64_t word = block_support(rs, s, k, t, neg, r * 2, r < J.rows);
+                lo = writelane((int)(uint32_t)word, b, lo);
+                hi = writelane((int)(uint32_t)(word >> 32), b, hi);
+            }
+            if (w < J.w64)
+                J.support[(int64_t)ind * J.w64 + w] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
         }
-        if (lane < 32 && b0 + lane < J.w64)
-            J.support[(int64_t)ind * J.w64 + b0 + lane] =
-                ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
     }
 }
 
 // Kernel B: one wave per individual. Validates the series (length, range,
-// no repeated column), reduces the support words into n and the rows shared
-// with each archive member, and writes count, overlap and fitness.
+// no repeated column), reduces the support words into n, and for each
+// archive member counts the shared columns g and, where the penalty can
+// depend on it or the caller asked for it, the shared rows h; writes count,
+// overlap and fitness. When the size score is 0 the fitness is 0 whatever
+// the penalty, so the members are only visited for the overlap output.
+// Shared columns come from per-column member masks built once per
+// workgroup in LDS (bit j of memb[c] = member j holds column c): each lane
+// takes one column of the series, and g_j is one ballot. Since h <= n, a
+// member can only overlap too much when 1000 g > theta k, so the shared rows
+// are only counted for those members (or when the output is requested).
 __global__ void __launch_bounds__(kThreads)
-    epilogue_kernel(const DevJob *__restrict__ jobs, int32_t njobs, int64_t total_ind) {
+    epilogue_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ ind_begins,
+                    int32_t njobs, int64_t total_ind) {
     __shared__ uint32_t s_bits[kWaves][EBIC_MAX_COLS / 32];
+    __shared__ uint64_t s_memb[kMembCols];
+    __shared__ int32_t s_aoff[EBIC_MAX_ARCHIVE + 1];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t gid = (int64_t)blockIdx.x * kWaves + wave;
+    const int64_t gid0 = (int64_t)blockIdx.x * kWaves;
+    const int64_t gid = gid0 + wave;
+    // member masks, shared by the workgroup when all its waves are of one job
+    const int64_t last = (gid0 + kWaves - 1 < total_ind ? gid0 + kWaves - 1 : total_ind - 1);
+    const int jf = find_job(ind_begins, njobs, gid0);
+    const bool shared_job = find_job(ind_begins, njobs, last) == jf;
+    const DevJob &JF = jobs[jf];
+    const bool use_memb = shared_job && JF.arch_size > 0 && JF.cols <= kMembCols;
+    if (use_memb) {
+        const int KF = JF.arch_size;
+        for (int c = threadIdx.x; c < JF.cols; c += kThreads) s_memb[c] = 0;
+        for (int j = threadIdx.x; j <= KF; j += kThreads) {
+            const int32_t o = JF.arch_off[j];
+            s_aoff[j] = o < 0 ? 0 : (o > JF.arch_len ? JF.arch_len : o);
+        }
+        __syncthreads();
+        // every archive entry at once; its member by binary search of the
+        // offsets (member j holds entries s_aoff[j] .. s_aoff[j+1])
+        for (int q = s_aoff[0] + threadIdx.x; q < s_aoff[KF]; q += kThreads) {
+            int lo = 0, hi = KF - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) / 2;
+                if (s_aoff[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const int col = JF.arch_cols[q];
+            if (col < JF.cols && q < s_aoff[lo + 1])
+                atomicOr((unsigned long long *)&s_memb[col], 1ull << lo);
+        }
+        __syncthreads();
+    }
     if (gid >= total_ind) return;
-    const DevJob &J = jobs[find_job(jobs, njobs, gid, false)];
+    const DevJob &J = jobs[find_job(ind_begins, njobs, gid)];
     const int32_t i = (int32_t)(gid - J.ind_begin);
     const int32_t beg = J.pop_off[i], end = J.pop_off[i + 1];
     const int k = end - beg;
@@ -273,36 +377,79 @@ __global__ void __launch_bounds__(kThreads)
         }
         return;
     }
+    const bool in_regs = J.w64 <= kWave * kSupRegs;
+    uint64_t sv[kSupRegs];
     int c = 0;
-    for (int w = lane; w < J.w64; w += kWave) c += __popcll(S[w]);
+#pragma unroll
+    for (int q = 0; q < kSupRegs; q++) {
+        const int w = lane + kWave * q;
+        sv[q] = (in_regs && w < J.w64) ? S[w] : 0;
+        c += __popcll(sv[q]);
+    }
+    if (!in_regs)
+        for (int w = lane; w < J.w64; w += kWave) c += __popcll(S[w]);
     const int n = wave_sum(c);
+    const double score = (n >= J.min_rows && k >= J.k_score_min) ? ldexp((double)n, k) : 0.0;
     int m = 0;
-    int32_t my_h = 0;  // lane j keeps h of member j (j < 64)
-    for (int j = 0; j < K; j++) {
-        int32_t mb = J.arch_off[j], me = J.arch_off[j + 1];
-        if (mb < 0) mb = 0;
-        if (me > J.arch_len) me = J.arch_len;
-        int g = 0;
-        for (int q = mb + lane; q < me; q += kWave) {
-            const int col = J.arch_cols[q];
-            g += col < J.cols ? (int)((bits[col / 32] >> (col % 32)) & 1u) : 0;
+    int32_t my_h = 0;  // lane j keeps h of member j
+    if (K > 0 && (score > 0.0 || J.overlap)) {
+        // my_g: lane j ends with g_j
+        int my_g = 0;
+        if (use_memb) {
+            for (int q0 = 0; q0 < k; q0 += kWave) {
+                const int q = q0 + lane;
+                const uint64_t mask = q < k ? s_memb[J.pop_cols[beg + q]] : 0ull;
+                for (int j = 0; j < K; j++) {
+                    const int gj = __popcll(__ballot((mask >> j) & 1ull));
+                    if (lane == j) my_g += gj;
+                }
+            }
+        } else {
+            for (int j = 0; j < K; j++) {
+                int32_t mb = J.arch_off[j], me = J.arch_off[j + 1];
+                if (mb < 0) mb = 0;
+                if (me > J.arch_len) me = J.arch_len;
+                int g = 0;
+                for (int q0 = mb; q0 < me; q0 += kWave) {
+                    const int q = q0 + lane;
+                    bool hit = false;
+                    if (q < me) {
+                        const int col = J.arch_cols[q];
+                        hit = col < J.cols && ((bits[col / 32] >> (col % 32)) & 1u);
+                    }
+                    g += __popcll(__ballot(hit));
+                }
+                if (lane == j) my_g = g;
+            }
         }
-        g = wave_sum(g);
-        int h = 0;
-        if (n > 0 && (J.overlap || g > 0)) {
+        // members whose rows must be counted
+        const bool my_need = lane < K && n > 0 &&
+                             (J.overlap || 1000LL * my_g > (long long)J.overlap_permille * k);
+        uint64_t need = __ballot(my_need);
+        while (need) {
+            const int j = __ffsll((unsigned long long)need) - 1;
+            need &= need - 1;
             const uint64_t *A = J.arch_support + (int64_t)j * J.w64;
             int hp = 0;
-            for (int w = lane; w < J.w64; w += kWave) hp += __popcll(S[w] & A[w]);
-            h = wave_sum(hp);
+            if (in_regs) {
+#pragma unroll
+                for (int q = 0; q < kSupRegs; q++) {
+                    const int w = lane + kWave * q;
+                    if (w < J.w64) hp += __popcll(sv[q] & A[w]);
+                }
+            } else {
+                for (int w = lane; w < J.w64; w += kWave) hp += __popcll(S[w] & A[w]);
+            }
+            const int h = wave_sum(hp);
+            if (lane == j) my_h = h;
         }
-        if (lane == j) my_h = h;
-        m += 1000LL * h * g > (long long)J.overlap_permille * n * k;
+        const bool over = lane < K && 1000LL * my_h * my_g > (long long)J.overlap_permille * n * k;
+        m = __popcll(__ballot(over));
     }
     if (J.overlap && lane < K) J.overlap[(int64_t)i * K + lane] = my_h;
     if (lane == 0) {
-        const double s = (n >= J.min_rows && k >= J.k_score_min) ? ldexp((double)n, k) : 0.0;
         J.count[i] = n;
-        J.fitness[i] = ldexp(s, -m);
+        J.fitness[i] = ldexp(score, -m);
     }
 }
 
@@ -315,16 +462,33 @@ __global__ void __launch_bounds__(kThreads)
 struct Batch {
     int device = 0;
     std::vector<DevJob> jobs;
-    DevJob *d_jobs = nullptr;
+    DevJob *d_jobs = nullptr;       // device: DevJob[njobs], then the two begin arrays
+    int64_t *d_item_begins = nullptr;
+    int64_t *d_ind_begins = nullptr;
     std::vector<void *> scratch;
     int64_t total_items = 0, total_ind = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     // kernel arguments kept alive for the graph's nodes
     int32_t njobs = 0;
+    // timing: three events per profiled run (start, between, end)
+    std::vector<hipEvent_t> events;
+    int32_t prof_cap = 0, prof_used = 0;
 };
 
 namespace {
+
+// Chunks per item: one wave walks them in turn, paying the series set-up
+// once. EBIC_CHUNKS_PER_ITEM overrides the default (for tuning).
+int chunks_per_item(int nchunks) {
+    static const int forced = [] {
+        const char *v = getenv("EBIC_CHUNKS_PER_ITEM");
+        return v ? atoi(v) : 0;
+    }();
+    int c = forced > 0 ? forced : 1;
+    if (c > nchunks) c = nchunks;
+    return c < 1 ? 1 : c;
+}
 
 int check_job(const ebic_job *j, int idx) {
     const ebic_matrix *m = &j->matrix;
@@ -362,7 +526,7 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
         const ebic_job &j = jobs[i];
         DevJob d{};
         d.ranks = j.matrix.d_ranks;
-        d.pairs = reinterpret_cast<const uint32_t *>(j.matrix.d_pairs);
+        d.pairs = j.matrix.d_pairs;
         d.rows = j.matrix.rows;
         d.cols = j.matrix.cols;
         d.rows_pad = j.matrix.rows_pad;
@@ -370,6 +534,8 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
         d.w64 = j.matrix.rows_pad / 64;
         d.mode = (j.matrix.d_pairs && !(flags & EBIC_BATCH_GATHER)) ? 1 : 0;
         d.nchunks = (j.matrix.rows_pad + kItemRows - 1) / kItemRows;
+        d.cpi = chunks_per_item(d.nchunks);
+        d.ipi = (d.nchunks + d.cpi - 1) / d.cpi;
         d.pop_size = j.population.size;
         d.pop_len = j.population.length;
         d.pop_off = j.population.d_offsets;
@@ -401,15 +567,29 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
             b->scratch.push_back(p);
             d.support = static_cast<uint64_t *>(p);
         }
-        items += (int64_t)d.pop_size * d.nchunks;
+        items += (int64_t)d.pop_size * d.ipi;
         inds += d.pop_size;
         b->jobs.push_back(d);
     }
     b->total_items = items;
     b->total_ind = inds;
-    hipError_t e = hipMalloc(&b->d_jobs, sizeof(DevJob) * njobs);
+    std::vector<int64_t> begins(2 * (size_t)njobs);
+    for (int i = 0; i < njobs; i++) {
+        begins[i] = b->jobs[i].item_begin;
+        begins[njobs + i] = b->jobs[i].ind_begin;
+    }
+    void *mem = nullptr;
+    const size_t jbytes = sizeof(DevJob) * njobs;
+    hipError_t e = hipMalloc(&mem, jbytes + sizeof(int64_t) * begins.size());
+    if (e == hipSuccess) {
+        b->d_jobs = static_cast<DevJob *>(mem);
+        b->d_item_begins = reinterpret_cast<int64_t *>(static_cast<char *>(mem) + jbytes);
+        b->d_ind_begins = b->d_item_begins + njobs;
+        e = hipMemcpy(b->d_jobs, b->jobs.data(), jbytes, hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess)
-        e = hipMemcpy(b->d_jobs, b->jobs.data(), sizeof(DevJob) * njobs, hipMemcpyHostToDevice);
+        e = hipMemcpy(b->d_item_begins, begins.data(), sizeof(int64_t) * begins.size(),
+                      hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         batch_destroy(b);
         return check_hip(e, "batch job table");
@@ -418,8 +598,8 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
         // Two kernel nodes, A then B, built explicitly (no stream capture).
         int rc = EBIC_OK;
         hipGraphNode_t na = nullptr, nb = nullptr;
-        void *args_a[] = {&b->d_jobs, &b->njobs, &b->total_items};
-        void *args_b[] = {&b->d_jobs, &b->njobs, &b->total_ind};
+        void *args_a[] = {&b->d_jobs, &b->d_item_begins, &b->njobs, &b->total_items};
+        void *args_b[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
         hipKernelNodeParams pa{}, pb{};
         pa.func = reinterpret_cast<void *>(eval_items_kernel);
         pa.gridDim = dim3((unsigned)((b->total_items + kWaves - 1) / kWaves));
@@ -446,21 +626,58 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
 int batch_run(Batch *b, hipStream_t stream) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (b->total_ind == 0) return EBIC_OK;
+    hipEvent_t *ev = nullptr;
+    if (b->prof_used < b->prof_cap) ev = &b->events[3 * b->prof_used++];
+    if (ev) EBIC_HIP(hipEventRecord(ev[0], stream));
     if (b->exec) {
         EBIC_HIP(hipGraphLaunch(b->exec, stream));
+        if (ev) {
+            EBIC_HIP(hipEventRecord(ev[1], stream));
+            EBIC_HIP(hipEventRecord(ev[2], stream));
+        }
         return EBIC_OK;
     }
     if (b->total_items > 0)
         eval_items_kernel<<<(unsigned)((b->total_items + kWaves - 1) / kWaves), kThreads, 0,
-                            stream>>>(b->d_jobs, b->njobs, b->total_items);
+                            stream>>>(b->d_jobs, b->d_item_begins, b->njobs, b->total_items);
+    if (ev) EBIC_HIP(hipEventRecord(ev[1], stream));
     epilogue_kernel<<<(unsigned)((b->total_ind + kWaves - 1) / kWaves), kThreads, 0, stream>>>(
-        b->d_jobs, b->njobs, b->total_ind);
+        b->d_jobs, b->d_ind_begins, b->njobs, b->total_ind);
+    if (ev) EBIC_HIP(hipEventRecord(ev[2], stream));
     EBIC_HIP(hipGetLastError());
+    return EBIC_OK;
+}
+
+int batch_profile(Batch *b, int32_t n) {
+    if (!b || n < 0) return fail(EBIC_ERR_INVALID_ARG, "bad batch or count");
+    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
+    b->events.clear();
+    b->prof_cap = b->prof_used = 0;
+    for (int32_t i = 0; i < 3 * n; i++) {
+        hipEvent_t e;
+        EBIC_HIP(hipEventCreate(&e));
+        b->events.push_back(e);
+    }
+    b->prof_cap = n;
+    return EBIC_OK;
+}
+
+int batch_timings(Batch *b, float *ms_eval, float *ms_reduce, int32_t *n) {
+    if (!b || !ms_eval || !n || *n < 0) return fail(EBIC_ERR_INVALID_ARG, "bad arguments");
+    const int32_t m = b->prof_used < *n ? b->prof_used : *n;
+    for (int32_t i = 0; i < m; i++) {
+        hipEvent_t *ev = &b->events[3 * i];
+        EBIC_HIP(hipEventSynchronize(ev[2]));
+        EBIC_HIP(hipEventElapsedTime(&ms_eval[i], ev[0], ev[1]));
+        if (ms_reduce) EBIC_HIP(hipEventElapsedTime(&ms_reduce[i], ev[1], ev[2]));
+    }
+    *n = m;
     return EBIC_OK;
 }
 
 int batch_destroy(Batch *b) {
     if (!b) return EBIC_OK;
+    for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->d_jobs) (void)hipFree(b->d_jobs);

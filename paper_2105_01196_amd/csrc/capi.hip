@@ -226,6 +226,16 @@ int ebic_batch_destroy(ebic_batch *b) {
     return batch_destroy(reinterpret_cast<Batch *>(b));
 }
 
+int ebic_batch_profile(ebic_batch *b, int32_t n) {
+    clear_error();
+    return batch_profile(reinterpret_cast<Batch *>(b), n);
+}
+
+int ebic_batch_timings(ebic_batch *b, float *ms_eval, float *ms_reduce, int32_t *n) {
+    clear_error();
+    return batch_timings(reinterpret_cast<Batch *>(b), ms_eval, ms_reduce, n);
+}
+
 int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream) {
     clear_error();
     Batch *b = nullptr;

@@ -65,10 +65,16 @@ __device__ inline int writelane(int val, int lane, int old) {
     return old;
 }
 
+// Sum over the 64 lanes (all lanes must be active): DPP butterflies within
+// each 16-lane row (quad xor 1, quad xor 2, half-row mirror, row mirror),
+// then the four row sums read out with readlane. Wave-uniform result.
 __device__ inline int wave_sum(int v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 
 // Index of the unordered column pair (lo < hi) among the C(C-1)/2 pairs in

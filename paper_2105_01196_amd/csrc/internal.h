@@ -70,5 +70,7 @@ struct Batch;
 int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out);
 int batch_run(Batch *b, hipStream_t stream);
 int batch_destroy(Batch *b);
+int batch_profile(Batch *b, int32_t n);
+int batch_timings(Batch *b, float *ms_eval, float *ms_reduce, int32_t *n);
 
 }  // namespace ebic

@@ -93,6 +93,10 @@ _SIGNATURES = {
     "ebic_batch_run": (ctypes.c_int, [_vp, _vp]),
     "ebic_batch_destroy": (ctypes.c_int, [_vp]),
     "ebic_evaluate_batched": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _vp]),
+    "ebic_batch_profile": (ctypes.c_int, [_vp, _i32]),
+    "ebic_batch_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(ctypes.c_float),
+                                          ctypes.POINTER(_i32)]),
 }
 
 _lib = None
@@ -384,6 +388,18 @@ class Batch:
 
     def run(self, stream=None) -> None:
         _check(lib().ebic_batch_run(self.handle, _stream(stream)))
+
+    def profile(self, n: int) -> None:
+        """Record kernel times for the next n runs."""
+        _check(lib().ebic_batch_profile(self.handle, n))
+
+    def timings(self, n: int):
+        """(evaluation ms, reduction ms) of up to n recorded runs."""
+        a = (ctypes.c_float * max(n, 1))()
+        b = (ctypes.c_float * max(n, 1))()
+        m = _i32(n)
+        _check(lib().ebic_batch_timings(self.handle, a, b, ctypes.byref(m)))
+        return np.array(a[:m.value]), np.array(b[:m.value])
 
     def close(self) -> None:
         if self.handle:
