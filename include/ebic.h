@@ -219,6 +219,52 @@ int ebic_batch_timings(ebic_batch *b, float *ms_eval, float *ms_reduce, int32_t 
 /* One-shot batched evaluation: create, run, wait, destroy. Synchronous. */
 int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream);
 
+/* One bicluster of a run: rows ascending, columns in series order. */
+typedef struct ebic_bicluster {
+    int32_t n_rows;
+    const int32_t *rows;
+    int32_t n_cols;
+    const uint16_t *cols;
+    double score;              /* size score s = n * 2^k */
+} ebic_bicluster;
+
+#define EBIC_STOP_GENERATIONS 1 /* the iteration limit was reached            */
+#define EBIC_STOP_TABU 2        /* the tabu-hit threshold was reached         */
+#define EBIC_STOP_EXHAUSTED 3   /* a population slot ran out of attempts      */
+
+/* Result of ebic_run; library-owned, released with ebic_result_free. */
+typedef struct ebic_result {
+    int32_t count;                      /* biclusters returned (<= n_out)       */
+    const ebic_bicluster *biclusters;   /* top-rank order: score desc, series asc */
+    int32_t generations;                /* populations evaluated                */
+    int64_t evaluations;                /* individuals evaluated                */
+    int64_t tabu_hits;
+    int32_t stop_reason;                /* EBIC_STOP_*                           */
+    const double *trace;                /* generations x 4: population size,
+                                           top-rank size, best score, tabu hits
+                                           so far (after each evaluation)       */
+} ebic_result;
+
+/* The whole method (Sec. 2.4, steps 1-9) on a host float32 rows x cols
+ * row-major matrix: random initial population of series (step 1), GPU
+ * evaluation of every population (steps 2 and 7), top-rank list update
+ * (steps 3 and 7), elitism (step 4), tournament selection with the
+ * column-overuse penalty and mutation (step 5), tabu list and tabu-hit stop
+ * (step 6), and the final supports of the top-rank list (step 9). All draws
+ * come from one SplitMix64 stream seeded with `seed`; the same seed gives the
+ * same result. The host parts follow the readings stated at the top of this
+ * file and in the parameter comments; evaluation uses the pair table when
+ * it fits in a quarter of the free device memory, else the gather form
+ * (identical results). Device memory is allocated and freed inside the call.
+ * Synchronous on `stream`. Errors: EBIC_ERR_INVALID_ARG (parameters:
+ * 2 <= k_min <= k_max <= min(cols, 512), population >= 1, generations >= 1,
+ * 1 <= archive_size <= 64, tournament >= 1, max_attempts >= 1,
+ * max_tabu_hits >= 1, n_out >= 0), EBIC_ERR_NONFINITE, EBIC_ERR_OOM,
+ * EBIC_ERR_DEVICE. On success *out is set. */
+int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
+             void *stream, ebic_result **out);
+void ebic_result_free(ebic_result *r);
+
 /* Support compaction (Sec. 2.4, step 9: the trend-preserving rows' indices of
  * the top-rank list). For each of n_sel selected individuals sel[i] of a
  * P x W support array, writes its row indices in ascending order to

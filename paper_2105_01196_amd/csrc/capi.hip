@@ -251,6 +251,16 @@ int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream) {
     return rc;
 }
 
+int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
+             void *stream, ebic_result **out) {
+    clear_error();
+    return run_method(h_x, rows, cols, p, seed, static_cast<hipStream_t>(stream), out);
+}
+
+void ebic_result_free(ebic_result *r) {
+    if (r) free_result(r);
+}
+
 int ebic_support_rows(const uint64_t *d_support, int32_t size, int32_t words,
                       const int32_t *d_sel, int32_t n_sel, const int32_t *d_row_offsets,
                       int32_t *d_rows, void *stream) {

@@ -66,6 +66,10 @@ int launch_prepare(const float *x, int32_t rows, int32_t cols, uint16_t *ranks, 
 int launch_build_pairs(const uint16_t *ranks, int32_t cols, int32_t rows_pad, uint64_t *table,
                        hipStream_t stream);
 
+int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
+               hipStream_t stream, ebic_result **out);
+void free_result(ebic_result *r);
+
 struct Batch;
 int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out);
 int batch_run(Batch *b, hipStream_t stream);

@@ -70,6 +70,21 @@ class ebic_job(ctypes.Structure):
                 ("archive", ebic_archive), ("params", ebic_params), ("out", ebic_eval_out)]
 
 
+class ebic_bicluster(ctypes.Structure):
+    _fields_ = [("n_rows", _i32), ("rows", ctypes.POINTER(_i32)), ("n_cols", _i32),
+                ("cols", ctypes.POINTER(ctypes.c_uint16)), ("score", ctypes.c_double)]
+
+
+class ebic_result(ctypes.Structure):
+    _fields_ = [("count", _i32), ("biclusters", ctypes.POINTER(ebic_bicluster)),
+                ("generations", _i32), ("evaluations", ctypes.c_int64),
+                ("tabu_hits", ctypes.c_int64), ("stop_reason", _i32),
+                ("trace", ctypes.POINTER(ctypes.c_double))]
+
+
+EBIC_STOP_GENERATIONS = 1
+EBIC_STOP_TABU = 2
+EBIC_STOP_EXHAUSTED = 3
 EBIC_BATCH_GRAPH = 1
 EBIC_BATCH_GATHER = 2
 
@@ -93,6 +108,9 @@ _SIGNATURES = {
     "ebic_batch_run": (ctypes.c_int, [_vp, _vp]),
     "ebic_batch_destroy": (ctypes.c_int, [_vp]),
     "ebic_evaluate_batched": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _vp]),
+    "ebic_run": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params), ctypes.c_uint64,
+                                _vp, ctypes.POINTER(ctypes.POINTER(ebic_result))]),
+    "ebic_result_free": (None, [ctypes.POINTER(ebic_result)]),
     "ebic_batch_profile": (ctypes.c_int, [_vp, _i32]),
     "ebic_batch_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float),
@@ -416,6 +434,51 @@ class Batch:
 def ebic_evaluate_batched(jobs: Sequence[Job], stream=None) -> None:
     views = (ebic_job * len(jobs))(*[j.view() for j in jobs])
     _check(lib().ebic_evaluate_batched(views, len(jobs), _stream(stream)))
+
+
+@dataclasses.dataclass
+class Bicluster:
+    rows: np.ndarray      # int64, ascending
+    cols: np.ndarray      # int64, series order
+    score: float
+
+    @property
+    def n(self) -> int:
+        return int(self.rows.size)
+
+
+@dataclasses.dataclass
+class RunResult:
+    biclusters: List[Bicluster]
+    generations: int
+    evaluations: int
+    tabu_hits: int
+    stop_reason: int
+    trace: np.ndarray     # generations x 4
+
+
+def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None) -> RunResult:
+    """The whole method on a host float32 matrix (synchronous)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    R, C = x.shape
+    res = ctypes.POINTER(ebic_result)()
+    _check(lib().ebic_run(x.ctypes.data, R, C, ctypes.byref(params), ctypes.c_uint64(seed),
+                          _stream(stream), ctypes.byref(res)))
+    try:
+        r = res.contents
+        bcs = []
+        for j in range(r.count):
+            b = r.biclusters[j]
+            rows = np.ctypeslib.as_array(b.rows, (b.n_rows,)).astype(np.int64) if b.n_rows \
+                else np.zeros(0, np.int64)
+            cols = np.ctypeslib.as_array(b.cols, (b.n_cols,)).astype(np.int64)
+            bcs.append(Bicluster(rows.copy(), cols.copy(), float(b.score)))
+        g = r.generations
+        trace = np.ctypeslib.as_array(r.trace, (g * 4,)).reshape(g, 4).copy() if g else \
+            np.zeros((0, 4))
+        return RunResult(bcs, g, int(r.evaluations), int(r.tabu_hits), int(r.stop_reason), trace)
+    finally:
+        lib().ebic_result_free(res)
 
 
 def ebic_support_rows(support: torch.Tensor, sel: Sequence[int], counts: Sequence[int],

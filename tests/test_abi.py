@@ -76,3 +76,17 @@ def test_evaluate_rejects_bad_arguments_on_host():
     bad_p = ebic.make_params(approx_permille=1001)
     assert L.ebic_evaluate(ctypes.byref(m), ctypes.byref(pop), ctypes.byref(arch0),
                            ctypes.byref(bad_p), ctypes.byref(out), None) == ebic.EBIC_ERR_INVALID_ARG
+
+
+def test_run_rejects_bad_parameters_on_host():
+    import numpy as np
+    from paper_2105_01196_amd import ebic
+    L = ebic.lib()
+    X = np.zeros((10, 5), np.float32)
+    res = ctypes.POINTER(ebic.ebic_result)()
+    for bad in (dict(k_min=1), dict(k_max=6), dict(k_min=4, k_max=3), dict(population=0),
+                dict(archive_size=65), dict(tournament=0), dict(max_tabu_hits=0),
+                dict(generations=0), dict(approx_permille=-1)):
+        p = ebic.make_params(**{**dict(k_min=2, k_max=4), **bad})
+        rc = L.ebic_run(X.ctypes.data, 10, 5, ctypes.byref(p), 1, None, ctypes.byref(res))
+        assert rc == ebic.EBIC_ERR_INVALID_ARG, bad
