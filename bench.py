@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--overlap", action="store_true",
                     help="also write each individual's per-member overlap counts (the "
                          "penalty itself never needs this output)")
+    ap.add_argument("--serving", type=int, default=0, metavar="JOBS",
+                    help="instead of the evaluation step, run the job-server mix: JOBS jobs "
+                         "with Poisson arrivals, and print its own JSON line")
+    ap.add_argument("--serving-gens", type=int, default=30)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of rocprofv3) and exit")
@@ -92,6 +96,9 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.gpus == 1 and args.serving:
+        serving(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the evaluation path "
@@ -212,6 +219,80 @@ def main():
         line["cpu_baseline"] = cpu_baseline(case.X, pops_seqs[0])
     print(json.dumps(line), flush=True)
     batch.close()
+
+
+def serving(args):
+    """Job-server mix: jobs on matrices of 500-50,000 rows x 20-2,000 columns
+    (log-uniform, log-normal background, 1-20 planted biclusters each),
+    populations of 256-4,096, arriving as a Poisson process whose mean gap is
+    a quarter of one median job's time alone. Reports the server's throughput
+    and p50/p99 job latency, and the same jobs run one after another."""
+    import torch
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_2105_01196_amd import ebic as E
+
+    specs = synth.serving_jobs(args.serving)
+    t0 = time.perf_counter()
+    mats = [synth.job_matrix(s).X for s in specs]
+    gen_s = time.perf_counter() - t0
+
+    def params(s):
+        return E.make_params(approx_permille=850, negative_trends=1, overlap_permille=750,
+                             min_rows=5, k_min=3, k_max=min(64, s.C), archive_size=20,
+                             n_out=20, population=s.population, generations=args.serving_gens,
+                             max_tabu_hits=10 ** 9, tournament=4, max_attempts=1000)
+
+    sizes = [s.R * s.C * s.population for s in specs]
+    med = int(np.argsort(sizes)[len(sizes) // 2])
+    E.ebic_run(mats[med], params(specs[med]), specs[med].seed)  # warm-up
+    t = time.perf_counter()
+    E.ebic_run(mats[med], params(specs[med]), specs[med].seed)
+    t_one = time.perf_counter() - t
+    arrivals = synth.poisson_arrivals(len(specs), t_one / 4)
+
+    srv = E.Server()
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    ids = []
+    for s, X, at in zip(specs, mats, arrivals):
+        delay = at - (time.perf_counter() - start)
+        if delay > 0:
+            time.sleep(delay)
+        ids.append(srv.submit(X, params(s), s.seed))
+    results = [srv.wait(i) for i in ids]
+    wall = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    evals = sum(r.evaluations for r in results)
+
+    # the same jobs, one after another, each through ebic_run
+    t = time.perf_counter()
+    same = True
+    for s, X, r in zip(specs, mats, results):
+        a = E.ebic_run(X, params(s), s.seed)
+        same &= (a.generations == r.generations and np.array_equal(a.trace, r.trace)
+                 and all(np.array_equal(x.rows, y.rows) and np.array_equal(x.cols, y.cols)
+                         for x, y in zip(a.biclusters, r.biclusters)))
+    seq = time.perf_counter() - t
+    line = {
+        "metric": "job-server individual evaluations/s and p50/p99 job latency",
+        "value": evals / wall, "unit": "individual evaluations/s", "n_gpus": 1,
+        "higher_is_better": True, "data": "synthetic", "dtype": "u32",
+        "config": {"workload": "serving-mix", "jobs": len(specs),
+                   "rows": [min(s.R for s in specs), max(s.R for s in specs)],
+                   "cols": [min(s.C for s in specs), max(s.C for s in specs)],
+                   "populations": sorted({s.population for s in specs}),
+                   "generations": args.serving_gens, "archive": 20,
+                   "mean_gap_s": t_one / 4},
+        "wall_s": wall, "p50_latency_s": st["p50_latency_s"],
+        "p99_latency_s": st["p99_latency_s"], "mean_latency_s": st["mean_latency_s"],
+        "ticks": st["ticks"], "evaluations": evals,
+        "sequential_runs": {"wall_s": seq, "value": evals / seq},
+        "results_identical_alone_and_mixed": bool(same),
+        "matrix_generation_s": gen_s,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def cpu_baseline(X, seqs):

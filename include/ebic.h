@@ -189,6 +189,7 @@ typedef struct ebic_job {
 
 #define EBIC_BATCH_GRAPH 1   /* replay the launch as a prebuilt HIP graph */
 #define EBIC_BATCH_GATHER 2  /* ignore pair tables, use the gather form    */
+#define EBIC_BATCH_TUNE 4    /* autotune the item shape on the first run   */
 
 typedef struct ebic_batch ebic_batch;
 
@@ -204,6 +205,13 @@ typedef struct ebic_batch ebic_batch;
  * batch. Errors: EBIC_ERR_INVALID_ARG (as ebic_evaluate, per job),
  * EBIC_ERR_OOM, EBIC_ERR_DEVICE. Runs of one batch must not overlap. */
 int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_batch **out);
+/* With EBIC_BATCH_TUNE the first run times every candidate item shape
+ * (4,096-row chunks per item: 1, 2, 4; pair-bitmap loads in flight per wave:
+ * 2, 4) on the batch's own inputs, waits for the timings (that run is
+ * synchronous), keeps the fastest, and caches the choice per shape in the
+ * process and, when the environment variable EBIC_TUNE_CACHE names a file,
+ * in that JSON file. ebic_batch_tuning reports the shape in use. */
+int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight);
 int ebic_batch_run(ebic_batch *b, void *stream);
 int ebic_batch_destroy(ebic_batch *b);
 
@@ -264,6 +272,54 @@ typedef struct ebic_result {
 int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
              void *stream, ebic_result **out);
 void ebic_result_free(ebic_result *r);
+
+/* Job server: continuous batching of many runs of the method (each as in
+ * ebic_run) on one GPU. A scheduler thread admits submitted jobs in arrival
+ * order while their device footprint (matrix, ranks, pair table when it
+ * takes at most an eighth of the budget, population, outputs, archive) fits
+ * in the HBM budget and a slot is free; every admitted job keeps its state
+ * resident on the device; each scheduler tick scores the current populations
+ * of all active jobs in one batched launch, then runs their host steps. A
+ * finished job frees its memory and slot, and queued jobs are admitted at
+ * the next tick. Each job's result is identical to ebic_run with the same
+ * matrix, parameters and seed. */
+typedef struct ebic_server ebic_server;
+
+typedef struct ebic_server_config {
+    size_t hbm_budget;      /* bytes of device memory jobs may hold; 0 = 80% of free */
+    int32_t max_active;     /* jobs resident at once; 0 = 64                         */
+} ebic_server_config;
+
+typedef struct ebic_server_metrics {
+    int64_t submitted, completed, failed, queued, active;
+    int64_t evaluations;        /* individuals scored by completed jobs        */
+    int64_t ticks;              /* batched launches                            */
+    double p50_latency_s;       /* submit -> result, completed jobs            */
+    double p99_latency_s;
+    double mean_latency_s;
+    double busy_s;              /* time with at least one active job           */
+    size_t hbm_in_use, hbm_budget;
+} ebic_server_metrics;
+
+/* Creates the server on the current device; the scheduler thread uses a
+ * stream of its own. Errors: EBIC_ERR_INVALID_ARG, EBIC_ERR_DEVICE. */
+int ebic_server_create(const ebic_server_config *cfg, ebic_server **out);
+/* Queues a job (the host matrix is copied; parameters validated as for
+ * ebic_run); never waits for the GPU. *job_id identifies it. Errors:
+ * EBIC_ERR_INVALID_ARG. A job whose footprint exceeds the whole budget fails
+ * with EBIC_ERR_CAPACITY when the scheduler reaches it. */
+int ebic_server_submit(ebic_server *s, const float *h_x, int32_t rows, int32_t cols,
+                       const ebic_params *p, uint64_t seed, int64_t *job_id);
+/* EBIC_PENDING while the job is queued or running; EBIC_OK with *out set
+ * (caller frees it with ebic_result_free; the job is then forgotten); or the
+ * job's error. */
+int ebic_server_poll(ebic_server *s, int64_t job_id, ebic_result **out);
+/* As poll, but blocks until the job has finished. */
+int ebic_server_wait(ebic_server *s, int64_t job_id, ebic_result **out);
+int ebic_server_stats(ebic_server *s, ebic_server_metrics *out);
+/* Finishes the active jobs, fails the queued ones, joins the scheduler and
+ * frees everything (unclaimed results included). */
+int ebic_server_destroy(ebic_server *s);
 
 /* Support compaction (Sec. 2.4, step 9: the trend-preserving rows' indices of
  * the top-rank list). For each of n_sel selected individuals sel[i] of a

@@ -13,8 +13,13 @@
 // words into the count, the rows shared with each archive member, and the
 // FP64 fitness. The paper sends the whole population to the GPU at once
 // (Sec. 2.4, step 2); here several populations share the launch.
+#include <algorithm>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "device.h"
@@ -52,9 +57,6 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
 constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
-#ifndef EBIC_KBATCH
-#define EBIC_KBATCH 2
-#endif
 #ifndef EBIC_THERMO_MAX
 #define EBIC_THERMO_MAX 8
 #endif
@@ -66,7 +68,8 @@ constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
 #else
 #define EBIC_COUNTER_FN __device__ __noinline__
 #endif
-constexpr int kBatch = EBIC_KBATCH;  // pair-bitmap loads in flight per wave
+// pair-bitmap loads in flight per wave: a template parameter KB (2 or 4),
+// picked per batch by the autotuner
 constexpr int kSupRegs = 8;      // support words kept in registers (64 x 8 words)
 constexpr int kMembCols = 2048;  // widest matrix whose member masks fit in LDS
 
@@ -81,7 +84,7 @@ __device__ inline int find_job(const int64_t *__restrict__ begins, int njobs, in
 // Thermometer counters of steps against the increasing trend (D) and against
 // the decreasing trend (U), T = t+1 planes each, over the 64 rows of this
 // lane's word; returns the fit word.
-template <int T, bool NEG>
+template <int T, bool NEG, int KB>
 EBIC_COUNTER_FN uint64_t pairs_thermo(const uint64_t *__restrict__ pairs, int64_t w64,
                                       const int32_t *s_pd, int k, int w, bool active) {
     uint64_t D[T], U[T];
@@ -89,10 +92,10 @@ EBIC_COUNTER_FN uint64_t pairs_thermo(const uint64_t *__restrict__ pairs, int64_
     for (int m = 0; m < T; m++) D[m] = U[m] = 0;
     int j = 1;
     while (j < k) {
-        const int n = (k - j) < kBatch ? (k - j) : kBatch;
-        uint64_t x[kBatch];
+        const int n = (k - j) < KB ? (k - j) : KB;
+        uint64_t x[KB];
 #pragma unroll
-        for (int q = 0; q < kBatch; q++) {
+        for (int q = 0; q < KB; q++) {
             x[q] = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
@@ -102,7 +105,7 @@ EBIC_COUNTER_FN uint64_t pairs_thermo(const uint64_t *__restrict__ pairs, int64_
             }
         }
 #pragma unroll
-        for (int q = 0; q < kBatch; q++) {
+        for (int q = 0; q < KB; q++) {
             if (q < n) {  // uniform; no break, so the loop unrolls fully
                 const uint64_t up = x[q], down = ~x[q];
 #pragma unroll
@@ -141,7 +144,7 @@ __device__ __forceinline__ void cmp_const(const uint64_t *b, int c, uint64_t *lt
 // Exact bit-sliced count of up-steps (9 planes, k <= 512) for larger
 // tolerances; returns the fit word. Early exit once every row has more than
 // t steps against each trend (ups > t and downs = steps - ups > t).
-template <bool NEG>
+template <bool NEG, int KB>
 EBIC_COUNTER_FN uint64_t pairs_binary(const uint64_t *__restrict__ pairs, int64_t w64,
                                       const int32_t *s_pd, int k, int t, int w, bool active) {
     uint64_t b[9];
@@ -149,10 +152,10 @@ EBIC_COUNTER_FN uint64_t pairs_binary(const uint64_t *__restrict__ pairs, int64_
     for (int p = 0; p < 9; p++) b[p] = 0;
     int j = 1;
     while (j < k) {
-        const int n = (k - j) < kBatch ? (k - j) : kBatch;
-        uint64_t x[kBatch];
+        const int n = (k - j) < KB ? (k - j) : KB;
+        uint64_t x[KB];
 #pragma unroll
-        for (int q = 0; q < kBatch; q++) {
+        for (int q = 0; q < KB; q++) {
             x[q] = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
@@ -162,7 +165,7 @@ EBIC_COUNTER_FN uint64_t pairs_binary(const uint64_t *__restrict__ pairs, int64_
             }
         }
 #pragma unroll
-        for (int q = 0; q < kBatch; q++) {
+        for (int q = 0; q < KB; q++) {
             if (q < n) {
                 uint64_t carry = x[q];
 #pragma unroll
@@ -197,13 +200,13 @@ EBIC_COUNTER_FN uint64_t pairs_binary(const uint64_t *__restrict__ pairs, int64_
     return fit;
 }
 
-template <bool NEG>
+template <bool NEG, int KB>
 __device__ __forceinline__ uint64_t pairs_dispatch(const uint64_t *pairs, int64_t w64,
                                                    const int32_t *s_pd, int k, int t, int w,
                                                    bool active) {
     switch (t) {
 #define EBIC_T(TT) \
-    case TT - 1: return pairs_thermo<TT, NEG>(pairs, w64, s_pd, k, w, active);
+    case TT - 1: return pairs_thermo<TT, NEG, KB>(pairs, w64, s_pd, k, w, active);
         EBIC_T(1) EBIC_T(2) EBIC_T(3) EBIC_T(4)
 #if EBIC_THERMO_MAX > 4
         EBIC_T(5) EBIC_T(6) EBIC_T(7) EBIC_T(8)
@@ -215,10 +218,11 @@ __device__ __forceinline__ uint64_t pairs_dispatch(const uint64_t *pairs, int64_
         EBIC_T(13) EBIC_T(14) EBIC_T(15) EBIC_T(16)
 #endif
 #undef EBIC_T
-        default: return pairs_binary<NEG>(pairs, w64, s_pd, k, t, w, active);
+        default: return pairs_binary<NEG, KB>(pairs, w64, s_pd, k, t, w, active);
     }
 }
 
+template <int KB>
 __global__ void __launch_bounds__(kThreads)
     eval_items_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ item_begins,
                       int32_t njobs, int64_t total_items) {
@@ -271,8 +275,8 @@ __global__ void __launch_bounds__(kThreads)
         const int w = chunk * 64 + lane;  // this lane's 64-row word
         if (J.mode == 1) {
             const bool active = w < J.w64;
-            uint64_t fit = neg ? pairs_dispatch<true>(J.pairs, J.w64, s, k, t, w, active)
-                               : pairs_dispatch<false>(J.pairs, J.w64, s, k, t, w, active);
+            uint64_t fit = neg ? pairs_dispatch<true, KB>(J.pairs, J.w64, s, k, t, w, active)
+                               : pairs_dispatch<false, KB>(J.pairs, J.w64, s, k, t, w, active);
             const int r0 = w * 64;
             if (r0 + 64 > J.rows) fit &= r0 >= J.rows ? 0ull : ((1ull << (J.rows - r0)) - 1ull);
             if (active) J.support[(int64_t)ind * J.w64 + w] = fit;
@@ -456,21 +460,26 @@ __global__ void __launch_bounds__(kThreads)
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Host side: the batch object.
+// Host side: the batch object and its autotuner.
 // ---------------------------------------------------------------------------
 
 struct Batch {
     int device = 0;
+    int32_t flags = 0;
     std::vector<DevJob> jobs;
-    DevJob *d_jobs = nullptr;       // device: DevJob[njobs], then the two begin arrays
+    DevJob *d_jobs = nullptr;  // device: DevJob[njobs], then the two start arrays
     int64_t *d_item_begins = nullptr;
     int64_t *d_ind_begins = nullptr;
+    int32_t cap_jobs = 0;      // capacity of d_jobs / h_stage
+    void *h_stage = nullptr;   // pinned staging of the table
     std::vector<void *> scratch;
     int64_t total_items = 0, total_ind = 0;
+    int32_t njobs = 0;         // kept alive: the graph's kernel arguments
+    int kb = 2;                // pair-bitmap loads in flight (template)
+    int cpi = 1;               // chunks per item
+    bool tuned = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // kernel arguments kept alive for the graph's nodes
-    int32_t njobs = 0;
     // timing: three events per profiled run (start, between, end)
     std::vector<hipEvent_t> events;
     int32_t prof_cap = 0, prof_used = 0;
@@ -478,16 +487,13 @@ struct Batch {
 
 namespace {
 
-// Chunks per item: one wave walks them in turn, paying the series set-up
-// once. EBIC_CHUNKS_PER_ITEM overrides the default (for tuning).
-int chunks_per_item(int nchunks) {
+// Default chunks per item; EBIC_CHUNKS_PER_ITEM overrides it.
+int default_cpi() {
     static const int forced = [] {
         const char *v = getenv("EBIC_CHUNKS_PER_ITEM");
         return v ? atoi(v) : 0;
     }();
-    int c = forced > 0 ? forced : 1;
-    if (c > nchunks) c = nchunks;
-    return c < 1 ? 1 : c;
+    return forced > 0 ? forced : 1;
 }
 
 int check_job(const ebic_job *j, int idx) {
@@ -510,7 +516,269 @@ int check_job(const ebic_job *j, int idx) {
     return EBIC_OK;
 }
 
+DevJob make_devjob(const ebic_job &j, int32_t flags) {
+    DevJob d{};
+    d.ranks = j.matrix.d_ranks;
+    d.pairs = j.matrix.d_pairs;
+    d.rows = j.matrix.rows;
+    d.cols = j.matrix.cols;
+    d.rows_pad = j.matrix.rows_pad;
+    d.w32 = j.matrix.rows_pad / 32;
+    d.w64 = j.matrix.rows_pad / 64;
+    d.mode = (j.matrix.d_pairs && !(flags & EBIC_BATCH_GATHER)) ? 1 : 0;
+    d.nchunks = (j.matrix.rows_pad + kItemRows - 1) / kItemRows;
+    d.pop_size = j.population.size;
+    d.pop_len = j.population.length;
+    d.pop_off = j.population.d_offsets;
+    d.pop_cols = j.population.d_cols;
+    d.order = j.population.d_order;
+    d.arch_size = j.archive.size;
+    d.arch_len = j.archive.length;
+    d.arch_support = j.archive.d_support;
+    d.arch_off = j.archive.d_offsets;
+    d.arch_cols = j.archive.d_cols;
+    d.approx_permille = j.params.approx_permille;
+    d.negative_trends = j.params.negative_trends;
+    d.overlap_permille = j.params.overlap_permille;
+    d.min_rows = j.params.min_rows;
+    d.k_score_min = j.params.k_score_min;
+    d.fitness = j.out.d_fitness;
+    d.count = j.out.d_count;
+    d.support = j.out.d_support;
+    d.overlap = j.out.d_overlap;
+    return d;
+}
+
+// Lay the items out for `cpi` chunks per item (item starts of every job)
+// and queue the table's upload on `stream` from pinned staging, growing the
+// device table when needed.
+int upload_table(Batch *b, int cpi, hipStream_t stream) {
+    b->cpi = cpi;
+    int64_t items = 0, inds = 0;
+    for (DevJob &d : b->jobs) {
+        d.cpi = cpi < d.nchunks ? cpi : d.nchunks;
+        if (d.cpi < 1) d.cpi = 1;
+        d.ipi = (d.nchunks + d.cpi - 1) / d.cpi;
+        d.item_begin = items;
+        d.ind_begin = inds;
+        items += (int64_t)d.pop_size * d.ipi;
+        inds += d.pop_size;
+    }
+    b->total_items = items;
+    b->total_ind = inds;
+    const int32_t n = b->njobs;
+    const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 2 * n;
+    if (n > b->cap_jobs) {
+        if (b->d_jobs) (void)hipFree(b->d_jobs);
+        if (b->h_stage) (void)hipHostFree(b->h_stage);
+        b->d_jobs = nullptr;
+        b->h_stage = nullptr;
+        b->cap_jobs = 0;
+        void *mem = nullptr;
+        EBIC_HIP(hipMalloc(&mem, bytes));
+        b->d_jobs = static_cast<DevJob *>(mem);
+        EBIC_HIP(hipHostMalloc(&b->h_stage, bytes, hipHostMallocDefault));
+        b->cap_jobs = n;
+    }
+    b->d_item_begins = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) + jbytes);
+    b->d_ind_begins = b->d_item_begins + n;
+    char *h = static_cast<char *>(b->h_stage);
+    std::memcpy(h, b->jobs.data(), jbytes);
+    int64_t *hb = reinterpret_cast<int64_t *>(h + jbytes);
+    for (int i = 0; i < n; i++) {
+        hb[i] = b->jobs[i].item_begin;
+        hb[n + i] = b->jobs[i].ind_begin;
+    }
+    EBIC_HIP(hipMemcpyAsync(b->d_jobs, h, bytes, hipMemcpyHostToDevice, stream));
+    return EBIC_OK;
+}
+
+void *eval_kernel_fn(int kb) {
+    return kb == 4 ? reinterpret_cast<void *>(eval_items_kernel<4>)
+                   : reinterpret_cast<void *>(eval_items_kernel<2>);
+}
+
+int launch_eval(Batch *b, hipStream_t stream) {
+    if (b->total_items == 0) return EBIC_OK;
+    const unsigned grid = (unsigned)((b->total_items + kWaves - 1) / kWaves);
+    if (b->kb == 4)
+        eval_items_kernel<4><<<grid, kThreads, 0, stream>>>(b->d_jobs, b->d_item_begins,
+                                                            b->njobs, b->total_items);
+    else
+        eval_items_kernel<2><<<grid, kThreads, 0, stream>>>(b->d_jobs, b->d_item_begins,
+                                                            b->njobs, b->total_items);
+    EBIC_HIP(hipGetLastError());
+    return EBIC_OK;
+}
+
+int build_graph(Batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    // two kernel nodes, evaluation then reduction (no stream capture)
+    hipGraphNode_t na = nullptr, nb = nullptr;
+    void *args_a[] = {&b->d_jobs, &b->d_item_begins, &b->njobs, &b->total_items};
+    void *args_b[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
+    hipKernelNodeParams pa{}, pb{};
+    pa.func = eval_kernel_fn(b->kb);
+    pa.gridDim = dim3((unsigned)((b->total_items + kWaves - 1) / kWaves));
+    pa.blockDim = dim3(kThreads);
+    pa.kernelParams = args_a;
+    pb.func = reinterpret_cast<void *>(epilogue_kernel);
+    pb.gridDim = dim3((unsigned)((b->total_ind + kWaves - 1) / kWaves));
+    pb.blockDim = dim3(kThreads);
+    pb.kernelParams = args_b;
+    hipError_t e = hipGraphCreate(&b->graph, 0);
+    if (e == hipSuccess && b->total_items > 0)
+        e = hipGraphAddKernelNode(&na, b->graph, nullptr, 0, &pa);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&nb, b->graph, na ? &na : nullptr, na ? 1 : 0,
+                                                   &pb);
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return check_hip(e, "batch graph");
+    return EBIC_OK;
+}
+
+// ---- autotuner: chunks per item x loads in flight, cached per shape ----
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+const char *tune_file() { return getenv("EBIC_TUNE_CACHE"); }
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = tune_file();
+    if (!path) return;
+    FILE *f = fopen(path, "r");
+    if (!f) return;
+    char key[256];
+    int a = 0, c = 0;
+    // entries look like  "key": [cpi, kb]
+    while (fscanf(f, " \"%255[^\"]\" : [ %d , %d ]", key, &a, &c) == 3) {
+        g_tune[key] = {a, c};
+        int ch;
+        while ((ch = fgetc(f)) != EOF && ch != ',' && ch != '}') {
+        }
+        if (ch != ',') break;
+    }
+    fclose(f);
+}
+
+void tune_save_locked() {
+    const char *path = tune_file();
+    if (!path) return;
+    FILE *f = fopen(path, "w");
+    if (!f) return;
+    fprintf(f, "{");
+    bool first = true;
+    for (auto &kv : g_tune) {
+        fprintf(f, "%s\n \"%s\": [%d, %d]", first ? "" : ",", kv.first.c_str(), kv.second.first,
+                kv.second.second);
+        first = false;
+    }
+    fprintf(f, "\n}\n");
+    fclose(f);
+}
+
+std::string tune_key(const Batch *b) {
+    int32_t w = 0, mode = 0;
+    for (const DevJob &d : b->jobs) {
+        w = d.w64 > w ? d.w64 : w;
+        mode |= 1 << d.mode;
+    }
+    char buf[128];
+    snprintf(buf, sizeof buf, "m%d_w%d_i%lld_j%d", mode, w, (long long)b->total_ind, b->njobs);
+    return buf;
+}
+
+// Time every (chunks per item, loads in flight) candidate on this batch's
+// inputs with HIP events around the evaluation kernel (median of 3) and keep
+// the fastest. Results never depend on the choice.
+int tune(Batch *b, hipStream_t stream) {
+    b->tuned = true;
+    const std::string key = tune_key(b);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            b->kb = it->second.second;
+            return upload_table(b, it->second.first, stream);
+        }
+    }
+    int32_t maxch = 1;
+    for (const DevJob &d : b->jobs) maxch = d.nchunks > maxch ? d.nchunks : maxch;
+    hipEvent_t e0, e1;
+    EBIC_HIP(hipEventCreate(&e0));
+    EBIC_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int best_cpi = 1, best_kb = 2;
+    int rc = EBIC_OK;
+    for (int cpi : {1, 2, 4}) {
+        if (cpi > 1 && cpi > maxch) break;
+        for (int kb : {2, 4}) {
+            b->kb = kb;
+            rc = upload_table(b, cpi, stream);
+            if (rc == EBIC_OK) rc = launch_eval(b, stream);  // warm-up
+            float t[3];
+            for (int r = 0; r < 3 && rc == EBIC_OK; r++) {
+                (void)hipEventRecord(e0, stream);
+                rc = launch_eval(b, stream);
+                (void)hipEventRecord(e1, stream);
+                (void)hipEventSynchronize(e1);
+                (void)hipEventElapsedTime(&t[r], e0, e1);
+            }
+            if (rc) break;
+            std::sort(t, t + 3);
+            if (t[1] < best) {
+                best = t[1];
+                best_cpi = cpi;
+                best_kb = kb;
+            }
+        }
+        if (rc) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[key] = {best_cpi, best_kb};
+        tune_save_locked();
+    }
+    b->kb = best_kb;
+    return upload_table(b, best_cpi, stream);
+}
+
 }  // namespace
+
+// Re-target a batch at a new set of jobs (every job must bring its support
+// output): the job table and the start arrays go to the device with one
+// asynchronous copy on `stream` from pinned staging, reusing the device
+// table when it is large enough. Creates the batch when *bp is NULL.
+int batch_set(Batch **bp, const ebic_job *jobs, int32_t njobs, hipStream_t stream) {
+    if (!bp || njobs < 1 || !jobs) return fail(EBIC_ERR_INVALID_ARG, "no jobs");
+    for (int i = 0; i < njobs; i++) {
+        int rc = check_job(&jobs[i], i);
+        if (rc) return rc;
+        if (jobs[i].population.size > 0 && !jobs[i].out.d_support)
+            return fail(EBIC_ERR_INVALID_ARG, "job %d: support output required", i);
+    }
+    Batch *b = *bp;
+    if (!b) {
+        b = new Batch();
+        EBIC_HIP(hipGetDevice(&b->device));
+        b->cpi = default_cpi();
+        *bp = b;
+    }
+    b->jobs.clear();
+    for (int i = 0; i < njobs; i++) b->jobs.push_back(make_devjob(jobs[i], 0));
+    b->njobs = njobs;
+    return upload_table(b, b->cpi, stream);
+}
 
 int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out) {
     if (!out || njobs < 1 || !jobs) return fail(EBIC_ERR_INVALID_ARG, "no jobs");
@@ -519,47 +787,19 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
         if (rc) return rc;
     }
     Batch *b = new Batch();
-    EBIC_HIP(hipGetDevice(&b->device));
+    b->flags = flags;
+    b->cpi = default_cpi();
+    hipError_t e = hipGetDevice(&b->device);
+    if (e != hipSuccess) {
+        delete b;
+        return check_hip(e, "hipGetDevice");
+    }
     b->njobs = njobs;
-    int64_t items = 0, inds = 0;
     for (int i = 0; i < njobs; i++) {
-        const ebic_job &j = jobs[i];
-        DevJob d{};
-        d.ranks = j.matrix.d_ranks;
-        d.pairs = j.matrix.d_pairs;
-        d.rows = j.matrix.rows;
-        d.cols = j.matrix.cols;
-        d.rows_pad = j.matrix.rows_pad;
-        d.w32 = j.matrix.rows_pad / 32;
-        d.w64 = j.matrix.rows_pad / 64;
-        d.mode = (j.matrix.d_pairs && !(flags & EBIC_BATCH_GATHER)) ? 1 : 0;
-        d.nchunks = (j.matrix.rows_pad + kItemRows - 1) / kItemRows;
-        d.cpi = chunks_per_item(d.nchunks);
-        d.ipi = (d.nchunks + d.cpi - 1) / d.cpi;
-        d.pop_size = j.population.size;
-        d.pop_len = j.population.length;
-        d.pop_off = j.population.d_offsets;
-        d.pop_cols = j.population.d_cols;
-        d.order = j.population.d_order;
-        d.item_begin = items;
-        d.ind_begin = inds;
-        d.arch_size = j.archive.size;
-        d.arch_len = j.archive.length;
-        d.arch_support = j.archive.d_support;
-        d.arch_off = j.archive.d_offsets;
-        d.arch_cols = j.archive.d_cols;
-        d.approx_permille = j.params.approx_permille;
-        d.negative_trends = j.params.negative_trends;
-        d.overlap_permille = j.params.overlap_permille;
-        d.min_rows = j.params.min_rows;
-        d.k_score_min = j.params.k_score_min;
-        d.fitness = j.out.d_fitness;
-        d.count = j.out.d_count;
-        d.support = j.out.d_support;
-        d.overlap = j.out.d_overlap;
+        DevJob d = make_devjob(jobs[i], flags);
         if (!d.support && d.pop_size > 0) {
             void *p = nullptr;
-            hipError_t e = hipMalloc(&p, (size_t)d.pop_size * d.w64 * sizeof(uint64_t));
+            e = hipMalloc(&p, (size_t)d.pop_size * d.w64 * sizeof(uint64_t));
             if (e != hipSuccess) {
                 batch_destroy(b);
                 return check_hip(e, "hipMalloc(support scratch)");
@@ -567,57 +807,16 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
             b->scratch.push_back(p);
             d.support = static_cast<uint64_t *>(p);
         }
-        items += (int64_t)d.pop_size * d.ipi;
-        inds += d.pop_size;
         b->jobs.push_back(d);
     }
-    b->total_items = items;
-    b->total_ind = inds;
-    std::vector<int64_t> begins(2 * (size_t)njobs);
-    for (int i = 0; i < njobs; i++) {
-        begins[i] = b->jobs[i].item_begin;
-        begins[njobs + i] = b->jobs[i].ind_begin;
+    int rc = upload_table(b, b->cpi, nullptr);
+    if (rc == EBIC_OK) {
+        e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) rc = check_hip(e, "batch job table");
     }
-    void *mem = nullptr;
-    const size_t jbytes = sizeof(DevJob) * njobs;
-    hipError_t e = hipMalloc(&mem, jbytes + sizeof(int64_t) * begins.size());
-    if (e == hipSuccess) {
-        b->d_jobs = static_cast<DevJob *>(mem);
-        b->d_item_begins = reinterpret_cast<int64_t *>(static_cast<char *>(mem) + jbytes);
-        b->d_ind_begins = b->d_item_begins + njobs;
-        e = hipMemcpy(b->d_jobs, b->jobs.data(), jbytes, hipMemcpyHostToDevice);
-    }
-    if (e == hipSuccess)
-        e = hipMemcpy(b->d_item_begins, begins.data(), sizeof(int64_t) * begins.size(),
-                      hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
+    if (rc) {
         batch_destroy(b);
-        return check_hip(e, "batch job table");
-    }
-    if ((flags & EBIC_BATCH_GRAPH) && b->total_ind > 0) {
-        // Two kernel nodes, A then B, built explicitly (no stream capture).
-        int rc = EBIC_OK;
-        hipGraphNode_t na = nullptr, nb = nullptr;
-        void *args_a[] = {&b->d_jobs, &b->d_item_begins, &b->njobs, &b->total_items};
-        void *args_b[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
-        hipKernelNodeParams pa{}, pb{};
-        pa.func = reinterpret_cast<void *>(eval_items_kernel);
-        pa.gridDim = dim3((unsigned)((b->total_items + kWaves - 1) / kWaves));
-        pa.blockDim = dim3(kThreads);
-        pa.kernelParams = args_a;
-        pb.func = reinterpret_cast<void *>(epilogue_kernel);
-        pb.gridDim = dim3((unsigned)((b->total_ind + kWaves - 1) / kWaves));
-        pb.blockDim = dim3(kThreads);
-        pb.kernelParams = args_b;
-        e = hipGraphCreate(&b->graph, 0);
-        if (e == hipSuccess) e = hipGraphAddKernelNode(&na, b->graph, nullptr, 0, &pa);
-        if (e == hipSuccess) e = hipGraphAddKernelNode(&nb, b->graph, &na, 1, &pb);
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            rc = check_hip(e, "batch graph");
-            batch_destroy(b);
-            return rc;
-        }
+        return rc;
     }
     *out = b;
     return EBIC_OK;
@@ -626,6 +825,15 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
 int batch_run(Batch *b, hipStream_t stream) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (b->total_ind == 0) return EBIC_OK;
+    if ((b->flags & EBIC_BATCH_TUNE) && !b->tuned) {
+        int rc = tune(b, stream);
+        if (rc) return rc;
+    }
+    if ((b->flags & EBIC_BATCH_GRAPH) && !b->exec) {
+        EBIC_HIP(hipStreamSynchronize(stream));  // the table upload must land first
+        int rc = build_graph(b);
+        if (rc) return rc;
+    }
     hipEvent_t *ev = nullptr;
     if (b->prof_used < b->prof_cap) ev = &b->events[3 * b->prof_used++];
     if (ev) EBIC_HIP(hipEventRecord(ev[0], stream));
@@ -637,14 +845,20 @@ int batch_run(Batch *b, hipStream_t stream) {
         }
         return EBIC_OK;
     }
-    if (b->total_items > 0)
-        eval_items_kernel<<<(unsigned)((b->total_items + kWaves - 1) / kWaves), kThreads, 0,
-                            stream>>>(b->d_jobs, b->d_item_begins, b->njobs, b->total_items);
+    int rc = launch_eval(b, stream);
+    if (rc) return rc;
     if (ev) EBIC_HIP(hipEventRecord(ev[1], stream));
     epilogue_kernel<<<(unsigned)((b->total_ind + kWaves - 1) / kWaves), kThreads, 0, stream>>>(
         b->d_jobs, b->d_ind_begins, b->njobs, b->total_ind);
     if (ev) EBIC_HIP(hipEventRecord(ev[2], stream));
     EBIC_HIP(hipGetLastError());
+    return EBIC_OK;
+}
+
+int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb) {
+    if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
+    if (cpi) *cpi = b->cpi;
+    if (kb) *kb = b->kb;
     return EBIC_OK;
 }
 
@@ -681,6 +895,7 @@ int batch_destroy(Batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->h_stage) (void)hipHostFree(b->h_stage);
     for (void *p : b->scratch) (void)hipFree(p);
     delete b;
     return EBIC_OK;

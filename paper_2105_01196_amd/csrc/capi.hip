@@ -226,6 +226,11 @@ int ebic_batch_destroy(ebic_batch *b) {
     return batch_destroy(reinterpret_cast<Batch *>(b));
 }
 
+int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight) {
+    clear_error();
+    return batch_tuning(reinterpret_cast<Batch *>(b), chunks_per_item, loads_in_flight);
+}
+
 int ebic_batch_profile(ebic_batch *b, int32_t n) {
     clear_error();
     return batch_profile(reinterpret_cast<Batch *>(b), n);
@@ -259,6 +264,48 @@ int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
 
 void ebic_result_free(ebic_result *r) {
     if (r) free_result(r);
+}
+
+int ebic_server_create(const ebic_server_config *cfg, ebic_server **out) {
+    clear_error();
+    if (!out) return fail(EBIC_ERR_INVALID_ARG, "out is NULL");
+    Server *s = nullptr;
+    int rc = server_create(cfg, &s);
+    if (rc) return rc;
+    *out = reinterpret_cast<ebic_server *>(s);
+    return EBIC_OK;
+}
+
+int ebic_server_submit(ebic_server *s, const float *h_x, int32_t rows, int32_t cols,
+                       const ebic_params *p, uint64_t seed, int64_t *job_id) {
+    clear_error();
+    if (!s) return fail(EBIC_ERR_INVALID_ARG, "server is NULL");
+    return server_submit(reinterpret_cast<Server *>(s), h_x, rows, cols, p, seed, job_id);
+}
+
+int ebic_server_poll(ebic_server *s, int64_t job_id, ebic_result **out) {
+    clear_error();
+    if (!s) return fail(EBIC_ERR_INVALID_ARG, "server is NULL");
+    return server_poll(reinterpret_cast<Server *>(s), job_id, out, false);
+}
+
+int ebic_server_wait(ebic_server *s, int64_t job_id, ebic_result **out) {
+    clear_error();
+    if (!s) return fail(EBIC_ERR_INVALID_ARG, "server is NULL");
+    return server_poll(reinterpret_cast<Server *>(s), job_id, out, true);
+}
+
+int ebic_server_stats(ebic_server *s, ebic_server_metrics *out) {
+    clear_error();
+    if (!s || !out) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
+    server_stats(reinterpret_cast<Server *>(s), out);
+    return EBIC_OK;
+}
+
+int ebic_server_destroy(ebic_server *s) {
+    clear_error();
+    if (s) server_destroy(reinterpret_cast<Server *>(s));
+    return EBIC_OK;
 }
 
 int ebic_support_rows(const uint64_t *d_support, int32_t size, int32_t words,

@@ -70,9 +70,19 @@ int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *
                hipStream_t stream, ebic_result **out);
 void free_result(ebic_result *r);
 
+class Server;
+int server_create(const ebic_server_config *cfg, Server **out);
+int server_submit(Server *s, const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                  uint64_t seed, int64_t *id);
+int server_poll(Server *s, int64_t id, ebic_result **out, bool block);
+void server_stats(Server *s, ebic_server_metrics *st);
+void server_destroy(Server *s);
+
 struct Batch;
 int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out);
 int batch_run(Batch *b, hipStream_t stream);
+int batch_set(Batch **b, const ebic_job *jobs, int32_t njobs, hipStream_t stream);
+int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb);
 int batch_destroy(Batch *b);
 int batch_profile(Batch *b, int32_t n);
 int batch_timings(Batch *b, float *ms_eval, float *ms_reduce, int32_t *n);

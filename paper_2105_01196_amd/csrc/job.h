@@ -1,0 +1,191 @@
+// Per-job state of the evolutionary loop (Sec. 2.4), shared by ebic_run and
+// the job server. Internal to the library.
+#pragma once
+
+#include <algorithm>
+#include <cmath>
+#include <memory>
+#include <numeric>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.h"
+
+namespace ebic {
+
+// SplitMix64 (Steele, Lea and Flood, OOPSLA 2014).
+class SplitMix64 {
+  public:
+    explicit SplitMix64(uint64_t seed) : state_(seed) {}
+    uint64_t next() {
+        state_ += 0x9E3779B97F4A7C15ULL;
+        uint64_t z = state_;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+        return z ^ (z >> 31);
+    }
+    // Uniform in [0, n): draws below 2^64 mod n are rejected so that the
+    // accepted range holds a whole number of periods of n.
+    uint64_t below(uint64_t n) {
+        const uint64_t reject = (0 - n) % n;
+        for (;;) {
+            const uint64_t x = next();
+            if (x >= reject) return x % n;
+        }
+    }
+    int below_int(int64_t n) { return (int)below((uint64_t)n); }
+
+  private:
+    uint64_t state_;
+};
+
+using Series = std::vector<uint16_t>;
+
+struct SeriesHash {
+    size_t operator()(const Series &s) const {
+        uint64_t h = 0x84222325CBF29CE4ULL ^ s.size();
+        for (uint16_t c : s) h = (h ^ c) * 0x100000001B3ULL;
+        return (size_t)h;
+    }
+};
+
+// With negative trends a series and its reverse have the same support; the
+// smaller of the two stands for both in the tabu list and the top-rank list.
+inline Series canonical(const Series &s, bool neg) {
+    if (!neg) return s;
+    Series r(s.rbegin(), s.rend());
+    return std::lexicographical_compare(r.begin(), r.end(), s.begin(), s.end()) ? r : s;
+}
+
+// Top-rank order: larger score first, then the lexicographically smaller
+// series (a proper prefix first).
+inline bool ranks_above(double sa, const Series &a, double sb, const Series &b) {
+    if (sa != sb) return sa > sb;
+    return std::lexicographical_compare(a.begin(), a.end(), b.begin(), b.end());
+}
+
+struct Member {
+    Series s;
+    std::vector<uint64_t> support;
+    int32_t n = 0;
+    double score = 0.0;
+};
+
+struct ResultImpl {
+    ebic_result pub{};
+    std::vector<ebic_bicluster> bcs;
+    std::vector<std::vector<int32_t>> rows;
+    std::vector<Series> cols;
+    std::vector<double> trace;
+};
+
+template <typename T>
+struct DeviceArray {
+    T *p = nullptr;
+    size_t n = 0;
+    ~DeviceArray() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t count) {
+        n = count ? count : 1;
+        return hipMalloc(reinterpret_cast<void **>(&p), n * sizeof(T));
+    }
+};
+
+template <typename T>
+struct PinnedArray {
+    T *p = nullptr;
+    size_t n = 0;
+    ~PinnedArray() {
+        if (p) (void)hipHostFree(p);
+    }
+    hipError_t alloc(size_t count) {
+        n = count ? count : 1;
+        return hipHostMalloc(reinterpret_cast<void **>(&p), n * sizeof(T), hipHostMallocDefault);
+    }
+};
+
+#define RUN_HIP(call)                                     \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return check_hip(e_, #call); \
+    } while (0)
+
+class Job {
+  public:
+    Job(const ebic_params &p, uint64_t seed, hipStream_t stream)
+        : p_(p), rng_(seed), stream_(stream), neg_(p.negative_trends != 0) {}
+
+    // Device bytes a job of this shape holds (matrix, ranks, pair table when
+    // used, population, outputs, archive).
+    static size_t footprint(int32_t rows, int32_t cols, const ebic_params &p, bool pairs);
+    // Allocate, ingest the matrix, build the pair table when `pairs`.
+    int setup(const float *h_x, int32_t rows, int32_t cols, bool pairs);
+    void start();                     // step 1
+    int stage(ebic_job *job);         // upload what is to be scored next
+    int fetch();                      // queue the outputs' download
+    int advance();                    // host steps after the scores arrived
+    bool done() const { return phase_ == Phase::Done; }
+    ResultImpl *take_result() { return res_.release(); }
+    int64_t evaluations() const { return evaluations_; }
+
+  private:
+    enum class Phase { Eval, FinalEval, Done };
+    void update_archive(const std::vector<Series> &pop);
+    void next_population();
+    int finish();
+    int tournament(const std::vector<double> &key, int n);
+    int unused_column(const Series &s);
+    Series mutate(const std::vector<Series> &pop, const std::vector<double> &key);
+    double size_score(int32_t n, int k) const {
+        return (n >= p_.min_rows && k >= p_.k_score_min) ? std::ldexp((double)n, k) : 0.0;
+    }
+    int64_t shared_rows(const uint64_t *a, const uint64_t *b) const {
+        int64_t h = 0;
+        for (int w = 0; w < W_; w++) h += __builtin_popcountll(a[w] & b[w]);
+        return h;
+    }
+    static int64_t shared_cols(const Series &a, const Series &b) {
+        int64_t g = 0;
+        for (uint16_t x : a)
+            if (std::find(b.begin(), b.end(), x) != b.end()) g++;
+        return g;
+    }
+
+    ebic_params p_;
+    SplitMix64 rng_;
+    hipStream_t stream_;
+    bool neg_;
+    int32_t R_ = 0, C_ = 0, W_ = 0;
+    ebic_matrix m_{};
+    DeviceArray<float> d_x_;
+    DeviceArray<uint16_t> d_ranks_;
+    DeviceArray<uint64_t> d_pairs_;
+    DeviceArray<int32_t> d_off_, d_order_, d_cnt_, d_aoff_, d_sel_, d_roff_, d_rows_;
+    DeviceArray<uint16_t> d_cols_, d_acols_;
+    DeviceArray<double> d_fit_;
+    DeviceArray<uint64_t> d_sup_, d_asup_;
+    PinnedArray<int32_t> h_off_, h_order_, h_cnt_, h_aoff_;
+    PinnedArray<uint16_t> h_cols_, h_acols_;
+    PinnedArray<double> h_fit_;
+    PinnedArray<uint64_t> h_sup_, h_asup_;
+
+    Phase phase_ = Phase::Eval;
+    int stop_ = 0;
+    int32_t g_ = 0;
+    int64_t evaluations_ = 0;
+    std::vector<Series> pop_;   // being scored (or the final list)
+    int32_t staged_P_ = 0;
+    std::unordered_set<Series, SeriesHash> tabu_;
+    int64_t tabu_hits_ = 0;
+    std::vector<Member> archive_;
+    std::vector<double> fitness_;
+    std::vector<int32_t> count_;
+    std::vector<int32_t> use_;
+    std::vector<char> in_;  // scratch: columns of the series being mutated
+    std::unique_ptr<ResultImpl> res_{new ResultImpl()};
+};
+
+int check_run_params(int32_t rows, int32_t cols, const ebic_params *p);
+
+}  // namespace ebic

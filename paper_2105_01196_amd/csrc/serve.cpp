@@ -1,0 +1,363 @@
+// Job server: continuous batching of many runs of the method on one GPU.
+//
+// A scheduler thread owns a stream and the batch. Each tick it admits
+// queued jobs whose device footprint fits the remaining HBM budget (arrival
+// order, so a large job is never starved by smaller ones behind it), stages
+// the population of every active job, scores them all in one batched
+// launch, downloads, and runs each job's host steps. Finished jobs release
+// their device memory and slot.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+
+#include "job.h"
+
+namespace ebic {
+namespace {
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Fixed pool of host threads for the jobs' host steps (they are independent
+// across jobs); run(n, fn) calls fn(0..n-1) and returns when all are done.
+class WorkerPool {
+  public:
+    explicit WorkerPool(int n) {
+        for (int i = 0; i < n; i++) threads_.emplace_back([this] { work(); });
+    }
+    ~WorkerPool() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            quit_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : threads_) t.join();
+    }
+    void run(size_t n, const std::function<void(size_t)> &fn) {
+        if (n == 0) return;
+        std::unique_lock<std::mutex> lk(mu_);
+        fn_ = &fn;
+        next_ = 0;
+        total_ = n;
+        left_ = n;
+        cv_.notify_all();
+        done_.wait(lk, [&] { return left_ == 0; });
+        fn_ = nullptr;
+    }
+
+  private:
+    void work() {
+        std::unique_lock<std::mutex> lk(mu_);
+        for (;;) {
+            cv_.wait(lk, [&] { return quit_ || (fn_ && next_ < total_); });
+            if (quit_) return;
+            const size_t i = next_++;
+            const std::function<void(size_t)> *fn = fn_;
+            lk.unlock();
+            (*fn)(i);
+            lk.lock();
+            if (--left_ == 0) done_.notify_all();
+        }
+    }
+    std::vector<std::thread> threads_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_;
+    const std::function<void(size_t)> *fn_ = nullptr;
+    size_t next_ = 0, total_ = 0, left_ = 0;
+    bool quit_ = false;
+};
+
+struct ServerJob {
+    int64_t id = 0;
+    std::vector<float> x;
+    int32_t rows = 0, cols = 0;
+    ebic_params params{};
+    uint64_t seed = 0;
+    bool pairs = false;
+    size_t footprint = 0;
+    std::unique_ptr<Job> job;
+    double t_submit = 0, t_done = 0;
+    int status = EBIC_PENDING;
+    std::string error;
+    ResultImpl *result = nullptr;
+};
+
+}  // namespace
+
+class Server {
+  public:
+    int init(const ebic_server_config *cfg);
+    ~Server();
+    int submit(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
+               int64_t *id);
+    int poll(int64_t id, ebic_result **out, bool block);
+    void stats(ebic_server_metrics *st);
+
+  private:
+    void loop();
+    void tick(std::vector<std::shared_ptr<ServerJob>> &active);
+    void finish_job(const std::shared_ptr<ServerJob> &j, int status, const char *err);
+
+    std::mutex mu_;
+    std::condition_variable cv_work_, cv_done_;
+    std::deque<std::shared_ptr<ServerJob>> queue_;
+    std::unordered_map<int64_t, std::shared_ptr<ServerJob>> jobs_;
+    std::vector<double> latencies_;
+    int64_t next_id_ = 1, submitted_ = 0, completed_ = 0, failed_ = 0, evaluations_ = 0;
+    int64_t ticks_ = 0, n_active_ = 0;
+    double busy_s_ = 0;
+    size_t budget_ = 0, in_use_ = 0;
+    int32_t max_active_ = 64;
+    bool stop_ = false;
+    int device_ = 0;
+    hipStream_t stream_ = nullptr;
+    Batch *batch_ = nullptr;
+    std::unique_ptr<WorkerPool> pool_;
+    std::thread thread_;
+};
+
+int Server::init(const ebic_server_config *cfg) {
+    EBIC_HIP(hipGetDevice(&device_));
+    size_t free_b = 0, total_b = 0;
+    EBIC_HIP(hipMemGetInfo(&free_b, &total_b));
+    budget_ = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : free_b / 10 * 8;
+    max_active_ = (cfg && cfg->max_active > 0) ? cfg->max_active : 64;
+    EBIC_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+    const unsigned hw = std::thread::hardware_concurrency();
+    pool_.reset(new WorkerPool((int)std::max(1u, std::min(hw ? hw : 1u, 16u))));
+    thread_ = std::thread([this] { loop(); });
+    return EBIC_OK;
+}
+
+Server::~Server() {
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        stop_ = true;
+    }
+    cv_work_.notify_all();
+    if (thread_.joinable()) thread_.join();
+    pool_.reset();
+    if (batch_) batch_destroy(batch_);
+    if (stream_) (void)hipStreamDestroy(stream_);
+    for (auto &kv : jobs_) delete kv.second->result;
+}
+
+int Server::submit(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                   uint64_t seed, int64_t *id) {
+    if (!h_x || !p || !id) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
+    int rc = check_run_params(rows, cols, p);
+    if (rc) return rc;
+    if (rows > EBIC_MAX_ROWS || cols > EBIC_MAX_COLS ||
+        (int64_t)cols * rows_padded(rows) > INT32_MAX)
+        return fail(EBIC_ERR_INVALID_ARG, "matrix shape %d x %d not supported", rows, cols);
+    auto j = std::make_shared<ServerJob>();
+    j->x.assign(h_x, h_x + (size_t)rows * cols);
+    j->rows = rows;
+    j->cols = cols;
+    j->params = *p;
+    j->seed = seed;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        const size_t pb = ebic_pairs_bytes(rows, cols);
+        j->pairs = pb > 0 && pb <= budget_ / 8;
+        j->footprint = Job::footprint(rows, cols, *p, j->pairs);
+        j->id = next_id_++;
+        j->t_submit = now_s();
+        jobs_[j->id] = j;
+        queue_.push_back(j);
+        submitted_++;
+        *id = j->id;
+    }
+    cv_work_.notify_all();
+    return EBIC_OK;
+}
+
+int Server::poll(int64_t id, ebic_result **out, bool block) {
+    if (!out) return fail(EBIC_ERR_INVALID_ARG, "out is NULL");
+    std::unique_lock<std::mutex> lk(mu_);
+    auto it = jobs_.find(id);
+    if (it == jobs_.end()) return fail(EBIC_ERR_INVALID_ARG, "unknown job %lld", (long long)id);
+    std::shared_ptr<ServerJob> j = it->second;
+    if (block) cv_done_.wait(lk, [&] { return j->status != EBIC_PENDING; });
+    if (j->status == EBIC_PENDING) return EBIC_PENDING;
+    jobs_.erase(id);
+    if (j->status != EBIC_OK) return fail(j->status, "job %lld: %s", (long long)id, j->error.c_str());
+    *out = &j->result->pub;
+    j->result = nullptr;
+    return EBIC_OK;
+}
+
+void Server::stats(ebic_server_metrics *st) {
+    std::lock_guard<std::mutex> lk(mu_);
+    *st = ebic_server_metrics{};
+    st->submitted = submitted_;
+    st->completed = completed_;
+    st->failed = failed_;
+    st->queued = (int64_t)queue_.size();
+    st->active = n_active_;
+    st->evaluations = evaluations_;
+    st->ticks = ticks_;
+    if (!latencies_.empty()) {
+        std::vector<double> l = latencies_;
+        std::sort(l.begin(), l.end());
+        auto q = [&](double f) {
+            const size_t i = (size_t)std::min<double>(l.size() - 1, std::ceil(f * l.size()) - 1);
+            return l[i];
+        };
+        st->p50_latency_s = q(0.50);
+        st->p99_latency_s = q(0.99);
+        double sum = 0;
+        for (double v : l) sum += v;
+        st->mean_latency_s = sum / l.size();
+    }
+    st->busy_s = busy_s_;
+    st->hbm_in_use = in_use_;
+    st->hbm_budget = budget_;
+}
+
+// Called with mu_ held.
+void Server::finish_job(const std::shared_ptr<ServerJob> &j, int status, const char *err) {
+    j->status = status;
+    if (err) j->error = err;
+    j->t_done = now_s();
+    if (status == EBIC_OK) {
+        completed_++;
+        latencies_.push_back(j->t_done - j->t_submit);
+    } else {
+        failed_++;
+    }
+}
+
+void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
+    std::vector<ebic_job> views(active.size());
+    std::vector<int> src(active.size(), EBIC_OK);
+    // host packing and uploads of every job in parallel (uploads are queued
+    // on the one stream; the launch below is queued after all of them)
+    pool_->run(active.size(), [&](size_t i) {
+        (void)hipSetDevice(device_);
+        src[i] = active[i]->job->stage(&views[i]);
+    });
+    int rc = EBIC_OK;
+    for (int v : src)
+        if (v != EBIC_OK) rc = v;
+    if (rc == EBIC_OK) rc = batch_set(&batch_, views.data(), (int32_t)views.size(), stream_);
+    if (rc == EBIC_OK) rc = batch_run(batch_, stream_);
+    for (size_t i = 0; i < active.size() && rc == EBIC_OK; i++) rc = active[i]->job->fetch();
+    if (rc == EBIC_OK) {
+        hipError_t e = hipStreamSynchronize(stream_);
+        if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
+    }
+    std::vector<int> st(active.size(), rc);
+    std::vector<std::string> msg(active.size(), rc ? ebic_last_error() : "");
+    if (rc == EBIC_OK)
+        pool_->run(active.size(), [&](size_t i) {
+            (void)hipSetDevice(device_);
+            st[i] = active[i]->job->advance();
+            if (st[i]) msg[i] = ebic_last_error();
+        });
+    std::lock_guard<std::mutex> lk(mu_);
+    ticks_++;
+    std::vector<std::shared_ptr<ServerJob>> keep;
+    for (size_t i = 0; i < active.size(); i++) {
+        auto &j = active[i];
+        if (st[i] == EBIC_OK && !j->job->done()) {
+            keep.push_back(j);
+            continue;
+        }
+        if (st[i] == EBIC_OK) {
+            evaluations_ += j->job->evaluations();
+            j->result = j->job->take_result();
+        }
+        finish_job(j, st[i], st[i] ? msg[i].c_str() : nullptr);
+        j->job.reset();  // device memory back to the budget
+        j->x.clear();
+        j->x.shrink_to_fit();
+        in_use_ -= j->footprint;
+    }
+    active.swap(keep);
+    n_active_ = (int64_t)active.size();
+    cv_done_.notify_all();
+}
+
+void Server::loop() {
+    (void)hipSetDevice(device_);
+    std::vector<std::shared_ptr<ServerJob>> active;
+    for (;;) {
+        std::vector<std::shared_ptr<ServerJob>> admit;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_work_.wait(lk, [&] { return stop_ || !queue_.empty() || !active.empty(); });
+            if (stop_) {  // queued jobs are dropped; active ones finish
+                while (!queue_.empty()) {
+                    finish_job(queue_.front(), EBIC_ERR_CAPACITY, "server stopped");
+                    queue_.pop_front();
+                }
+                cv_done_.notify_all();
+                if (active.empty()) break;
+            }
+            while (!queue_.empty() && (int32_t)(active.size() + admit.size()) < max_active_) {
+                auto &j = queue_.front();
+                if (j->footprint > budget_) {
+                    finish_job(j, EBIC_ERR_CAPACITY, "footprint exceeds the HBM budget");
+                    queue_.pop_front();
+                    cv_done_.notify_all();
+                    continue;
+                }
+                if (in_use_ + j->footprint > budget_) break;
+                in_use_ += j->footprint;
+                admit.push_back(j);
+                queue_.pop_front();
+            }
+            n_active_ = (int64_t)(active.size() + admit.size());  // admitted count as active
+        }
+        for (auto &j : admit) {
+            j->job.reset(new Job(j->params, j->seed, stream_));
+            int rc = j->job->setup(j->x.data(), j->rows, j->cols, j->pairs);
+            if (rc == EBIC_OK) {
+                j->job->start();
+                active.push_back(j);
+            } else {
+                std::lock_guard<std::mutex> lk(mu_);
+                finish_job(j, rc, ebic_last_error());
+                j->job.reset();
+                in_use_ -= j->footprint;
+                n_active_--;
+                cv_done_.notify_all();
+            }
+        }
+        if (active.empty()) continue;
+        const double t0 = now_s();
+        tick(active);
+        std::lock_guard<std::mutex> lk(mu_);
+        busy_s_ += now_s() - t0;
+    }
+}
+
+int server_create(const ebic_server_config *cfg, Server **out) {
+    Server *s = new Server();
+    int rc = s->init(cfg);
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return EBIC_OK;
+}
+int server_submit(Server *s, const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                  uint64_t seed, int64_t *id) {
+    return s->submit(h_x, rows, cols, p, seed, id);
+}
+int server_poll(Server *s, int64_t id, ebic_result **out, bool block) {
+    return s->poll(id, out, block);
+}
+void server_stats(Server *s, ebic_server_metrics *st) { s->stats(st); }
+void server_destroy(Server *s) { delete s; }
+
+}  // namespace ebic

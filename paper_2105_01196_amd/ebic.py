@@ -82,11 +82,26 @@ class ebic_result(ctypes.Structure):
                 ("trace", ctypes.POINTER(ctypes.c_double))]
 
 
+class ebic_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", _i32)]
+
+
+class ebic_server_metrics(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("evaluations", ctypes.c_int64),
+                ("ticks", ctypes.c_int64), ("p50_latency_s", ctypes.c_double),
+                ("p99_latency_s", ctypes.c_double), ("mean_latency_s", ctypes.c_double),
+                ("busy_s", ctypes.c_double), ("hbm_in_use", ctypes.c_size_t),
+                ("hbm_budget", ctypes.c_size_t)]
+
+
 EBIC_STOP_GENERATIONS = 1
 EBIC_STOP_TABU = 2
 EBIC_STOP_EXHAUSTED = 3
 EBIC_BATCH_GRAPH = 1
 EBIC_BATCH_GATHER = 2
+EBIC_BATCH_TUNE = 4
 
 # Every symbol include/ebic.h declares, with its ctypes signature.
 _SIGNATURES = {
@@ -111,7 +126,18 @@ _SIGNATURES = {
     "ebic_run": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params), ctypes.c_uint64,
                                 _vp, ctypes.POINTER(ctypes.POINTER(ebic_result))]),
     "ebic_result_free": (None, [ctypes.POINTER(ebic_result)]),
+    "ebic_server_create": (ctypes.c_int, [ctypes.POINTER(ebic_server_config),
+                                          ctypes.POINTER(_vp)]),
+    "ebic_server_submit": (ctypes.c_int, [_vp, _vp, _i32, _i32, ctypes.POINTER(ebic_params),
+                                          ctypes.c_uint64, ctypes.POINTER(ctypes.c_int64)]),
+    "ebic_server_poll": (ctypes.c_int, [_vp, ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.POINTER(ebic_result))]),
+    "ebic_server_wait": (ctypes.c_int, [_vp, ctypes.c_int64,
+                                        ctypes.POINTER(ctypes.POINTER(ebic_result))]),
+    "ebic_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ebic_server_metrics)]),
+    "ebic_server_destroy": (ctypes.c_int, [_vp]),
     "ebic_batch_profile": (ctypes.c_int, [_vp, _i32]),
+    "ebic_batch_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "ebic_batch_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(_i32)]),
@@ -396,16 +422,24 @@ def make_job(m: Matrix, pop: Population, archive: Optional[Archive] = None,
 class Batch:
     """A batch of jobs evaluated by one launch (ebic_batch_*)."""
 
-    def __init__(self, jobs: Sequence[Job], graph: bool = False, gather: bool = False):
+    def __init__(self, jobs: Sequence[Job], graph: bool = False, gather: bool = False,
+                 tune: bool = False):
         self.jobs = list(jobs)
         self._views = (ebic_job * len(self.jobs))(*[j.view() for j in self.jobs])
-        flags = (EBIC_BATCH_GRAPH if graph else 0) | (EBIC_BATCH_GATHER if gather else 0)
+        flags = (EBIC_BATCH_GRAPH if graph else 0) | (EBIC_BATCH_GATHER if gather else 0) | \
+            (EBIC_BATCH_TUNE if tune else 0)
         h = _vp()
         _check(lib().ebic_batch_create(self._views, len(self.jobs), flags, ctypes.byref(h)))
         self.handle = h
 
     def run(self, stream=None) -> None:
         _check(lib().ebic_batch_run(self.handle, _stream(stream)))
+
+    def tuning(self):
+        """(chunks per item, loads in flight) the batch uses."""
+        a, b = _i32(), _i32()
+        _check(lib().ebic_batch_tuning(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     def profile(self, n: int) -> None:
         """Record kernel times for the next n runs."""
@@ -457,13 +491,8 @@ class RunResult:
     trace: np.ndarray     # generations x 4
 
 
-def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None) -> RunResult:
-    """The whole method on a host float32 matrix (synchronous)."""
-    x = np.ascontiguousarray(x, dtype=np.float32)
-    R, C = x.shape
-    res = ctypes.POINTER(ebic_result)()
-    _check(lib().ebic_run(x.ctypes.data, R, C, ctypes.byref(params), ctypes.c_uint64(seed),
-                          _stream(stream), ctypes.byref(res)))
+def _take_result(res) -> RunResult:
+    """Copy a library-owned ebic_result into Python objects and free it."""
     try:
         r = res.contents
         bcs = []
@@ -479,6 +508,60 @@ def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None) -> RunR
         return RunResult(bcs, g, int(r.evaluations), int(r.tabu_hits), int(r.stop_reason), trace)
     finally:
         lib().ebic_result_free(res)
+
+
+def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None) -> RunResult:
+    """The whole method on a host float32 matrix (synchronous)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    R, C = x.shape
+    res = ctypes.POINTER(ebic_result)()
+    _check(lib().ebic_run(x.ctypes.data, R, C, ctypes.byref(params), ctypes.c_uint64(seed),
+                          _stream(stream), ctypes.byref(res)))
+    return _take_result(res)
+
+
+class Server:
+    """Job server (ebic_server_*): continuous batching of runs on one GPU."""
+
+    def __init__(self, hbm_budget: int = 0, max_active: int = 0):
+        cfg = ebic_server_config(hbm_budget, max_active)
+        h = _vp()
+        _check(lib().ebic_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+
+    def submit(self, x: np.ndarray, params: ebic_params, seed: int) -> int:
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        jid = ctypes.c_int64()
+        _check(lib().ebic_server_submit(self.handle, x.ctypes.data, x.shape[0], x.shape[1],
+                                        ctypes.byref(params), ctypes.c_uint64(seed),
+                                        ctypes.byref(jid)))
+        return int(jid.value)
+
+    def poll(self, jid: int) -> Optional[RunResult]:
+        res = ctypes.POINTER(ebic_result)()
+        rc = _check(lib().ebic_server_poll(self.handle, jid, ctypes.byref(res)))
+        return None if rc == EBIC_PENDING else _take_result(res)
+
+    def wait(self, jid: int) -> RunResult:
+        res = ctypes.POINTER(ebic_result)()
+        _check(lib().ebic_server_wait(self.handle, jid, ctypes.byref(res)))
+        return _take_result(res)
+
+    def stats(self) -> dict:
+        m = ebic_server_metrics()
+        _check(lib().ebic_server_stats(self.handle, ctypes.byref(m)))
+        return {n: getattr(m, n) for n, _ in ebic_server_metrics._fields_}
+
+    def close(self) -> None:
+        if self.handle:
+            lib().ebic_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ebic_support_rows(support: torch.Tensor, sel: Sequence[int], counts: Sequence[int],

@@ -219,3 +219,31 @@ def test_malformed_individuals_marked(E):
     ev = oracle.evaluate(X, [good, list(range(10)), good],
                          params=oracle.make_params(**_kw(min_rows=1)))
     np.testing.assert_array_equal(cnt[[0, 5, 6]], ev.count)
+
+
+def test_autotuned_batch_identical(E, tmp_path, monkeypatch):
+    """A tuned batch (every item shape timed on the first run) gives the
+    plain path's results bit for bit, records its choice in the JSON cache,
+    and a graph-backed tuned batch replays the same results."""
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("EBIC_TUNE_CACHE", str(cache))
+    case = synth.workload_matrix(2)
+    seqs = synth.workload_population(2, case, P=777)
+    kw = E.make_params(**_kw())
+    m = _matrix(E, case.X)
+    pop = E.ebic_population_upload(seqs, case.C)
+    plain = E.ebic_evaluate(m, pop, None, kw)
+    for graph in (False, True):
+        job = E.make_job(m, pop, None, kw)
+        b = E.Batch([job], tune=True, graph=graph)
+        for _ in range(2):
+            b.run()
+            torch.cuda.synchronize()
+            for x, y in ((plain.count, job.out.count), (plain.fitness, job.out.fitness),
+                         (plain.support, job.out.support)):
+                assert torch.equal(x, y)
+        cpi, kb = b.tuning()
+        assert cpi in (1, 2, 4) and kb in (2, 4)
+        b.close()
+    text = cache.read_text()
+    assert "_i777_j1" in text and "[" in text
