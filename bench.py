@@ -143,7 +143,7 @@ def main():
         archs.append(arch)
         plain_outs.append(E.alloc_eval_out(len(seqs), m.words, K, overlap=args.overlap))
         jobs.append(E.make_job(m, pop, arch, params, overlap=args.overlap))
-    batch = E.Batch(jobs)
+    batch = E.Batch(jobs, tune=True)  # item shape timed on the first (warm-up) run
     P = sum(len(s) for s in pops_seqs)
     ks = np.array([len(s) for seqs in pops_seqs for s in seqs], dtype=np.int64)
 
@@ -166,6 +166,7 @@ def main():
     ms_batched = timed(lambda: batch.run(stream), args.steps)
     a_ms, b_ms = batch.timings(args.steps)
     batch.profile(0)
+    cpi, kb = batch.tuning()
     kern_a = float(a_ms.mean())
     kern_b = float(b_ms.mean())
 
@@ -204,7 +205,8 @@ def main():
         "config": {"workload": w.name, "rows": R, "cols": C, "populations": npop,
                    "individuals": P, "k_range": [w.k_min, w.k_max], "archive": K,
                    "negative_trends": 1, "approx_permille": 850, "overlap_output": args.overlap,
-                   "path": "batched, pair table, one launch"},
+                   "path": "batched, pair table, one launch",
+                   "tuned_item": {"chunks_per_item": cpi, "loads_in_flight": kb}},
         "cells_per_s": float(R * ks.sum()) / (ms_batched / 1e3),
         "kernel_ms": {"eval_items_kernel": kern_a, "epilogue_kernel": kern_b},
         "pair_table": {"bytes": int(m.pairs.numel() * 8), "build_ms": table_ms},

@@ -50,6 +50,7 @@ struct DevJob {
     int32_t *count;
     uint64_t *support;
     int32_t *overlap;
+    uint64_t *memb;  // cols words: bit j = archive member j holds the column (or NULL)
 };
 
 namespace {
@@ -71,7 +72,6 @@ constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
 // pair-bitmap loads in flight per wave: a template parameter KB (2 or 4),
 // picked per batch by the autotuner
 constexpr int kSupRegs = 8;      // support words kept in registers (64 x 8 words)
-constexpr int kMembCols = 2048;  // widest matrix whose member masks fit in LDS
 
 // Job of a flat index: count the job starts at or below it. The starts sit
 // in a compact array, so the loads are independent scalar loads.
@@ -228,6 +228,27 @@ __global__ void __launch_bounds__(kThreads)
                       int32_t njobs, int64_t total_items) {
     __shared__ int32_t s_buf[kWaves][EBIC_MAX_K];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t main_blocks = (total_items + kWaves - 1) / kWaves;
+    if ((int64_t)blockIdx.x >= main_blocks) {
+        // one trailing workgroup per job: the archive's per-column member
+        // masks, read by the reduction kernel
+        const int jb = (int)((int64_t)blockIdx.x - main_blocks);
+        if (jb >= njobs) return;
+        const DevJob &M = jobs[jb];
+        if (!M.memb) return;
+        for (int c = threadIdx.x; c < M.cols; c += kThreads) M.memb[c] = 0;
+        __syncthreads();
+        for (int j = 0; j < M.arch_size; j++) {
+            int32_t mb = M.arch_off[j], me = M.arch_off[j + 1];
+            if (mb < 0) mb = 0;
+            if (me > M.arch_len) me = M.arch_len;
+            for (int q = mb + threadIdx.x; q < me; q += kThreads) {
+                const int col = M.arch_cols[q];
+                if (col < M.cols) atomicOr((unsigned long long *)&M.memb[col], 1ull << j);
+            }
+        }
+        return;
+    }
     const int64_t item = (int64_t)blockIdx.x * kWaves + wave;
     if (item >= total_items) return;
     const DevJob &J = jobs[find_job(item_begins, njobs, item)];
@@ -303,49 +324,18 @@ __global__ void __launch_bounds__(kThreads)
 // depend on it or the caller asked for it, the shared rows h; writes count,
 // overlap and fitness. When the size score is 0 the fitness is 0 whatever
 // the penalty, so the members are only visited for the overlap output.
-// Shared columns come from per-column member masks built once per
-// workgroup in LDS (bit j of memb[c] = member j holds column c): each lane
-// takes one column of the series, and g_j is one ballot. Since h <= n, a
+// Shared columns come from per-column member masks (bit j of memb[c] =
+// member j holds column c), built once per run by trailing workgroups of the
+// evaluation kernel: each lane takes one column of the series, and g_j is
+// one ballot. Since h <= n, a
 // member can only overlap too much when 1000 g > theta k, so the shared rows
 // are only counted for those members (or when the output is requested).
 __global__ void __launch_bounds__(kThreads)
     epilogue_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ ind_begins,
                     int32_t njobs, int64_t total_ind) {
     __shared__ uint32_t s_bits[kWaves][EBIC_MAX_COLS / 32];
-    __shared__ uint64_t s_memb[kMembCols];
-    __shared__ int32_t s_aoff[EBIC_MAX_ARCHIVE + 1];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t gid0 = (int64_t)blockIdx.x * kWaves;
-    const int64_t gid = gid0 + wave;
-    // member masks, shared by the workgroup when all its waves are of one job
-    const int64_t last = (gid0 + kWaves - 1 < total_ind ? gid0 + kWaves - 1 : total_ind - 1);
-    const int jf = find_job(ind_begins, njobs, gid0);
-    const bool shared_job = find_job(ind_begins, njobs, last) == jf;
-    const DevJob &JF = jobs[jf];
-    const bool use_memb = shared_job && JF.arch_size > 0 && JF.cols <= kMembCols;
-    if (use_memb) {
-        const int KF = JF.arch_size;
-        for (int c = threadIdx.x; c < JF.cols; c += kThreads) s_memb[c] = 0;
-        for (int j = threadIdx.x; j <= KF; j += kThreads) {
-            const int32_t o = JF.arch_off[j];
-            s_aoff[j] = o < 0 ? 0 : (o > JF.arch_len ? JF.arch_len : o);
-        }
-        __syncthreads();
-        // every archive entry at once; its member by binary search of the
-        // offsets (member j holds entries s_aoff[j] .. s_aoff[j+1])
-        for (int q = s_aoff[0] + threadIdx.x; q < s_aoff[KF]; q += kThreads) {
-            int lo = 0, hi = KF - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) / 2;
-                if (s_aoff[mid] <= q) lo = mid;
-                else hi = mid - 1;
-            }
-            const int col = JF.arch_cols[q];
-            if (col < JF.cols && q < s_aoff[lo + 1])
-                atomicOr((unsigned long long *)&s_memb[col], 1ull << lo);
-        }
-        __syncthreads();
-    }
+    const int64_t gid = (int64_t)blockIdx.x * kWaves + wave;
     if (gid >= total_ind) return;
     const DevJob &J = jobs[find_job(ind_begins, njobs, gid)];
     const int32_t i = (int32_t)(gid - J.ind_begin);
@@ -353,13 +343,25 @@ __global__ void __launch_bounds__(kThreads)
     const int k = end - beg;
     uint32_t *bits = s_bits[wave];
     const int K = J.arch_size;
+    uint64_t *S = J.support + (int64_t)i * J.w64;
+    // every load the individual needs, issued before any of them is used:
+    // its support words, its first 64 columns and their member masks
+    const bool in_regs = J.w64 <= kWave * kSupRegs;
+    uint64_t sv[kSupRegs];
+#pragma unroll
+    for (int q = 0; q < kSupRegs; q++) {
+        const int w = lane + kWave * q;
+        sv[q] = (in_regs && w < J.w64) ? S[w] : 0;
+    }
     bool bad = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
+    const int col0 = (!bad && lane < k) ? J.pop_cols[beg + lane] : -1;
+    const uint64_t memb0 = (J.memb && col0 >= 0 && col0 < J.cols) ? J.memb[col0] : 0ull;
     if (!bad) {
         for (int q = lane; q < (J.cols + 31) / 32; q += kWave) bits[q] = 0;
         __builtin_amdgcn_wave_barrier();
         int lbad = 0;
         for (int j = lane; j < k; j += kWave) {
-            const int c = J.pop_cols[beg + j];
+            const int c = j < kWave ? col0 : J.pop_cols[beg + j];
             if (c >= J.cols) {
                 lbad = 1;
             } else {
@@ -370,7 +372,6 @@ __global__ void __launch_bounds__(kThreads)
         __builtin_amdgcn_wave_barrier();
         bad = __ballot(lbad) != 0;
     }
-    uint64_t *S = J.support + (int64_t)i * J.w64;
     if (bad) {
         for (int w = lane; w < J.w64; w += kWave) S[w] = 0;
         if (J.overlap)
@@ -381,15 +382,9 @@ __global__ void __launch_bounds__(kThreads)
         }
         return;
     }
-    const bool in_regs = J.w64 <= kWave * kSupRegs;
-    uint64_t sv[kSupRegs];
     int c = 0;
 #pragma unroll
-    for (int q = 0; q < kSupRegs; q++) {
-        const int w = lane + kWave * q;
-        sv[q] = (in_regs && w < J.w64) ? S[w] : 0;
-        c += __popcll(sv[q]);
-    }
+    for (int q = 0; q < kSupRegs; q++) c += __popcll(sv[q]);
     if (!in_regs)
         for (int w = lane; w < J.w64; w += kWave) c += __popcll(S[w]);
     const int n = wave_sum(c);
@@ -399,10 +394,11 @@ __global__ void __launch_bounds__(kThreads)
     if (K > 0 && (score > 0.0 || J.overlap)) {
         // my_g: lane j ends with g_j
         int my_g = 0;
-        if (use_memb) {
+        if (J.memb) {
             for (int q0 = 0; q0 < k; q0 += kWave) {
                 const int q = q0 + lane;
-                const uint64_t mask = q < k ? s_memb[J.pop_cols[beg + q]] : 0ull;
+                const uint64_t mask =
+                    q0 == 0 ? memb0 : (q < k ? J.memb[J.pop_cols[beg + q]] : 0ull);
                 for (int j = 0; j < K; j++) {
                     const int gj = __popcll(__ballot((mask >> j) & 1ull));
                     if (lane == j) my_g += gj;
@@ -475,6 +471,8 @@ struct Batch {
     std::vector<void *> scratch;
     int64_t total_items = 0, total_ind = 0;
     int32_t njobs = 0;         // kept alive: the graph's kernel arguments
+    uint64_t *d_memb = nullptr;  // member masks of all jobs with an archive
+    size_t memb_cap = 0;       // words
     int kb = 2;                // pair-bitmap loads in flight (template)
     int cpi = 1;               // chunks per item
     bool tuned = false;
@@ -566,6 +564,21 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
     }
     b->total_items = items;
     b->total_ind = inds;
+    // member-mask scratch for every job with an archive
+    size_t words = 0;
+    for (const DevJob &d : b->jobs) words += d.arch_size > 0 ? (size_t)d.cols : 0;
+    if (words > b->memb_cap) {
+        if (b->d_memb) (void)hipFree(b->d_memb);
+        b->d_memb = nullptr;
+        b->memb_cap = 0;
+        EBIC_HIP(hipMalloc(reinterpret_cast<void **>(&b->d_memb), words * sizeof(uint64_t)));
+        b->memb_cap = words;
+    }
+    size_t at = 0;
+    for (DevJob &d : b->jobs) {
+        d.memb = d.arch_size > 0 ? b->d_memb + at : nullptr;
+        at += d.arch_size > 0 ? (size_t)d.cols : 0;
+    }
     const int32_t n = b->njobs;
     const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 2 * n;
     if (n > b->cap_jobs) {
@@ -598,9 +611,12 @@ void *eval_kernel_fn(int kb) {
                    : reinterpret_cast<void *>(eval_items_kernel<2>);
 }
 
+unsigned eval_grid(const Batch *b) {
+    return (unsigned)((b->total_items + kWaves - 1) / kWaves + b->njobs);
+}
+
 int launch_eval(Batch *b, hipStream_t stream) {
-    if (b->total_items == 0) return EBIC_OK;
-    const unsigned grid = (unsigned)((b->total_items + kWaves - 1) / kWaves);
+    const unsigned grid = eval_grid(b);
     if (b->kb == 4)
         eval_items_kernel<4><<<grid, kThreads, 0, stream>>>(b->d_jobs, b->d_item_begins,
                                                             b->njobs, b->total_items);
@@ -622,7 +638,7 @@ int build_graph(Batch *b) {
     void *args_b[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
     hipKernelNodeParams pa{}, pb{};
     pa.func = eval_kernel_fn(b->kb);
-    pa.gridDim = dim3((unsigned)((b->total_items + kWaves - 1) / kWaves));
+    pa.gridDim = dim3(eval_grid(b));
     pa.blockDim = dim3(kThreads);
     pa.kernelParams = args_a;
     pb.func = reinterpret_cast<void *>(epilogue_kernel);
@@ -630,10 +646,8 @@ int build_graph(Batch *b) {
     pb.blockDim = dim3(kThreads);
     pb.kernelParams = args_b;
     hipError_t e = hipGraphCreate(&b->graph, 0);
-    if (e == hipSuccess && b->total_items > 0)
-        e = hipGraphAddKernelNode(&na, b->graph, nullptr, 0, &pa);
-    if (e == hipSuccess) e = hipGraphAddKernelNode(&nb, b->graph, na ? &na : nullptr, na ? 1 : 0,
-                                                   &pb);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&na, b->graph, nullptr, 0, &pa);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&nb, b->graph, &na, 1, &pb);
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return check_hip(e, "batch graph");
     return EBIC_OK;
@@ -896,6 +910,7 @@ int batch_destroy(Batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
+    if (b->d_memb) (void)hipFree(b->d_memb);
     for (void *p : b->scratch) (void)hipFree(p);
     delete b;
     return EBIC_OK;
