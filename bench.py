@@ -72,20 +72,28 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, cpi: int, kb: int):
     """HBM bytes per launch of the evaluation kernel from the committed
-    rocprofv3 counter summary, or None when the kernel source changed since
-    the counters were taken."""
+    rocprofv3 counter summary (one block per workload, each opened by a
+    `workload:` line), or None when the kernel source changed since the
+    counters were taken or they were taken on another item shape."""
     try:
-        fields = {}
+        blocks, glob, cur = {}, {}, None
         with open(TRAFFIC_FILE) as f:
             for line in f:
-                if ":" in line and not line.startswith("#"):
-                    k, v = line.split(":", 1)
-                    fields[k.strip()] = v.strip()
-        if fields.get("source_sha256_16") != kernel_source_hash():
+                if ":" not in line or line.startswith("#"):
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k == "workload":
+                    cur = blocks.setdefault(v, {})
+                elif cur is None:
+                    glob[k] = v
+                else:
+                    cur[k] = v
+        if glob.get("source_sha256_16") != kernel_source_hash():
             return None
-        if fields.get("workload") != workload:
+        fields = blocks.get(workload)
+        if not fields or int(fields["chunks_per_item"]) != cpi or int(fields["loads_in_flight"]) != kb:
             return None
         return float(fields["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -188,7 +196,7 @@ def main():
     # support bitmap written (R/8).
     alg = float(((ks - 1) * R / 8.0 + 4 + 2 * ks + R / 8.0).sum())
     achieved = alg / (kern_a / 1e3) / 1e9
-    traffic = measured_traffic(w.name)
+    traffic = measured_traffic(w.name, cpi, kb)
     line = {
         "metric": "individual evaluations/s and % peak HBM GB/s (batched vs plain, bit-exact)",
         "value": value,

@@ -212,6 +212,11 @@ int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_b
  * process and, when the environment variable EBIC_TUNE_CACHE names a file,
  * in that JSON file. ebic_batch_tuning reports the shape in use. */
 int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight);
+/* Pins the item shape (chunks per item 1, 2 or 4; loads in flight 2 or 4),
+ * e.g. one reported by ebic_batch_tuning in an earlier process; later runs
+ * use it and do not tune. Results never depend on the shape. Synchronous;
+ * call between runs. Errors: EBIC_ERR_INVALID_ARG for another shape. */
+int ebic_batch_set_tuning(ebic_batch *b, int32_t chunks_per_item, int32_t loads_in_flight);
 int ebic_batch_run(ebic_batch *b, void *stream);
 int ebic_batch_destroy(ebic_batch *b);
 

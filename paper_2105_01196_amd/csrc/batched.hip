@@ -1,17 +1,18 @@
 // Batched evaluation: many populations (of one or several jobs, each with
 // its own matrix, archive and parameters) in one launch of two kernels.
 //
-// Kernel A splits every individual into items of 2048 rows and gives each
-// item to one wavefront; items of all jobs form one flat index space, so a
-// single launch covers the whole batch, individuals of uneven length
-// included. With a pair table a lane tests 32 rows at once: each step of the
-// series is one 32-bit load of the pair's bitmap, and the rows' counts of
-// steps against each trend are kept bit-sliced, saturating at t+1
-// (thermometer code: plane m holds "at least m violations"), so an update is
-// one AND-OR per plane. Without a table the item runs the gather form (lane =
-// row) over its 32 blocks. Kernel B then reduces each individual's support
-// words into the count, the rows shared with each archive member, and the
-// FP64 fitness. The paper sends the whole population to the GPU at once
+// Kernel A splits every individual into items of 4096 rows (or a few such
+// chunks) and gives each item to one wavefront; items of all jobs form one
+// flat index space, so a single launch covers the whole batch, individuals
+// of uneven length included. With a pair table a lane tests 64 rows at once:
+// each step of the series is one 64-bit load of the pair's bitmap, and the
+// rows' steps against each trend are counted bit-sliced in a counter that
+// starts at 2^P - (t+1) and so carries out of its top plane on the (t+1)-th
+// such step; a sticky carry flag per trend then decides the row, with no
+// compares. Without a table the item runs the gather form (lane = row) over
+// its 64-row blocks. Kernel B then reduces each individual's support words
+// into the count, the rows shared with each archive member, and the FP64
+// fitness. The paper sends the whole population to the GPU at once
 // (Sec. 2.4, step 2); here several populations share the launch.
 #include <algorithm>
 #include <cstdio>
@@ -58,17 +59,6 @@ namespace {
 constexpr int kWaves = 4;
 constexpr int kThreads = kWaves * kWave;
 constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
-#ifndef EBIC_THERMO_MAX
-#define EBIC_THERMO_MAX 8
-#endif
-#ifndef EBIC_INLINE_COUNTERS
-#define EBIC_INLINE_COUNTERS 1
-#endif
-#if EBIC_INLINE_COUNTERS
-#define EBIC_COUNTER_FN __device__ __forceinline__
-#else
-#define EBIC_COUNTER_FN __device__ __noinline__
-#endif
 // pair-bitmap loads in flight per wave: a template parameter KB (2 or 4),
 // picked per batch by the autotuner
 constexpr int kSupRegs = 8;      // support words kept in registers (64 x 8 words)
@@ -81,145 +71,134 @@ __device__ inline int find_job(const int64_t *__restrict__ begins, int njobs, in
     return j;
 }
 
-// Thermometer counters of steps against the increasing trend (D) and against
-// the decreasing trend (U), T = t+1 planes each, over the 64 rows of this
-// lane's word; returns the fit word.
-template <int T, bool NEG, int KB>
-EBIC_COUNTER_FN uint64_t pairs_thermo(const uint64_t *__restrict__ pairs, int64_t w64,
-                                      const int32_t *s_pd, int k, int w, bool active) {
-    uint64_t D[T], U[T];
+// Bit-sliced sum of KB one-bit inputs into PSUM_BITS(KB) planes.
+template <int KB>
+struct PartialSum {
+    static constexpr int B = KB == 1 ? 1 : KB == 2 ? 2 : 3;
+    static_assert(KB == 1 || KB == 2 || KB == 4, "groups of 1, 2 or 4 steps");
+    __device__ __forceinline__ static void sum(const uint64_t *v, uint64_t *s) {
+        if constexpr (KB == 1) {
+            s[0] = v[0];
+        } else if constexpr (KB == 2) {
+            s[0] = v[0] ^ v[1];
+            s[1] = v[0] & v[1];
+        } else {
+            const uint64_t a0 = v[0] ^ v[1] ^ v[2];
+            const uint64_t a1 = (v[0] & v[1]) | (v[2] & (v[0] ^ v[1]));
+            const uint64_t c = a0 & v[3];
+            s[0] = a0 ^ v[3];
+            s[1] = a1 ^ c;
+            s[2] = a1 & c;
+        }
+    }
+};
+
+// C (P planes) += S (B planes), ripple carry; the carry out of the top plane
+// and any bit of S at or above plane P set the sticky flag ov.
+template <int P, int B>
+__device__ __forceinline__ void add_sticky(uint64_t *C, const uint64_t *S, uint64_t &ov) {
+    uint64_t c = 0;
 #pragma unroll
-    for (int m = 0; m < T; m++) D[m] = U[m] = 0;
+    for (int p = 0; p < P; p++) {
+        if (p < B) {
+            const uint64_t a = C[p], x = a ^ S[p];
+            C[p] = x ^ c;
+            c = (a & S[p]) | (c & x);
+        } else {
+            const uint64_t a = C[p];
+            C[p] = a ^ c;
+            c = a & c;
+        }
+    }
+#pragma unroll
+    for (int p = P; p < B; p++) c |= S[p];
+    ov |= c;
+}
+
+// Steps against the increasing trend (downs) and against the decreasing
+// trend (ups) of the 64 rows of this lane's word, counted bit-sliced over P
+// planes from the start value 2^P - (t+1) (2^P >= t+1), so that the count
+// passes 2^P - 1 exactly on the (t+1)-th step against the trend; that
+// carry is kept in a sticky flag per trend (dov, uov). A row fits the
+// increasing trend while dov is clear, the decreasing one while uov is
+// clear. Each group of KB steps is loaded together, summed into a small
+// partial count and added to the counters once; after each group the wave
+// stops once every row has failed both trends. Returns the fit word.
+template <int P, bool NEG, int KB>
+__device__ __forceinline__ uint64_t pairs_count(const uint64_t *__restrict__ pairs, int64_t w64,
+                                                const int32_t *s_pd, int k, int t, int w,
+                                                bool active) {
+    constexpr int NP = P > 0 ? P : 1;
+    constexpr int B = PartialSum<KB>::B;
+    uint32_t start = __builtin_amdgcn_readfirstlane((1u << P) - (uint32_t)(t + 1));
+    // opaque to the optimiser: keeps the start planes from being hoisted out
+    // of the caller's chunk loop and held in registers across it
+    asm volatile("" : "+s"(start));
+    uint64_t D[NP], U[NP];
+#pragma unroll
+    for (int p = 0; p < P; p++) D[p] = U[p] = ((start >> p) & 1u) ? ~0ull : 0ull;
+    uint64_t dov = 0, uov = 0;
     int j = 1;
     while (j < k) {
         const int n = (k - j) < KB ? (k - j) : KB;
-        uint64_t x[KB];
+        uint64_t up[KB], dn[KB];
 #pragma unroll
         for (int q = 0; q < KB; q++) {
-            x[q] = 0;
+            uint64_t x = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
                 const uint64_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w64;
                 const uint64_t bits = active ? vec[w] : 0ull;
-                x[q] = pd < 0 ? ~bits : bits;  // 1 = up-step in this row
+                x = pd < 0 ? ~bits : bits;  // 1 = up-step in this row
             }
+            const uint64_t vm = q < n ? ~0ull : 0ull;  // steps past the end count nothing
+            up[q] = x & vm;
+            dn[q] = ~x & vm;
         }
-#pragma unroll
-        for (int q = 0; q < KB; q++) {
-            if (q < n) {  // uniform; no break, so the loop unrolls fully
-                const uint64_t up = x[q], down = ~x[q];
-#pragma unroll
-                for (int m = T - 1; m >= 1; m--) {
-                    D[m] |= D[m - 1] & down;
-                    if (NEG) U[m] |= U[m - 1] & up;
-                }
-                D[0] |= down;
-                if (NEG) U[0] |= up;
-            }
+        uint64_t S[B];
+        PartialSum<KB>::sum(dn, S);
+        add_sticky<P, B>(D, S, dov);
+        if (NEG) {
+            PartialSum<KB>::sum(up, S);
+            add_sticky<P, B>(U, S, uov);
         }
         j += n;
-        const uint64_t dead = D[T - 1] & (NEG ? U[T - 1] : ~0ull);
+        const uint64_t dead = dov & (NEG ? uov : ~0ull);
         if (__ballot(active && dead != ~0ull) == 0) break;
     }
-    return ~D[T - 1] | (NEG ? ~U[T - 1] : 0ull);
+    return ~dov | (NEG ? ~uov : 0ull);
 }
 
-// Bit-sliced compare of the 9-bit per-row counts b[] with a wave-uniform
-// value c (0 <= c < 512): rows with count < c in *lt, count == c in *eq.
-__device__ __forceinline__ void cmp_const(const uint64_t *b, int c, uint64_t *lt, uint64_t *eq) {
-    uint64_t l = 0, e = ~0ull;
-#pragma unroll
-    for (int p = 8; p >= 0; p--) {
-        if ((c >> p) & 1) {
-            l |= e & ~b[p];
-            e &= b[p];
-        } else {
-            e &= ~b[p];
-        }
+// Widest counter the pair path instantiates for KB steps per group: what
+// keeps the evaluation kernel within 64 VGPRs (8 waves per SIMD). Items with
+// a larger tolerance (t >= 2^P; at approx 0.85 none up to 512 columns with
+// KB = 2) take the gather form.
+template <int KB>
+struct PairLimit {
+    static constexpr int P = KB == 4 ? 5 : 7;
+    static constexpr int T = (1 << P) - 1;
+};
+
+template <int PP, int MAXP, bool NEG, int KB>
+__device__ __forceinline__ uint64_t pairs_width(int P, const uint64_t *pairs, int64_t w64,
+                                                const int32_t *s_pd, int k, int t, int w,
+                                                bool active) {
+    if constexpr (PP == MAXP) {
+        return pairs_count<PP, NEG, KB>(pairs, w64, s_pd, k, t, w, active);
+    } else {
+        if (P == PP) return pairs_count<PP, NEG, KB>(pairs, w64, s_pd, k, t, w, active);
+        return pairs_width<PP + 1, MAXP, NEG, KB>(P, pairs, w64, s_pd, k, t, w, active);
     }
-    *lt = l;
-    *eq = e;
 }
 
-// Exact bit-sliced count of up-steps (9 planes, k <= 512) for larger
-// tolerances; returns the fit word. Early exit once every row has more than
-// t steps against each trend (ups > t and downs = steps - ups > t).
-template <bool NEG, int KB>
-EBIC_COUNTER_FN uint64_t pairs_binary(const uint64_t *__restrict__ pairs, int64_t w64,
-                                      const int32_t *s_pd, int k, int t, int w, bool active) {
-    uint64_t b[9];
-#pragma unroll
-    for (int p = 0; p < 9; p++) b[p] = 0;
-    int j = 1;
-    while (j < k) {
-        const int n = (k - j) < KB ? (k - j) : KB;
-        uint64_t x[KB];
-#pragma unroll
-        for (int q = 0; q < KB; q++) {
-            x[q] = 0;
-            if (q < n) {
-                const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
-                const uint64_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w64;
-                const uint64_t bits = active ? vec[w] : 0ull;
-                x[q] = pd < 0 ? ~bits : bits;
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < KB; q++) {
-            if (q < n) {
-                uint64_t carry = x[q];
-#pragma unroll
-                for (int p = 0; p < 9; p++) {
-                    const uint64_t c2 = b[p] & carry;
-                    b[p] ^= carry;
-                    carry = c2;
-                }
-            }
-        }
-        j += n;
-        uint64_t lt, eq;
-        cmp_const(b, t, &lt, &eq);
-        uint64_t dead = ~(lt | eq);  // ups > t: the decreasing trend is broken
-        if (!NEG) dead = ~0ull;
-        const int cd = (j - 1) - t;  // steps so far minus t
-        if (cd <= 0) {
-            dead = 0;  // no row can have more than t steps against the increase yet
-        } else {
-            cmp_const(b, cd, &lt, &eq);
-            dead &= lt;  // ups < steps - t: the increasing trend is broken
-        }
-        if (__ballot(active && dead != ~0ull) == 0) break;
-    }
-    uint64_t lt, eq;
-    cmp_const(b, k - 1 - t, &lt, &eq);
-    uint64_t fit = ~lt;  // ups >= k-1-t  <=>  downs <= t
-    if (NEG) {
-        cmp_const(b, t, &lt, &eq);
-        fit |= lt | eq;  // ups <= t
-    }
-    return fit;
-}
-
+// Counter width for tolerance t <= PairLimit<KB>::T: the least P with
+// 2^P >= t+1.
 template <bool NEG, int KB>
 __device__ __forceinline__ uint64_t pairs_dispatch(const uint64_t *pairs, int64_t w64,
                                                    const int32_t *s_pd, int k, int t, int w,
                                                    bool active) {
-    switch (t) {
-#define EBIC_T(TT) \
-    case TT - 1: return pairs_thermo<TT, NEG, KB>(pairs, w64, s_pd, k, w, active);
-        EBIC_T(1) EBIC_T(2) EBIC_T(3) EBIC_T(4)
-#if EBIC_THERMO_MAX > 4
-        EBIC_T(5) EBIC_T(6) EBIC_T(7) EBIC_T(8)
-#endif
-#if EBIC_THERMO_MAX > 8
-        EBIC_T(9) EBIC_T(10) EBIC_T(11) EBIC_T(12)
-#endif
-#if EBIC_THERMO_MAX > 12
-        EBIC_T(13) EBIC_T(14) EBIC_T(15) EBIC_T(16)
-#endif
-#undef EBIC_T
-        default: return pairs_binary<NEG, KB>(pairs, w64, s_pd, k, t, w, active);
-    }
+    const int P = t == 0 ? 0 : 32 - __builtin_clz((unsigned)t);
+    return pairs_width<0, PairLimit<KB>::P, NEG, KB>(P, pairs, w64, s_pd, k, t, w, active);
 }
 
 template <int KB>
@@ -262,15 +241,18 @@ __global__ void __launch_bounds__(kThreads)
     const int k = end - beg;
     int32_t *s = s_buf[wave];
     bool bad = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
+    const int t = bad ? 0 : tol(k, J.approx_permille);
+    // pair table when the batch has one and the counters fit; else gather
+    const bool use_pairs = J.mode == 1 && t <= PairLimit<KB>::T;
     if (!bad) {
-        // stage the series (pair mode: one descriptor per step; gather mode:
+        // stage the series (pair form: one descriptor per step; gather form:
         // each column's byte offset)
         int lbad = 0;
         for (int j = lane; j < k; j += kWave) {
             const int c = J.pop_cols[beg + j];
             lbad |= c >= J.cols;
             if (j > 0) lbad |= c == J.pop_cols[beg + j - 1];
-            if (J.mode == 1) {
+            if (use_pairs) {
                 if (j > 0) {
                     const int a = J.pop_cols[beg + j - 1];
                     const int lo = a < c ? a : c, hi = a < c ? c : a;
@@ -290,11 +272,10 @@ __global__ void __launch_bounds__(kThreads)
         }
         return;
     }
-    const int t = tol(k, J.approx_permille);
     const bool neg = J.negative_trends != 0;
     for (int32_t chunk = ch0; chunk < ch1; chunk++) {
         const int w = chunk * 64 + lane;  // this lane's 64-row word
-        if (J.mode == 1) {
+        if (use_pairs) {
             const bool active = w < J.w64;
             uint64_t fit = neg ? pairs_dispatch<true, KB>(J.pairs, J.w64, s, k, t, w, active)
                                : pairs_dispatch<false, KB>(J.pairs, J.w64, s, k, t, w, active);
@@ -655,6 +636,9 @@ int build_graph(Batch *b) {
 
 // ---- autotuner: chunks per item x loads in flight, cached per shape ----
 
+constexpr int kTuneLaunches = 10;     // launches per timed sample
+constexpr float kTuneMargin = 0.98f;  // required gain over the current best
+
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<int, int>> g_tune;
 bool g_tune_loaded = false;
@@ -668,17 +652,26 @@ void tune_load_locked() {
     if (!path) return;
     FILE *f = fopen(path, "r");
     if (!f) return;
-    char key[256];
-    int a = 0, c = 0;
-    // entries look like  "key": [cpi, kb]
-    while (fscanf(f, " \"%255[^\"]\" : [ %d , %d ]", key, &a, &c) == 3) {
-        g_tune[key] = {a, c};
-        int ch;
-        while ((ch = fgetc(f)) != EOF && ch != ',' && ch != '}') {
-        }
-        if (ch != ',') break;
-    }
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
     fclose(f);
+    // entries look like  "key": [cpi, kb]  inside one JSON object
+    size_t pos = 0;
+    for (;;) {
+        const size_t q0 = text.find('"', pos);
+        if (q0 == std::string::npos) break;
+        const size_t q1 = text.find('"', q0 + 1);
+        if (q1 == std::string::npos) break;
+        int a = 0, c = 0;
+        if (sscanf(text.c_str() + q1 + 1, " : [ %d , %d ]", &a, &c) == 2 &&
+            (a == 1 || a == 2 || a == 4) && (c == 2 || c == 4))
+            g_tune[text.substr(q0 + 1, q1 - q0 - 1)] = {a, c};
+        const size_t close = text.find(']', q1);
+        if (close == std::string::npos) break;
+        pos = close + 1;
+    }
 }
 
 void tune_save_locked() {
@@ -709,8 +702,8 @@ std::string tune_key(const Batch *b) {
 }
 
 // Time every (chunks per item, loads in flight) candidate on this batch's
-// inputs with HIP events around the evaluation kernel (median of 3) and keep
-// the fastest. Results never depend on the choice.
+// inputs with HIP events around blocks of evaluation launches (median of 3
+// blocks) and keep the fastest. Results never depend on the choice.
 int tune(Batch *b, hipStream_t stream) {
     b->tuned = true;
     const std::string key = tune_key(b);
@@ -740,14 +733,16 @@ int tune(Batch *b, hipStream_t stream) {
             float t[3];
             for (int r = 0; r < 3 && rc == EBIC_OK; r++) {
                 (void)hipEventRecord(e0, stream);
-                rc = launch_eval(b, stream);
+                for (int l = 0; l < kTuneLaunches && rc == EBIC_OK; l++) rc = launch_eval(b, stream);
                 (void)hipEventRecord(e1, stream);
                 (void)hipEventSynchronize(e1);
                 (void)hipEventElapsedTime(&t[r], e0, e1);
             }
             if (rc) break;
             std::sort(t, t + 3);
-            if (t[1] < best) {
+            // a later (larger) shape must win clearly, so that timing noise
+            // does not flip the choice from run to run
+            if (t[1] < best * kTuneMargin) {
                 best = t[1];
                 best_cpi = cpi;
                 best_kb = kb;
@@ -873,6 +868,24 @@ int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (cpi) *cpi = b->cpi;
     if (kb) *kb = b->kb;
+    return EBIC_OK;
+}
+
+int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb) {
+    if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
+    if (!(cpi == 1 || cpi == 2 || cpi == 4) || !(kb == 2 || kb == 4))
+        return fail(EBIC_ERR_INVALID_ARG, "item shape (%d, %d): chunks per item 1, 2 or 4, loads "
+                    "in flight 2 or 4", cpi, kb);
+    // a graph holds the old grid and kernel: rebuilt on the next run
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    b->kb = kb;
+    b->tuned = true;
+    int rc = upload_table(b, cpi, nullptr);
+    if (rc) return rc;
+    EBIC_HIP(hipStreamSynchronize(nullptr));
     return EBIC_OK;
 }
 

@@ -231,6 +231,11 @@ int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in
     return batch_tuning(reinterpret_cast<Batch *>(b), chunks_per_item, loads_in_flight);
 }
 
+int ebic_batch_set_tuning(ebic_batch *b, int32_t chunks_per_item, int32_t loads_in_flight) {
+    clear_error();
+    return batch_set_tuning(reinterpret_cast<Batch *>(b), chunks_per_item, loads_in_flight);
+}
+
 int ebic_batch_profile(ebic_batch *b, int32_t n) {
     clear_error();
     return batch_profile(reinterpret_cast<Batch *>(b), n);

@@ -138,6 +138,7 @@ _SIGNATURES = {
     "ebic_server_destroy": (ctypes.c_int, [_vp]),
     "ebic_batch_profile": (ctypes.c_int, [_vp, _i32]),
     "ebic_batch_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "ebic_batch_set_tuning": (ctypes.c_int, [_vp, _i32, _i32]),
     "ebic_batch_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(_i32)]),
@@ -440,6 +441,10 @@ class Batch:
         a, b = _i32(), _i32()
         _check(lib().ebic_batch_tuning(self.handle, ctypes.byref(a), ctypes.byref(b)))
         return int(a.value), int(b.value)
+
+    def set_tuning(self, chunks_per_item: int, loads_in_flight: int) -> None:
+        """Pin the item shape; later runs use it and do not tune."""
+        _check(lib().ebic_batch_set_tuning(self.handle, chunks_per_item, loads_in_flight))
 
     def profile(self, n: int) -> None:
         """Record kernel times for the next n runs."""

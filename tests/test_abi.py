@@ -90,3 +90,10 @@ def test_run_rejects_bad_parameters_on_host():
         p = ebic.make_params(**{**dict(k_min=2, k_max=4), **bad})
         rc = L.ebic_run(X.ctypes.data, 10, 5, ctypes.byref(p), 1, None, ctypes.byref(res))
         assert rc == ebic.EBIC_ERR_INVALID_ARG, bad
+
+
+def test_batch_set_tuning_rejects_null_batch_on_host():
+    from paper_2105_01196_amd import ebic
+    L = ebic.lib()
+    assert L.ebic_batch_set_tuning(None, 1, 2) == ebic.EBIC_ERR_INVALID_ARG
+    assert L.ebic_last_error()

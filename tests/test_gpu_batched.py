@@ -141,6 +141,66 @@ def test_tolerance_regimes(E, approx):
         _run(E, X, seqs, _kw(approx_permille=approx, negative_trends=neg, min_rows=1))
 
 
+def _descent_rows(C):
+    """Row d (d < C) has exactly d descents along columns 0..C-1:
+    d, d-1, ..., 0, d+1, ..., C-1; then the same rows negated, whose
+    prefixes hold every count of ascents."""
+    rows = [np.r_[np.arange(d, -1, -1), np.arange(d + 1, C)] for d in range(C)]
+    X = np.array(rows, np.float32)
+    return np.vstack([X, -X])
+
+
+def _approx_for(k, t):
+    """An approx (per mille) whose tolerance for length k is exactly t, or None."""
+    for a in range(1000, -1, -1):
+        if ((k - 1) * (1000 - a)) // 1000 == t:
+            return a
+    return None
+
+
+@pytest.mark.parametrize("shape", [(1, 2), (1, 4), (2, 2), (4, 4)])
+def test_step_counts_at_counter_boundaries(E, shape):
+    """Every count of steps against a trend, from 0 to k-1, meets tolerances
+    at each counter width boundary (t = 2^P - 1 and 2^P) and beyond the
+    widest pair-path counter, for every item shape."""
+    C = 512
+    X = _descent_rows(C)
+    m = _matrix(E, X)
+    rng = np.random.default_rng(11)
+    for t in (0, 1, 2, 3, 4, 7, 8, 15, 16, 31, 32, 63, 64, 127, 128, 255, 256, 511):
+        for k in sorted({min(C, t + 1), min(C, t + 2), min(C, 2 * t + 3), min(C, 4 * t + 5)}):
+            a = _approx_for(k, t)
+            if a is None or k < 2:
+                continue
+            cols = np.arange(k)
+            seqs = [list(cols), list(cols[::-1]), list(rng.permutation(k)),
+                    list(np.r_[cols[1:], cols[:1]])]
+            pop = E.ebic_population_upload(seqs, C)
+            for neg in (0, 1):
+                kw = _kw(approx_permille=a, negative_trends=neg, min_rows=1)
+                job = E.make_job(m, pop, None, E.make_params(**kw))
+                b = E.Batch([job])
+                b.set_tuning(*shape)
+                assert b.tuning() == shape
+                b.run()
+                torch.cuda.synchronize()
+                _check_job(E, job, X, seqs, kw)
+                b.close()
+
+
+def test_set_tuning_rejects_other_shapes(E):
+    X = synth.random_matrix(100, 20, seed=3)
+    m = _matrix(E, X)
+    pop = E.ebic_population_upload([[0, 1, 2]], 20)
+    b = E.Batch([E.make_job(m, pop, None, E.make_params(**_kw()))])
+    for bad in ((3, 2), (1, 3), (0, 2), (8, 4)):
+        with pytest.raises(Exception):
+            b.set_tuning(*bad)
+    b.set_tuning(2, 4)
+    assert b.tuning() == (2, 4)
+    b.close()
+
+
 def test_multi_job_batch(E):
     """Jobs on different matrices and parameters in one launch, each equal to
     its own oracle evaluation; one job in gather form (no table)."""
