@@ -61,7 +61,11 @@ constexpr int kThreads = kWaves * kWave;
 constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
 // pair-bitmap loads in flight per wave: a template parameter KB (2 or 4),
 // picked per batch by the autotuner
-constexpr int kSupRegs = 8;      // support words kept in registers (64 x 8 words)
+// reduction kernel: Q support words per lane kept in registers (a template
+// parameter: 2, 4, 8 or 16, the least that holds the batch's longest support)
+// and the shared rows of G = 16 / Q archive members counted per pass, so
+// that about 16 loads are in flight per lane either way
+constexpr int kEpiMaxQ = 16;
 
 // Job of a flat index: count the job starts at or below it. The starts sit
 // in a compact array, so the loads are independent scalar loads.
@@ -311,10 +315,12 @@ __global__ void __launch_bounds__(kThreads)
 // one ballot. Since h <= n, a
 // member can only overlap too much when 1000 g > theta k, so the shared rows
 // are only counted for those members (or when the output is requested).
+template <int Q>
 __global__ void __launch_bounds__(kThreads)
     epilogue_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ ind_begins,
                     int32_t njobs, int64_t total_ind) {
     __shared__ uint32_t s_bits[kWaves][EBIC_MAX_COLS / 32];
+    constexpr int G = 16 / Q;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t gid = (int64_t)blockIdx.x * kWaves + wave;
     if (gid >= total_ind) return;
@@ -327,10 +333,10 @@ __global__ void __launch_bounds__(kThreads)
     uint64_t *S = J.support + (int64_t)i * J.w64;
     // every load the individual needs, issued before any of them is used:
     // its support words, its first 64 columns and their member masks
-    const bool in_regs = J.w64 <= kWave * kSupRegs;
-    uint64_t sv[kSupRegs];
+    const bool in_regs = J.w64 <= kWave * Q;
+    uint64_t sv[Q];
 #pragma unroll
-    for (int q = 0; q < kSupRegs; q++) {
+    for (int q = 0; q < Q; q++) {
         const int w = lane + kWave * q;
         sv[q] = (in_regs && w < J.w64) ? S[w] : 0;
     }
@@ -365,7 +371,7 @@ __global__ void __launch_bounds__(kThreads)
     }
     int c = 0;
 #pragma unroll
-    for (int q = 0; q < kSupRegs; q++) c += __popcll(sv[q]);
+    for (int q = 0; q < Q; q++) c += __popcll(sv[q]);
     if (!in_regs)
         for (int w = lane; w < J.w64; w += kWave) c += __popcll(S[w]);
     const int n = wave_sum(c);
@@ -407,22 +413,45 @@ __global__ void __launch_bounds__(kThreads)
         const bool my_need = lane < K && n > 0 &&
                              (J.overlap || 1000LL * my_g > (long long)J.overlap_permille * k);
         uint64_t need = __ballot(my_need);
+        // up to G members per pass, all their loads issued together
         while (need) {
-            const int j = __ffsll((unsigned long long)need) - 1;
-            need &= need - 1;
-            const uint64_t *A = J.arch_support + (int64_t)j * J.w64;
-            int hp = 0;
-            if (in_regs) {
+            int js[G];
 #pragma unroll
-                for (int q = 0; q < kSupRegs; q++) {
-                    const int w = lane + kWave * q;
-                    if (w < J.w64) hp += __popcll(sv[q] & A[w]);
-                }
-            } else {
-                for (int w = lane; w < J.w64; w += kWave) hp += __popcll(S[w] & A[w]);
+            for (int g = 0; g < G; g++) {
+                js[g] = need ? __ffsll((unsigned long long)need) - 1 : js[g > 0 ? g - 1 : 0];
+                need &= need - 1;
             }
-            const int h = wave_sum(hp);
-            if (lane == j) my_h = h;
+            int hp[G];
+#pragma unroll
+            for (int g = 0; g < G; g++) hp[g] = 0;
+            if (in_regs) {
+                uint64_t a[G][Q];
+#pragma unroll
+                for (int g = 0; g < G; g++) {
+                    const uint64_t *A = J.arch_support + (int64_t)js[g] * J.w64;
+#pragma unroll
+                    for (int q = 0; q < Q; q++) {
+                        const int w = lane + kWave * q;
+                        a[g][q] = w < J.w64 ? A[w] : 0ull;
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < G; g++)
+#pragma unroll
+                    for (int q = 0; q < Q; q++) hp[g] += __popcll(sv[q] & a[g][q]);
+            } else {
+                for (int w = lane; w < J.w64; w += kWave) {
+                    const uint64_t sw = S[w];
+#pragma unroll
+                    for (int g = 0; g < G; g++)
+                        hp[g] += __popcll(sw & J.arch_support[(int64_t)js[g] * J.w64 + w]);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const int h = wave_sum(hp[g]);
+                if (lane == js[g]) my_h = h;  // a repeated member writes the same h
+            }
         }
         const bool over = lane < K && 1000LL * my_h * my_g > (long long)J.overlap_permille * n * k;
         m = __popcll(__ballot(over));
@@ -456,6 +485,7 @@ struct Batch {
     size_t memb_cap = 0;       // words
     int kb = 2;                // pair-bitmap loads in flight (template)
     int cpi = 1;               // chunks per item
+    int epi_q = 4;             // reduction kernel: support words per lane in registers
     bool tuned = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -545,6 +575,9 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
     }
     b->total_items = items;
     b->total_ind = inds;
+    int32_t wmax = 0;
+    for (const DevJob &d : b->jobs) wmax = d.w64 > wmax ? d.w64 : wmax;
+    b->epi_q = wmax <= 2 * kWave ? 2 : wmax <= 4 * kWave ? 4 : wmax <= 8 * kWave ? 8 : kEpiMaxQ;
     // member-mask scratch for every job with an archive
     size_t words = 0;
     for (const DevJob &d : b->jobs) words += d.arch_size > 0 ? (size_t)d.cols : 0;
@@ -592,6 +625,26 @@ void *eval_kernel_fn(int kb) {
                    : reinterpret_cast<void *>(eval_items_kernel<2>);
 }
 
+void *epilogue_kernel_fn(int q) {
+    switch (q) {
+        case 2: return reinterpret_cast<void *>(epilogue_kernel<2>);
+        case 4: return reinterpret_cast<void *>(epilogue_kernel<4>);
+        case 8: return reinterpret_cast<void *>(epilogue_kernel<8>);
+        default: return reinterpret_cast<void *>(epilogue_kernel<kEpiMaxQ>);
+    }
+}
+
+unsigned epilogue_grid(const Batch *b) {
+    return (unsigned)((b->total_ind + kWaves - 1) / kWaves);
+}
+
+int launch_epilogue(Batch *b, hipStream_t stream) {
+    void *args[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
+    EBIC_HIP(hipLaunchKernel(epilogue_kernel_fn(b->epi_q), dim3(epilogue_grid(b)), dim3(kThreads),
+                             args, 0, stream));
+    return EBIC_OK;
+}
+
 unsigned eval_grid(const Batch *b) {
     return (unsigned)((b->total_items + kWaves - 1) / kWaves + b->njobs);
 }
@@ -622,8 +675,8 @@ int build_graph(Batch *b) {
     pa.gridDim = dim3(eval_grid(b));
     pa.blockDim = dim3(kThreads);
     pa.kernelParams = args_a;
-    pb.func = reinterpret_cast<void *>(epilogue_kernel);
-    pb.gridDim = dim3((unsigned)((b->total_ind + kWaves - 1) / kWaves));
+    pb.func = epilogue_kernel_fn(b->epi_q);
+    pb.gridDim = dim3(epilogue_grid(b));
     pb.blockDim = dim3(kThreads);
     pb.kernelParams = args_b;
     hipError_t e = hipGraphCreate(&b->graph, 0);
@@ -857,10 +910,9 @@ int batch_run(Batch *b, hipStream_t stream) {
     int rc = launch_eval(b, stream);
     if (rc) return rc;
     if (ev) EBIC_HIP(hipEventRecord(ev[1], stream));
-    epilogue_kernel<<<(unsigned)((b->total_ind + kWaves - 1) / kWaves), kThreads, 0, stream>>>(
-        b->d_jobs, b->d_ind_begins, b->njobs, b->total_ind);
+    rc = launch_epilogue(b, stream);
+    if (rc) return rc;
     if (ev) EBIC_HIP(hipEventRecord(ev[2], stream));
-    EBIC_HIP(hipGetLastError());
     return EBIC_OK;
 }
 
