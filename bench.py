@@ -72,7 +72,7 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, cpi: int, kb: int):
+def measured_traffic(workload: str, cpi: int, kb: int, wpl: int):
     """HBM bytes per launch of the evaluation kernel from the committed
     rocprofv3 counter summary (one block per workload, each opened by a
     `workload:` line), or None when the kernel source changed since the
@@ -93,7 +93,8 @@ def measured_traffic(workload: str, cpi: int, kb: int):
         if glob.get("source_sha256_16") != kernel_source_hash():
             return None
         fields = blocks.get(workload)
-        if not fields or int(fields["chunks_per_item"]) != cpi or int(fields["loads_in_flight"]) != kb:
+        if not fields or (int(fields["chunk_groups_per_item"]), int(fields["loads_in_flight"]),
+                          int(fields["words_per_lane"])) != (cpi, kb, wpl):
             return None
         return float(fields["hbm_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
@@ -174,7 +175,7 @@ def main():
     ms_batched = timed(lambda: batch.run(stream), args.steps)
     a_ms, b_ms = batch.timings(args.steps)
     batch.profile(0)
-    cpi, kb = batch.tuning()
+    cpi, kb, wpl = batch.tuning()
     kern_a = float(a_ms.mean())
     kern_b = float(b_ms.mean())
 
@@ -196,7 +197,7 @@ def main():
     # support bitmap written (R/8).
     alg = float(((ks - 1) * R / 8.0 + 4 + 2 * ks + R / 8.0).sum())
     achieved = alg / (kern_a / 1e3) / 1e9
-    traffic = measured_traffic(w.name, cpi, kb)
+    traffic = measured_traffic(w.name, cpi, kb, wpl)
     line = {
         "metric": "individual evaluations/s and % peak HBM GB/s (batched vs plain, bit-exact)",
         "value": value,
@@ -214,7 +215,8 @@ def main():
                    "individuals": P, "k_range": [w.k_min, w.k_max], "archive": K,
                    "negative_trends": 1, "approx_permille": 850, "overlap_output": args.overlap,
                    "path": "batched, pair table, one launch",
-                   "tuned_item": {"chunks_per_item": cpi, "loads_in_flight": kb}},
+                   "tuned_item": {"chunk_groups_per_item": cpi, "loads_in_flight": kb,
+                                  "words_per_lane": wpl}},
         "cells_per_s": float(R * ks.sum()) / (ms_batched / 1e3),
         "kernel_ms": {"eval_items_kernel": kern_a, "epilogue_kernel": kern_b},
         "pair_table": {"bytes": int(m.pairs.numel() * 8), "build_ms": table_ms},

@@ -205,18 +205,24 @@ typedef struct ebic_batch ebic_batch;
  * batch. Errors: EBIC_ERR_INVALID_ARG (as ebic_evaluate, per job),
  * EBIC_ERR_OOM, EBIC_ERR_DEVICE. Runs of one batch must not overlap. */
 int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_batch **out);
-/* With EBIC_BATCH_TUNE the first run times every candidate item shape
- * (4,096-row chunks per item: 1, 2, 4; pair-bitmap loads in flight per wave:
- * 2, 4) on the batch's own inputs, waits for the timings (that run is
- * synchronous), keeps the fastest, and caches the choice per shape in the
- * process and, when the environment variable EBIC_TUNE_CACHE names a file,
- * in that JSON file. ebic_batch_tuning reports the shape in use. */
-int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight);
-/* Pins the item shape (chunks per item 1, 2 or 4; loads in flight 2 or 4),
- * e.g. one reported by ebic_batch_tuning in an earlier process; later runs
- * use it and do not tune. Results never depend on the shape. Synchronous;
- * call between runs. Errors: EBIC_ERR_INVALID_ARG for another shape. */
-int ebic_batch_set_tuning(ebic_batch *b, int32_t chunks_per_item, int32_t loads_in_flight);
+/* Item shape of the evaluation kernel: a wave takes one item, i.e.
+ * chunks_per_item groups (1, 2 or 4) of words_per_lane (1 or 2) chunks of
+ * 4,096 rows, walking a group's chunks together (each lane holds one 64-row
+ * word of each), with loads_in_flight (2 or 4) pair-bitmap loads issued per
+ * group of steps. With EBIC_BATCH_TUNE the first run times every candidate
+ * shape on the batch's own inputs, waits for the timings (that run is
+ * synchronous), keeps the fastest, and caches the choice per batch shape in
+ * the process and, when the environment variable EBIC_TUNE_CACHE names a
+ * file, in that JSON file. ebic_batch_tuning reports the shape in use; any
+ * output pointer may be NULL. */
+int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight,
+                      int32_t *words_per_lane);
+/* Pins the item shape, e.g. one reported by ebic_batch_tuning in an earlier
+ * process; later runs use it and do not tune. Results never depend on the
+ * shape. Synchronous; call between runs. Errors: EBIC_ERR_INVALID_ARG for a
+ * shape outside the values above. */
+int ebic_batch_set_tuning(ebic_batch *b, int32_t chunks_per_item, int32_t loads_in_flight,
+                          int32_t words_per_lane);
 int ebic_batch_run(ebic_batch *b, void *stream);
 int ebic_batch_destroy(ebic_batch *b);
 

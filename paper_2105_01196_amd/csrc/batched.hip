@@ -34,10 +34,9 @@ struct DevJob {
     int32_t rows, cols, rows_pad, w32, w64;
     int32_t mode;     // 1 = pair table, 0 = gather
     int32_t nchunks;  // 2048-row chunks per individual
-    int32_t cpi;      // chunks per item (one wave walks them in turn)
+    int32_t cpi;      // chunks per item (one wave walks them WPL at a time)
     int32_t ipi;      // items per individual = ceil(nchunks / cpi)
     int32_t pop_size, pop_len;
-    int64_t item_begin;  // first item of this job in the batch
     int64_t ind_begin;   // first individual of this job in the batch
     const int32_t *pop_off;
     const uint16_t *pop_cols;
@@ -67,9 +66,10 @@ constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
 // that about 16 loads are in flight per lane either way
 constexpr int kEpiMaxQ = 16;
 
-// Job of a flat index: count the job starts at or below it. The starts sit
-// in a compact array, so the loads are independent scalar loads.
-__device__ inline int find_job(const int64_t *__restrict__ begins, int njobs, int64_t x) {
+// Segment of a flat index (a job's individuals, a phase of the item
+// schedule): count the segment starts after the first at or below it. The
+// starts sit in a compact array, so the loads are independent scalar loads.
+__device__ inline int find_segment(const int64_t *__restrict__ begins, int njobs, int64_t x) {
     int j = 0;
     for (int q = 1; q < njobs; q++) j += begins[q] <= x;
     return j;
@@ -120,103 +120,121 @@ __device__ __forceinline__ void add_sticky(uint64_t *C, const uint64_t *S, uint6
 }
 
 // Steps against the increasing trend (downs) and against the decreasing
-// trend (ups) of the 64 rows of this lane's word, counted bit-sliced over P
-// planes from the start value 2^P - (t+1) (2^P >= t+1), so that the count
-// passes 2^P - 1 exactly on the (t+1)-th step against the trend; that
-// carry is kept in a sticky flag per trend (dov, uov). A row fits the
-// increasing trend while dov is clear, the decreasing one while uov is
-// clear. Each group of KB steps is loaded together, summed into a small
-// partial count and added to the counters once; after each group the wave
-// stops once every row has failed both trends. Returns the fit word.
-template <int P, bool NEG, int KB>
-__device__ __forceinline__ uint64_t pairs_count(const uint64_t *__restrict__ pairs, int64_t w64,
-                                                const int32_t *s_pd, int k, int t, int w,
-                                                bool active) {
+// trend (ups) of the 64 rows of each of this lane's WPL words (w, w + 64,
+// ...), counted bit-sliced over P planes from the start value 2^P - (t+1)
+// (2^P >= t+1), so that the count passes 2^P - 1 exactly on the (t+1)-th
+// step against the trend; that carry is kept in a sticky flag per trend
+// (dov, uov). A row fits the increasing trend while dov is clear, the
+// decreasing one while uov is clear. Each group of KB steps is loaded
+// together, summed into a small partial count and added to the counters
+// once; after each group the wave stops once every row has failed both
+// trends. Writes the fit words to fit[].
+template <int P, bool NEG, int KB, int WPL>
+__device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, int64_t w64,
+                                            int wlim, const int32_t *s_pd, int k, int t, int w,
+                                            uint64_t *fit) {
     constexpr int NP = P > 0 ? P : 1;
     constexpr int B = PartialSum<KB>::B;
     uint32_t start = __builtin_amdgcn_readfirstlane((1u << P) - (uint32_t)(t + 1));
     // opaque to the optimiser: keeps the start planes from being hoisted out
     // of the caller's chunk loop and held in registers across it
     asm volatile("" : "+s"(start));
-    uint64_t D[NP], U[NP];
+    bool active[WPL];
+    uint64_t D[WPL][NP], U[WPL][NP], dov[WPL], uov[WPL];
 #pragma unroll
-    for (int p = 0; p < P; p++) D[p] = U[p] = ((start >> p) & 1u) ? ~0ull : 0ull;
-    uint64_t dov = 0, uov = 0;
+    for (int v = 0; v < WPL; v++) {
+        active[v] = w + kWave * v < wlim;
+#pragma unroll
+        for (int p = 0; p < P; p++) D[v][p] = U[v][p] = ((start >> p) & 1u) ? ~0ull : 0ull;
+        dov[v] = uov[v] = 0;
+    }
     int j = 1;
     while (j < k) {
         const int n = (k - j) < KB ? (k - j) : KB;
-        uint64_t up[KB], dn[KB];
+        uint64_t up[WPL][KB], dn[WPL][KB];
 #pragma unroll
         for (int q = 0; q < KB; q++) {
-            uint64_t x = 0;
+            uint64_t x[WPL];
+#pragma unroll
+            for (int v = 0; v < WPL; v++) x[v] = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
                 const uint64_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w64;
-                const uint64_t bits = active ? vec[w] : 0ull;
-                x = pd < 0 ? ~bits : bits;  // 1 = up-step in this row
+#pragma unroll
+                for (int v = 0; v < WPL; v++) {
+                    const uint64_t bits = active[v] ? vec[w + kWave * v] : 0ull;
+                    x[v] = pd < 0 ? ~bits : bits;  // 1 = up-step in this row
+                }
             }
             const uint64_t vm = q < n ? ~0ull : 0ull;  // steps past the end count nothing
-            up[q] = x & vm;
-            dn[q] = ~x & vm;
+#pragma unroll
+            for (int v = 0; v < WPL; v++) {
+                up[v][q] = x[v] & vm;
+                dn[v][q] = ~x[v] & vm;
+            }
         }
-        uint64_t S[B];
-        PartialSum<KB>::sum(dn, S);
-        add_sticky<P, B>(D, S, dov);
-        if (NEG) {
-            PartialSum<KB>::sum(up, S);
-            add_sticky<P, B>(U, S, uov);
+        bool live = false;
+#pragma unroll
+        for (int v = 0; v < WPL; v++) {
+            uint64_t S[B];
+            PartialSum<KB>::sum(dn[v], S);
+            add_sticky<P, B>(D[v], S, dov[v]);
+            if (NEG) {
+                PartialSum<KB>::sum(up[v], S);
+                add_sticky<P, B>(U[v], S, uov[v]);
+            }
+            const uint64_t dead = dov[v] & (NEG ? uov[v] : ~0ull);
+            live |= active[v] && dead != ~0ull;
         }
         j += n;
-        const uint64_t dead = dov & (NEG ? uov : ~0ull);
-        if (__ballot(active && dead != ~0ull) == 0) break;
+        if (__ballot(live) == 0) break;
     }
-    return ~dov | (NEG ? ~uov : 0ull);
+#pragma unroll
+    for (int v = 0; v < WPL; v++) fit[v] = ~dov[v] | (NEG ? ~uov[v] : 0ull);
 }
 
-// Widest counter the pair path instantiates for KB steps per group: what
-// keeps the evaluation kernel within 64 VGPRs (8 waves per SIMD). Items with
-// a larger tolerance (t >= 2^P; at approx 0.85 none up to 512 columns with
-// KB = 2) take the gather form.
-template <int KB>
+// Widest counter the pair path instantiates for KB steps per group and WPL
+// words per lane: what keeps the evaluation kernel within 64 VGPRs (8 waves
+// per SIMD). Items with a larger tolerance (t >= 2^P) take the gather form.
+template <int KB, int WPL>
 struct PairLimit {
-    static constexpr int P = KB == 4 ? 5 : 7;
+    static constexpr int P = WPL == 1 ? (KB == 4 ? 4 : 6) : (KB == 4 ? 3 : 4);
     static constexpr int T = (1 << P) - 1;
 };
 
-template <int PP, int MAXP, bool NEG, int KB>
-__device__ __forceinline__ uint64_t pairs_width(int P, const uint64_t *pairs, int64_t w64,
-                                                const int32_t *s_pd, int k, int t, int w,
-                                                bool active) {
+template <int PP, int MAXP, bool NEG, int KB, int WPL>
+__device__ __forceinline__ void pairs_width(int P, const uint64_t *pairs, int64_t w64, int wlim,
+                                            const int32_t *s_pd, int k, int t, int w,
+                                            uint64_t *fit) {
     if constexpr (PP == MAXP) {
-        return pairs_count<PP, NEG, KB>(pairs, w64, s_pd, k, t, w, active);
+        pairs_count<PP, NEG, KB, WPL>(pairs, w64, wlim, s_pd, k, t, w, fit);
     } else {
-        if (P == PP) return pairs_count<PP, NEG, KB>(pairs, w64, s_pd, k, t, w, active);
-        return pairs_width<PP + 1, MAXP, NEG, KB>(P, pairs, w64, s_pd, k, t, w, active);
+        if (P == PP) return pairs_count<PP, NEG, KB, WPL>(pairs, w64, wlim, s_pd, k, t, w, fit);
+        pairs_width<PP + 1, MAXP, NEG, KB, WPL>(P, pairs, w64, wlim, s_pd, k, t, w, fit);
     }
 }
 
-// Counter width for tolerance t <= PairLimit<KB>::T: the least P with
+// Counter width for tolerance t <= PairLimit<KB, WPL>::T: the least P with
 // 2^P >= t+1.
-template <bool NEG, int KB>
-__device__ __forceinline__ uint64_t pairs_dispatch(const uint64_t *pairs, int64_t w64,
-                                                   const int32_t *s_pd, int k, int t, int w,
-                                                   bool active) {
+template <bool NEG, int KB, int WPL>
+__device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, int64_t w64, int wlim,
+                                               const int32_t *s_pd, int k, int t, int w,
+                                               uint64_t *fit) {
     const int P = t == 0 ? 0 : 32 - __builtin_clz((unsigned)t);
-    return pairs_width<0, PairLimit<KB>::P, NEG, KB>(P, pairs, w64, s_pd, k, t, w, active);
+    pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL>(P, pairs, w64, wlim, s_pd, k, t, w, fit);
 }
 
-template <int KB>
+template <int KB, int WPL>
 __global__ void __launch_bounds__(kThreads)
-    eval_items_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ item_begins,
+    eval_items_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
                       int32_t njobs, int64_t total_items) {
     __shared__ int32_t s_buf[kWaves][EBIC_MAX_K];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t main_blocks = (total_items + kWaves - 1) / kWaves;
-    if ((int64_t)blockIdx.x >= main_blocks) {
-        // one trailing workgroup per job: the archive's per-column member
-        // masks, read by the reduction kernel
-        const int jb = (int)((int64_t)blockIdx.x - main_blocks);
-        if (jb >= njobs) return;
+    if ((int)blockIdx.x < njobs) {
+        // one leading workgroup per job (dispatched first, so it never
+        // lengthens the launch): the archive's per-column member masks, read
+        // by the reduction kernel
+        const int jb = (int)blockIdx.x;
         const DevJob &M = jobs[jb];
         if (!M.memb) return;
         for (int c = threadIdx.x; c < M.cols; c += kThreads) M.memb[c] = 0;
@@ -232,10 +250,13 @@ __global__ void __launch_bounds__(kThreads)
         }
         return;
     }
-    const int64_t item = (int64_t)blockIdx.x * kWaves + wave;
+    const int64_t item = ((int64_t)blockIdx.x - njobs) * kWaves + wave;
     if (item >= total_items) return;
-    const DevJob &J = jobs[find_job(item_begins, njobs, item)];
-    const int64_t local = item - J.item_begin;
+    // round-robin schedule: phase p interleaves the first njobs - p jobs
+    const int p = find_segment(sched, njobs, item);
+    const int64_t rel = item - sched[p], m = njobs - p;
+    const DevJob &J = jobs[rel % m];
+    const int64_t local = sched[njobs + p] + rel / m;
     const int32_t oi = (int32_t)(local / J.ipi), grp = (int32_t)(local % J.ipi);
     const int32_t ind = J.order ? J.order[oi] : oi;
     if (ind < 0 || ind >= J.pop_size) return;
@@ -247,7 +268,7 @@ __global__ void __launch_bounds__(kThreads)
     bool bad = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
     const int t = bad ? 0 : tol(k, J.approx_permille);
     // pair table when the batch has one and the counters fit; else gather
-    const bool use_pairs = J.mode == 1 && t <= PairLimit<KB>::T;
+    const bool use_pairs = J.mode == 1 && t <= PairLimit<KB, WPL>::T;
     if (!bad) {
         // stage the series (pair form: one descriptor per step; gather form:
         // each column's byte offset)
@@ -277,28 +298,40 @@ __global__ void __launch_bounds__(kThreads)
         return;
     }
     const bool neg = J.negative_trends != 0;
-    for (int32_t chunk = ch0; chunk < ch1; chunk++) {
-        const int w = chunk * 64 + lane;  // this lane's 64-row word
+    // WPL chunks at a time: lane words c0*64 + lane + 64 v, v < WPL
+    for (int32_t c0 = ch0; c0 < ch1; c0 += WPL) {
         if (use_pairs) {
-            const bool active = w < J.w64;
-            uint64_t fit = neg ? pairs_dispatch<true, KB>(J.pairs, J.w64, s, k, t, w, active)
-                               : pairs_dispatch<false, KB>(J.pairs, J.w64, s, k, t, w, active);
-            const int r0 = w * 64;
-            if (r0 + 64 > J.rows) fit &= r0 >= J.rows ? 0ull : ((1ull << (J.rows - r0)) - 1ull);
-            if (active) J.support[(int64_t)ind * J.w64 + w] = fit;
+            const int w = c0 * 64 + lane;
+            const int wlim = J.w64 < ch1 * 64 ? J.w64 : ch1 * 64;
+            uint64_t fit[WPL];
+            if (neg)
+                pairs_dispatch<true, KB, WPL>(J.pairs, J.w64, wlim, s, k, t, w, fit);
+            else
+                pairs_dispatch<false, KB, WPL>(J.pairs, J.w64, wlim, s, k, t, w, fit);
+#pragma unroll
+            for (int v = 0; v < WPL; v++) {
+                const int wv = w + kWave * v, r0 = wv * 64;
+                uint64_t f = fit[v];
+                if (r0 + 64 > J.rows) f &= r0 >= J.rows ? 0ull : ((1ull << (J.rows - r0)) - 1ull);
+                if (wv < wlim) J.support[(int64_t)ind * J.w64 + wv] = f;
+            }
         } else {
             const __amdgpu_buffer_rsrc_t rs =
                 make_rsrc(J.ranks, (uint32_t)((size_t)J.cols * J.rows_pad * 2));
-            int lo = 0, hi = 0;
-            const int b0 = chunk * 64;
-            for (int b = 0; b < 64 && b0 + b < J.w64; b++) {
-                const int r = (b0 + b) * kWave + lane;
-                const uint64_t word = block_support(rs, s, k, t, neg, r * 2, r < J.rows);
-                lo = writelane((int)(uint32_t)word, b, lo);
-                hi = writelane((int)(uint32_t)(word >> 32), b, hi);
+            for (int32_t chunk = c0; chunk < c0 + WPL && chunk < ch1; chunk++) {
+                const int w = chunk * 64 + lane;  // this lane's 64-row word
+                int lo = 0, hi = 0;
+                const int b0 = chunk * 64;
+                for (int b = 0; b < 64 && b0 + b < J.w64; b++) {
+                    const int r = (b0 + b) * kWave + lane;
+                    const uint64_t word = block_support(rs, s, k, t, neg, r * 2, r < J.rows);
+                    lo = writelane((int)(uint32_t)word, b, lo);
+                    hi = writelane((int)(uint32_t)(word >> 32), b, hi);
+                }
+                if (w < J.w64)
+                    J.support[(int64_t)ind * J.w64 + w] =
+                        ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
             }
-            if (w < J.w64)
-                J.support[(int64_t)ind * J.w64 + w] = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
         }
     }
 }
@@ -310,7 +343,7 @@ __global__ void __launch_bounds__(kThreads)
 // overlap and fitness. When the size score is 0 the fitness is 0 whatever
 // the penalty, so the members are only visited for the overlap output.
 // Shared columns come from per-column member masks (bit j of memb[c] =
-// member j holds column c), built once per run by trailing workgroups of the
+// member j holds column c), built once per run by leading workgroups of the
 // evaluation kernel: each lane takes one column of the series, and g_j is
 // one ballot. Since h <= n, a
 // member can only overlap too much when 1000 g > theta k, so the shared rows
@@ -324,7 +357,7 @@ __global__ void __launch_bounds__(kThreads)
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int64_t gid = (int64_t)blockIdx.x * kWaves + wave;
     if (gid >= total_ind) return;
-    const DevJob &J = jobs[find_job(ind_begins, njobs, gid)];
+    const DevJob &J = jobs[find_segment(ind_begins, njobs, gid)];
     const int32_t i = (int32_t)(gid - J.ind_begin);
     const int32_t beg = J.pop_off[i], end = J.pop_off[i + 1];
     const int k = end - beg;
@@ -473,9 +506,9 @@ struct Batch {
     int device = 0;
     int32_t flags = 0;
     std::vector<DevJob> jobs;
-    DevJob *d_jobs = nullptr;  // device: DevJob[njobs], then the two start arrays
-    int64_t *d_item_begins = nullptr;
-    int64_t *d_ind_begins = nullptr;
+    DevJob *d_jobs = nullptr;  // device: DevJob[njobs] by item count, descending; then
+    int64_t *d_sched = nullptr;       // the item schedule (phase starts, phase rounds)
+    int64_t *d_ind_begins = nullptr;  // and each device job's first individual
     int32_t cap_jobs = 0;      // capacity of d_jobs / h_stage
     void *h_stage = nullptr;   // pinned staging of the table
     std::vector<void *> scratch;
@@ -484,7 +517,8 @@ struct Batch {
     uint64_t *d_memb = nullptr;  // member masks of all jobs with an archive
     size_t memb_cap = 0;       // words
     int kb = 2;                // pair-bitmap loads in flight (template)
-    int cpi = 1;               // chunks per item
+    int wpl = 1;               // 64-row words per lane (template)
+    int cpi = 1;               // chunk groups (of wpl chunks) per item
     int epi_q = 4;             // reduction kernel: support words per lane in registers
     bool tuned = false;
     hipGraph_t graph = nullptr;
@@ -558,23 +592,25 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
     return d;
 }
 
-// Lay the items out for `cpi` chunks per item (item starts of every job)
+// Lay the items out for `cpi` groups of b->wpl chunks per item
 // and queue the table's upload on `stream` from pinned staging, growing the
 // device table when needed.
 int upload_table(Batch *b, int cpi, hipStream_t stream) {
     b->cpi = cpi;
-    int64_t items = 0, inds = 0;
-    for (DevJob &d : b->jobs) {
-        d.cpi = cpi < d.nchunks ? cpi : d.nchunks;
+    const int32_t n = b->njobs;
+    int64_t items = 0;
+    std::vector<int64_t> count(n);
+    for (int i = 0; i < n; i++) {
+        DevJob &d = b->jobs[i];
+        // whole groups per item, so that no two items share a group
+        const int32_t cpc = cpi * b->wpl;
+        d.cpi = cpc < d.nchunks ? cpc : d.nchunks;
         if (d.cpi < 1) d.cpi = 1;
         d.ipi = (d.nchunks + d.cpi - 1) / d.cpi;
-        d.item_begin = items;
-        d.ind_begin = inds;
-        items += (int64_t)d.pop_size * d.ipi;
-        inds += d.pop_size;
+        count[i] = (int64_t)d.pop_size * d.ipi;
+        items += count[i];
     }
     b->total_items = items;
-    b->total_ind = inds;
     int32_t wmax = 0;
     for (const DevJob &d : b->jobs) wmax = d.w64 > wmax ? d.w64 : wmax;
     b->epi_q = wmax <= 2 * kWave ? 2 : wmax <= 4 * kWave ? 4 : wmax <= 8 * kWave ? 8 : kEpiMaxQ;
@@ -593,8 +629,7 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
         d.memb = d.arch_size > 0 ? b->d_memb + at : nullptr;
         at += d.arch_size > 0 ? (size_t)d.cols : 0;
     }
-    const int32_t n = b->njobs;
-    const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 2 * n;
+    const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 3 * n;
     if (n > b->cap_jobs) {
         if (b->d_jobs) (void)hipFree(b->d_jobs);
         if (b->h_stage) (void)hipHostFree(b->h_stage);
@@ -607,22 +642,43 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
         EBIC_HIP(hipHostMalloc(&b->h_stage, bytes, hipHostMallocDefault));
         b->cap_jobs = n;
     }
-    b->d_item_begins = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) + jbytes);
-    b->d_ind_begins = b->d_item_begins + n;
+    b->d_sched = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) + jbytes);
+    b->d_ind_begins = b->d_sched + 2 * n;
+    // Items of all jobs are interleaved round-robin, so that each job's
+    // longest-first order holds across the batch: with the jobs stored by
+    // item count, descending, phase p takes one item of each of the first
+    // n - p jobs per round, over the rounds that those jobs still have.
+    std::vector<int> perm(n);
+    for (int i = 0; i < n; i++) perm[i] = i;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int a, int c) { return count[a] > count[c]; });
     char *h = static_cast<char *>(b->h_stage);
-    std::memcpy(h, b->jobs.data(), jbytes);
-    int64_t *hb = reinterpret_cast<int64_t *>(h + jbytes);
-    for (int i = 0; i < n; i++) {
-        hb[i] = b->jobs[i].item_begin;
-        hb[n + i] = b->jobs[i].ind_begin;
+    DevJob *hj = reinterpret_cast<DevJob *>(h);
+    int64_t *ph_start = reinterpret_cast<int64_t *>(h + jbytes);
+    int64_t *ph_round = ph_start + n;
+    int64_t *ind_begin = ph_start + 2 * n;
+    int64_t inds = 0, start = 0;
+    for (int p = 0; p < n; p++) {
+        hj[p] = b->jobs[perm[p]];
+        hj[p].ind_begin = inds;
+        inds += hj[p].pop_size;
+        ind_begin[p] = hj[p].ind_begin;
+        const int64_t first = p == 0 ? 0 : count[perm[n - p]];
+        ph_start[p] = start;
+        ph_round[p] = first;
+        start += (int64_t)(n - p) * (count[perm[n - 1 - p]] - first);
     }
+    b->total_ind = inds;
     EBIC_HIP(hipMemcpyAsync(b->d_jobs, h, bytes, hipMemcpyHostToDevice, stream));
     return EBIC_OK;
 }
 
-void *eval_kernel_fn(int kb) {
-    return kb == 4 ? reinterpret_cast<void *>(eval_items_kernel<4>)
-                   : reinterpret_cast<void *>(eval_items_kernel<2>);
+void *eval_kernel_fn(int kb, int wpl) {
+    if (wpl == 2)
+        return kb == 4 ? reinterpret_cast<void *>(eval_items_kernel<4, 2>)
+                       : reinterpret_cast<void *>(eval_items_kernel<2, 2>);
+    return kb == 4 ? reinterpret_cast<void *>(eval_items_kernel<4, 1>)
+                   : reinterpret_cast<void *>(eval_items_kernel<2, 1>);
 }
 
 void *epilogue_kernel_fn(int q) {
@@ -650,14 +706,9 @@ unsigned eval_grid(const Batch *b) {
 }
 
 int launch_eval(Batch *b, hipStream_t stream) {
-    const unsigned grid = eval_grid(b);
-    if (b->kb == 4)
-        eval_items_kernel<4><<<grid, kThreads, 0, stream>>>(b->d_jobs, b->d_item_begins,
-                                                            b->njobs, b->total_items);
-    else
-        eval_items_kernel<2><<<grid, kThreads, 0, stream>>>(b->d_jobs, b->d_item_begins,
-                                                            b->njobs, b->total_items);
-    EBIC_HIP(hipGetLastError());
+    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_items};
+    EBIC_HIP(hipLaunchKernel(eval_kernel_fn(b->kb, b->wpl), dim3(eval_grid(b)), dim3(kThreads),
+                             args, 0, stream));
     return EBIC_OK;
 }
 
@@ -668,10 +719,10 @@ int build_graph(Batch *b) {
     b->graph = nullptr;
     // two kernel nodes, evaluation then reduction (no stream capture)
     hipGraphNode_t na = nullptr, nb = nullptr;
-    void *args_a[] = {&b->d_jobs, &b->d_item_begins, &b->njobs, &b->total_items};
+    void *args_a[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_items};
     void *args_b[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
     hipKernelNodeParams pa{}, pb{};
-    pa.func = eval_kernel_fn(b->kb);
+    pa.func = eval_kernel_fn(b->kb, b->wpl);
     pa.gridDim = dim3(eval_grid(b));
     pa.blockDim = dim3(kThreads);
     pa.kernelParams = args_a;
@@ -687,13 +738,20 @@ int build_graph(Batch *b) {
     return EBIC_OK;
 }
 
-// ---- autotuner: chunks per item x loads in flight, cached per shape ----
+// ---- autotuner: item shapes, cached per batch shape ----
 
 constexpr int kTuneLaunches = 10;     // launches per timed sample
 constexpr float kTuneMargin = 0.98f;  // required gain over the current best
 
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;
+struct Shape {
+    int cpi, kb, wpl;
+};
+std::map<std::string, Shape> g_tune;
+
+bool valid_shape(int cpi, int kb, int wpl) {
+    return (cpi == 1 || cpi == 2 || cpi == 4) && (kb == 2 || kb == 4) && (wpl == 1 || wpl == 2);
+}
 bool g_tune_loaded = false;
 
 const char *tune_file() { return getenv("EBIC_TUNE_CACHE"); }
@@ -710,17 +768,17 @@ void tune_load_locked() {
     size_t got;
     while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
     fclose(f);
-    // entries look like  "key": [cpi, kb]  inside one JSON object
+    // entries look like  "key": [cpi, kb, wpl]  inside one JSON object
     size_t pos = 0;
     for (;;) {
         const size_t q0 = text.find('"', pos);
         if (q0 == std::string::npos) break;
         const size_t q1 = text.find('"', q0 + 1);
         if (q1 == std::string::npos) break;
-        int a = 0, c = 0;
-        if (sscanf(text.c_str() + q1 + 1, " : [ %d , %d ]", &a, &c) == 2 &&
-            (a == 1 || a == 2 || a == 4) && (c == 2 || c == 4))
-            g_tune[text.substr(q0 + 1, q1 - q0 - 1)] = {a, c};
+        int a = 0, c = 0, v = 0;
+        if (sscanf(text.c_str() + q1 + 1, " : [ %d , %d , %d ]", &a, &c, &v) == 3 &&
+            valid_shape(a, c, v))
+            g_tune[text.substr(q0 + 1, q1 - q0 - 1)] = {a, c, v};
         const size_t close = text.find(']', q1);
         if (close == std::string::npos) break;
         pos = close + 1;
@@ -735,8 +793,8 @@ void tune_save_locked() {
     fprintf(f, "{");
     bool first = true;
     for (auto &kv : g_tune) {
-        fprintf(f, "%s\n \"%s\": [%d, %d]", first ? "" : ",", kv.first.c_str(), kv.second.first,
-                kv.second.second);
+        fprintf(f, "%s\n \"%s\": [%d, %d, %d]", first ? "" : ",", kv.first.c_str(),
+                kv.second.cpi, kv.second.kb, kv.second.wpl);
         first = false;
     }
     fprintf(f, "\n}\n");
@@ -754,9 +812,10 @@ std::string tune_key(const Batch *b) {
     return buf;
 }
 
-// Time every (chunks per item, loads in flight) candidate on this batch's
-// inputs with HIP events around blocks of evaluation launches (median of 3
-// blocks) and keep the fastest. Results never depend on the choice.
+// Time every item shape (chunk groups per item, loads in flight, words per
+// lane) on this batch's inputs with HIP events around blocks of evaluation
+// launches (median of 3 blocks) and keep the fastest. Results never depend
+// on the choice.
 int tune(Batch *b, hipStream_t stream) {
     b->tuned = true;
     const std::string key = tune_key(b);
@@ -765,8 +824,9 @@ int tune(Batch *b, hipStream_t stream) {
         tune_load_locked();
         auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            b->kb = it->second.second;
-            return upload_table(b, it->second.first, stream);
+            b->kb = it->second.kb;
+            b->wpl = it->second.wpl;
+            return upload_table(b, it->second.cpi, stream);
         }
     }
     int32_t maxch = 1;
@@ -775,31 +835,36 @@ int tune(Batch *b, hipStream_t stream) {
     EBIC_HIP(hipEventCreate(&e0));
     EBIC_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    int best_cpi = 1, best_kb = 2;
+    Shape pick{1, 2, 1};
     int rc = EBIC_OK;
-    for (int cpi : {1, 2, 4}) {
-        if (cpi > 1 && cpi > maxch) break;
-        for (int kb : {2, 4}) {
-            b->kb = kb;
-            rc = upload_table(b, cpi, stream);
-            if (rc == EBIC_OK) rc = launch_eval(b, stream);  // warm-up
-            float t[3];
-            for (int r = 0; r < 3 && rc == EBIC_OK; r++) {
-                (void)hipEventRecord(e0, stream);
-                for (int l = 0; l < kTuneLaunches && rc == EBIC_OK; l++) rc = launch_eval(b, stream);
-                (void)hipEventRecord(e1, stream);
-                (void)hipEventSynchronize(e1);
-                (void)hipEventElapsedTime(&t[r], e0, e1);
+    for (int wpl : {1, 2}) {
+        if (wpl > maxch) break;
+        for (int cpi : {1, 2, 4}) {
+            if (cpi > 1 && cpi * wpl > maxch) break;
+            for (int kb : {2, 4}) {
+                b->kb = kb;
+                b->wpl = wpl;
+                rc = upload_table(b, cpi, stream);
+                if (rc == EBIC_OK) rc = launch_eval(b, stream);  // warm-up
+                float t[3];
+                for (int r = 0; r < 3 && rc == EBIC_OK; r++) {
+                    (void)hipEventRecord(e0, stream);
+                    for (int l = 0; l < kTuneLaunches && rc == EBIC_OK; l++)
+                        rc = launch_eval(b, stream);
+                    (void)hipEventRecord(e1, stream);
+                    (void)hipEventSynchronize(e1);
+                    (void)hipEventElapsedTime(&t[r], e0, e1);
+                }
+                if (rc) break;
+                std::sort(t, t + 3);
+                // a later (larger) shape must win clearly, so that timing
+                // noise does not flip the choice from run to run
+                if (t[1] < best * kTuneMargin) {
+                    best = t[1];
+                    pick = {cpi, kb, wpl};
+                }
             }
             if (rc) break;
-            std::sort(t, t + 3);
-            // a later (larger) shape must win clearly, so that timing noise
-            // does not flip the choice from run to run
-            if (t[1] < best * kTuneMargin) {
-                best = t[1];
-                best_cpi = cpi;
-                best_kb = kb;
-            }
         }
         if (rc) break;
     }
@@ -808,11 +873,12 @@ int tune(Batch *b, hipStream_t stream) {
     if (rc) return rc;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune[key] = {best_cpi, best_kb};
+        g_tune[key] = pick;
         tune_save_locked();
     }
-    b->kb = best_kb;
-    return upload_table(b, best_cpi, stream);
+    b->kb = pick.kb;
+    b->wpl = pick.wpl;
+    return upload_table(b, pick.cpi, stream);
 }
 
 }  // namespace
@@ -916,24 +982,26 @@ int batch_run(Batch *b, hipStream_t stream) {
     return EBIC_OK;
 }
 
-int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb) {
+int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb, int32_t *wpl) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (cpi) *cpi = b->cpi;
     if (kb) *kb = b->kb;
+    if (wpl) *wpl = b->wpl;
     return EBIC_OK;
 }
 
-int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb) {
+int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb, int32_t wpl) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
-    if (!(cpi == 1 || cpi == 2 || cpi == 4) || !(kb == 2 || kb == 4))
-        return fail(EBIC_ERR_INVALID_ARG, "item shape (%d, %d): chunks per item 1, 2 or 4, loads "
-                    "in flight 2 or 4", cpi, kb);
+    if (!valid_shape(cpi, kb, wpl))
+        return fail(EBIC_ERR_INVALID_ARG, "item shape (%d, %d, %d): chunk groups per item 1, 2 "
+                    "or 4, loads in flight 2 or 4, words per lane 1 or 2", cpi, kb, wpl);
     // a graph holds the old grid and kernel: rebuilt on the next run
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
     b->kb = kb;
+    b->wpl = wpl;
     b->tuned = true;
     int rc = upload_table(b, cpi, nullptr);
     if (rc) return rc;

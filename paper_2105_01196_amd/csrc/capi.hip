@@ -226,14 +226,18 @@ int ebic_batch_destroy(ebic_batch *b) {
     return batch_destroy(reinterpret_cast<Batch *>(b));
 }
 
-int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight) {
+int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight,
+                      int32_t *words_per_lane) {
     clear_error();
-    return batch_tuning(reinterpret_cast<Batch *>(b), chunks_per_item, loads_in_flight);
+    return batch_tuning(reinterpret_cast<Batch *>(b), chunks_per_item, loads_in_flight,
+                        words_per_lane);
 }
 
-int ebic_batch_set_tuning(ebic_batch *b, int32_t chunks_per_item, int32_t loads_in_flight) {
+int ebic_batch_set_tuning(ebic_batch *b, int32_t chunks_per_item, int32_t loads_in_flight,
+                          int32_t words_per_lane) {
     clear_error();
-    return batch_set_tuning(reinterpret_cast<Batch *>(b), chunks_per_item, loads_in_flight);
+    return batch_set_tuning(reinterpret_cast<Batch *>(b), chunks_per_item, loads_in_flight,
+                            words_per_lane);
 }
 
 int ebic_batch_profile(ebic_batch *b, int32_t n) {

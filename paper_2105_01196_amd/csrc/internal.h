@@ -82,8 +82,8 @@ struct Batch;
 int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out);
 int batch_run(Batch *b, hipStream_t stream);
 int batch_set(Batch **b, const ebic_job *jobs, int32_t njobs, hipStream_t stream);
-int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb);
-int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb);
+int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb, int32_t *wpl);
+int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb, int32_t wpl);
 int batch_destroy(Batch *b);
 int batch_profile(Batch *b, int32_t n);
 int batch_timings(Batch *b, float *ms_eval, float *ms_reduce, int32_t *n);

@@ -137,8 +137,9 @@ _SIGNATURES = {
     "ebic_server_stats": (ctypes.c_int, [_vp, ctypes.POINTER(ebic_server_metrics)]),
     "ebic_server_destroy": (ctypes.c_int, [_vp]),
     "ebic_batch_profile": (ctypes.c_int, [_vp, _i32]),
-    "ebic_batch_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
-    "ebic_batch_set_tuning": (ctypes.c_int, [_vp, _i32, _i32]),
+    "ebic_batch_tuning": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                         ctypes.POINTER(_i32)]),
+    "ebic_batch_set_tuning": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
     "ebic_batch_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(_i32)]),
@@ -437,14 +438,17 @@ class Batch:
         _check(lib().ebic_batch_run(self.handle, _stream(stream)))
 
     def tuning(self):
-        """(chunks per item, loads in flight) the batch uses."""
-        a, b = _i32(), _i32()
-        _check(lib().ebic_batch_tuning(self.handle, ctypes.byref(a), ctypes.byref(b)))
-        return int(a.value), int(b.value)
+        """(chunk groups per item, loads in flight, words per lane) in use."""
+        a, b, c = _i32(), _i32(), _i32()
+        _check(lib().ebic_batch_tuning(self.handle, ctypes.byref(a), ctypes.byref(b),
+                                       ctypes.byref(c)))
+        return int(a.value), int(b.value), int(c.value)
 
-    def set_tuning(self, chunks_per_item: int, loads_in_flight: int) -> None:
+    def set_tuning(self, chunks_per_item: int, loads_in_flight: int,
+                   words_per_lane: int = 1) -> None:
         """Pin the item shape; later runs use it and do not tune."""
-        _check(lib().ebic_batch_set_tuning(self.handle, chunks_per_item, loads_in_flight))
+        _check(lib().ebic_batch_set_tuning(self.handle, chunks_per_item, loads_in_flight,
+                                           words_per_lane))
 
     def profile(self, n: int) -> None:
         """Record kernel times for the next n runs."""

@@ -95,5 +95,5 @@ def test_run_rejects_bad_parameters_on_host():
 def test_batch_set_tuning_rejects_null_batch_on_host():
     from paper_2105_01196_amd import ebic
     L = ebic.lib()
-    assert L.ebic_batch_set_tuning(None, 1, 2) == ebic.EBIC_ERR_INVALID_ARG
+    assert L.ebic_batch_set_tuning(None, 1, 2, 1) == ebic.EBIC_ERR_INVALID_ARG
     assert L.ebic_last_error()

@@ -158,7 +158,8 @@ def _approx_for(k, t):
     return None
 
 
-@pytest.mark.parametrize("shape", [(1, 2), (1, 4), (2, 2), (4, 4)])
+@pytest.mark.parametrize("shape", [(1, 2, 1), (1, 4, 1), (2, 2, 1), (4, 4, 1), (1, 2, 2),
+                                   (1, 4, 2), (2, 2, 2)])
 def test_step_counts_at_counter_boundaries(E, shape):
     """Every count of steps against a trend, from 0 to k-1, meets tolerances
     at each counter width boundary (t = 2^P - 1 and 2^P) and beyond the
@@ -193,11 +194,11 @@ def test_set_tuning_rejects_other_shapes(E):
     m = _matrix(E, X)
     pop = E.ebic_population_upload([[0, 1, 2]], 20)
     b = E.Batch([E.make_job(m, pop, None, E.make_params(**_kw()))])
-    for bad in ((3, 2), (1, 3), (0, 2), (8, 4)):
+    for bad in ((3, 2, 1), (1, 3, 1), (0, 2, 1), (8, 4, 1), (1, 2, 3), (1, 2, 0)):
         with pytest.raises(Exception):
             b.set_tuning(*bad)
-    b.set_tuning(2, 4)
-    assert b.tuning() == (2, 4)
+    b.set_tuning(2, 4, 2)
+    assert b.tuning() == (2, 4, 2)
     b.close()
 
 
@@ -219,6 +220,42 @@ def test_multi_job_batch(E):
     torch.cuda.synchronize()
     for job, (X, seqs, kw) in zip(jobs, data):
         _check_job(E, job, X, seqs, kw)
+    b.close()
+
+
+@pytest.mark.parametrize("shape", [(1, 2, 1), (2, 4, 1), (4, 2, 1), (1, 2, 2), (2, 4, 2)])
+def test_uneven_jobs_interleaved(E, shape):
+    """Jobs of uneven item counts (including an empty population) share one
+    launch through the round-robin item schedule and its phases; each job
+    equals its own oracle evaluation, archives and processing orders
+    included."""
+    specs = [(2, 37, True), (0, 0, False), (2, 513, True), (1, 5, False), (3, 200, True),
+             (1, 300, True)]
+    jobs, data = [], []
+    for n, (wi, P, with_arch) in enumerate(specs):
+        case = synth.workload_matrix(wi)
+        seqs = synth.workload_population(wi, case, P=max(P, 1), seed=synth.POP_SEED + 50 + n)[:P]
+        kw = _kw(approx_permille=(850, 700, 900, 1000, 850, 600)[n], negative_trends=n % 2)
+        m = _matrix(E, case.X)
+        pop = E.ebic_population_upload(seqs, case.C)
+        if P:
+            E.set_order(pop, E.longest_first(seqs))
+        arch = oarch = None
+        if with_arch and P:
+            ev = oracle.evaluate(case.X, seqs, params=oracle.make_params(**kw), nthreads=NCPU)
+            top = [int(i) for i in np.argsort(-ev.score, kind="stable")[:min(8, P)]]
+            series = [seqs[i] for i in top]
+            arch = E.make_archive(E.flags_to_support(ev.support[top], m.words), series)
+            oarch = oracle.Archive(ev.support[top], series)
+        jobs.append(E.make_job(m, pop, arch, E.make_params(**kw)))
+        data.append((case.X, seqs, kw, oarch))
+    b = E.Batch(jobs)
+    b.set_tuning(*shape)
+    b.run()
+    torch.cuda.synchronize()
+    for job, (X, seqs, kw, oarch) in zip(jobs, data):
+        if seqs:
+            _check_job(E, job, X, seqs, kw, oarch)
     b.close()
 
 
@@ -302,8 +339,8 @@ def test_autotuned_batch_identical(E, tmp_path, monkeypatch):
             for x, y in ((plain.count, job.out.count), (plain.fitness, job.out.fitness),
                          (plain.support, job.out.support)):
                 assert torch.equal(x, y)
-        cpi, kb = b.tuning()
-        assert cpi in (1, 2, 4) and kb in (2, 4)
+        cpi, kb, wpl = b.tuning()
+        assert cpi in (1, 2, 4) and kb in (2, 4) and wpl in (1, 2)
         b.close()
     text = cache.read_text()
     assert "_i777_j1" in text and "[" in text
