@@ -194,8 +194,8 @@ typedef struct ebic_job {
 typedef struct ebic_batch ebic_batch;
 
 /* Batched evaluation (Sec. 2.4, steps 2-3 and 7, for several populations
- * at once): every individual of every job in one launch of the evaluation
- * kernel plus one launch of the reduction kernel, each job with its own
+ * at once): every individual of every job in one kernel launch (a
+ * workgroup per individual, counting and reducing it), each job with its own
  * matrix (pair-table form when the matrix has a table, else the gather
  * form), archive and parameters. Results are identical, bit for bit, to
  * ebic_evaluate on each job alone. create copies the job table to the
@@ -205,11 +205,12 @@ typedef struct ebic_batch ebic_batch;
  * batch. Errors: EBIC_ERR_INVALID_ARG (as ebic_evaluate, per job),
  * EBIC_ERR_OOM, EBIC_ERR_DEVICE. Runs of one batch must not overlap. */
 int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_batch **out);
-/* Item shape of the evaluation kernel: a wave takes one item, i.e.
- * chunks_per_item groups (1, 2 or 4) of words_per_lane (1 or 2) chunks of
- * 4,096 rows, walking a group's chunks together (each lane holds one 64-row
- * word of each), with loads_in_flight (2 or 4) pair-bitmap loads issued per
- * group of steps. With EBIC_BATCH_TUNE the first run times every candidate
+/* Item shape of the kernel: a wave takes one item of its individual's rows,
+ * i.e. chunks_per_item groups (1, 2 or 4) of words_per_lane (1 or 2) chunks
+ * of 4,096 rows, walking a group's chunks together (each lane holds one
+ * 64-row word of each), with loads_in_flight (2 or 4) pair-bitmap loads
+ * issued per group of steps (an individual with more than 16 items gets
+ * proportionally larger ones). With EBIC_BATCH_TUNE the first run times every candidate
  * shape on the batch's own inputs, waits for the timings (that run is
  * synchronous), keeps the fastest, and caches the choice per batch shape in
  * the process and, when the environment variable EBIC_TUNE_CACHE names a
@@ -227,13 +228,12 @@ int ebic_batch_run(ebic_batch *b, void *stream);
 int ebic_batch_destroy(ebic_batch *b);
 
 /* Kernel timing of a batch (metrics). ebic_batch_profile(b, n) makes the
- * next n runs record HIP events around the evaluation kernel and the
- * reduction kernel (n = 0 turns it off; graph-backed batches record around
- * the whole graph, reported as evaluation time). ebic_batch_timings waits
- * for the recorded runs and writes up to *n per-run times in milliseconds
- * (ms_reduce may be NULL); *n returns the number written. */
+ * next n runs record HIP events around the kernel (or the graph) on the
+ * run's stream (n = 0 turns it off). ebic_batch_timings waits for the
+ * recorded runs and writes up to *n per-run times in milliseconds to ms;
+ * *n returns the number written. */
 int ebic_batch_profile(ebic_batch *b, int32_t n);
-int ebic_batch_timings(ebic_batch *b, float *ms_eval, float *ms_reduce, int32_t *n);
+int ebic_batch_timings(ebic_batch *b, float *ms, int32_t *n);
 
 /* One-shot batched evaluation: create, run, wait, destroy. Synchronous. */
 int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream);

@@ -1,19 +1,20 @@
 // Batched evaluation: many populations (of one or several jobs, each with
-// its own matrix, archive and parameters) in one launch of two kernels.
+// its own matrix, archive and parameters) in one kernel launch.
 //
-// Kernel A splits every individual into items of 4096 rows (or a few such
-// chunks) and gives each item to one wavefront; items of all jobs form one
-// flat index space, so a single launch covers the whole batch, individuals
-// of uneven length included. With a pair table a lane tests 64 rows at once:
-// each step of the series is one 64-bit load of the pair's bitmap, and the
-// rows' steps against each trend are counted bit-sliced in a counter that
-// starts at 2^P - (t+1) and so carries out of its top plane on the (t+1)-th
-// such step; a sticky carry flag per trend then decides the row, with no
-// compares. Without a table the item runs the gather form (lane = row) over
-// its 64-row blocks. Kernel B then reduces each individual's support words
-// into the count, the rows shared with each archive member, and the FP64
-// fitness. The paper sends the whole population to the GPU at once
-// (Sec. 2.4, step 2); here several populations share the launch.
+// A workgroup takes one individual and splits its rows into items of 4096
+// rows (or a few such chunks), one wave each; individuals of all jobs form
+// one flat index space, so a single launch covers the whole batch,
+// individuals of uneven length included. With a pair table a lane tests 64
+// rows at once: each step of the series is one 64-bit load of the pair's
+// bitmap, and the rows' steps against each trend are counted bit-sliced in
+// a counter that starts at 2^P - (t+1) and so carries out of its top plane
+// on the (t+1)-th such step; a sticky carry flag per trend then decides the
+// row, with no compares. Without a table the item runs the gather form
+// (lane = row) over its 64-row blocks. The last wave of the workgroup to
+// finish reduces the individual: the count, the rows shared with each
+// archive member, and the FP64 fitness. The paper sends the whole
+// population to the GPU at once (Sec. 2.4, step 2); here several
+// populations share the launch.
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -33,9 +34,9 @@ struct DevJob {
     const uint64_t *pairs;
     int32_t rows, cols, rows_pad, w32, w64;
     int32_t mode;     // 1 = pair table, 0 = gather
-    int32_t nchunks;  // 2048-row chunks per individual
+    int32_t nchunks;  // 4096-row chunks per individual
     int32_t cpi;      // chunks per item (one wave walks them WPL at a time)
-    int32_t ipi;      // items per individual = ceil(nchunks / cpi)
+    int32_t ipi;      // items (waves) per individual = ceil(nchunks / cpi)
     int32_t pop_size, pop_len;
     int64_t ind_begin;   // first individual of this job in the batch
     const int32_t *pop_off;
@@ -50,21 +51,17 @@ struct DevJob {
     int32_t *count;
     uint64_t *support;
     int32_t *overlap;
-    uint64_t *memb;  // cols words: bit j = archive member j holds the column (or NULL)
 };
 
 namespace {
 
-constexpr int kWaves = 4;
-constexpr int kThreads = kWaves * kWave;
-constexpr int kItemRows = 4096;  // 64 lanes x 64 rows, or 64 blocks x 64 rows
-// pair-bitmap loads in flight per wave: a template parameter KB (2 or 4),
-// picked per batch by the autotuner
-// reduction kernel: Q support words per lane kept in registers (a template
-// parameter: 2, 4, 8 or 16, the least that holds the batch's longest support)
-// and the shared rows of G = 16 / Q archive members counted per pass, so
-// that about 16 loads are in flight per lane either way
-constexpr int kEpiMaxQ = 16;
+constexpr int kMaxWaves = 16;     // waves per workgroup: items per individual
+constexpr int kItemRows = 4096;   // 64 lanes x 64 rows, or 64 blocks x 64 rows
+// pair-bitmap loads in flight per wave (KB) and words per lane (WPL) are
+// template parameters, picked per batch by the autotuner
+constexpr int kGGroup = 8;        // archive members whose columns one pass loads
+constexpr int kHGroup = 4;        // archive members whose shared rows one pass counts
+constexpr int kHWords = 2;        // support words per lane and pass when counting them
 
 // Segment of a flat index (a job's individuals, a phase of the item
 // schedule): count the segment starts after the first at or below it. The
@@ -224,275 +221,240 @@ __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, int64_t w6
     pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL>(P, pairs, w64, wlim, s_pd, k, t, w, fit);
 }
 
+// One workgroup per individual, one wave per item (a few 4096-row chunks of
+// the individual's rows); the last wave of the workgroup to finish reduces
+// the individual. Workgroups follow a round-robin schedule over the jobs'
+// individuals (phase p interleaves the first njobs - p jobs of the job table,
+// which is sorted by population size, descending), so each job's
+// longest-first processing order holds across the batch.
+//
+// 1. All threads stage the series in LDS (one pair descriptor per step, or
+//    each column's byte offset for the gather form) and mark its columns in
+//    an LDS bitmap; a column out of range or repeated anywhere in the series
+//    makes the individual invalid.
+// 2. Wave w counts the rows of its chunks (pair counters or gather form),
+//    writes the support words, and adds their row count to an LDS sum.
+// 3. Every wave then counts itself done in LDS (after a workgroup-scope
+//    release); the last one (after the matching acquire) reduces: n from the
+//    LDS sum; the columns g shared with each archive member from the
+//    member's columns and the bitmap; the rows h shared with the members
+//    whose penalty can depend on them (h <= n, so only if 1000 g > theta k,
+//    or all of them when the overlap output is requested), a few members per
+//    pass with all loads issued together; then count, overlap and fitness.
+// When the size score is 0 the fitness is 0 whatever the penalty, so the
+// members are only visited for the overlap output.
 template <int KB, int WPL>
-__global__ void __launch_bounds__(kThreads)
-    eval_items_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
-                      int32_t njobs, int64_t total_items) {
-    __shared__ int32_t s_buf[kWaves][EBIC_MAX_K];
+__global__ void __launch_bounds__(kMaxWaves * kWave)
+    batch_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
+                 int32_t njobs, int64_t total_ind) {
+    __shared__ int32_t s_pd[EBIC_MAX_K];
+    __shared__ uint32_t s_bits[EBIC_MAX_COLS / 32];
+    __shared__ int32_t s_bad, s_done, s_n;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    if ((int)blockIdx.x < njobs) {
-        // one leading workgroup per job (dispatched first, so it never
-        // lengthens the launch): the archive's per-column member masks, read
-        // by the reduction kernel
-        const int jb = (int)blockIdx.x;
-        const DevJob &M = jobs[jb];
-        if (!M.memb) return;
-        for (int c = threadIdx.x; c < M.cols; c += kThreads) M.memb[c] = 0;
-        __syncthreads();
-        for (int j = 0; j < M.arch_size; j++) {
-            int32_t mb = M.arch_off[j], me = M.arch_off[j + 1];
-            if (mb < 0) mb = 0;
-            if (me > M.arch_len) me = M.arch_len;
-            for (int q = mb + threadIdx.x; q < me; q += kThreads) {
-                const int col = M.arch_cols[q];
-                if (col < M.cols) atomicOr((unsigned long long *)&M.memb[col], 1ull << j);
-            }
-        }
-        return;
-    }
-    const int64_t item = ((int64_t)blockIdx.x - njobs) * kWaves + wave;
-    if (item >= total_items) return;
-    // round-robin schedule: phase p interleaves the first njobs - p jobs
-    const int p = find_segment(sched, njobs, item);
-    const int64_t rel = item - sched[p], m = njobs - p;
+    const int nwaves = blockDim.x / kWave;
+    const int64_t slot = blockIdx.x;
+    if (slot >= total_ind) return;  // whole workgroup
+    const int p = find_segment(sched, njobs, slot);
+    const int64_t rel = slot - sched[p], m = njobs - p;
     const DevJob &J = jobs[rel % m];
-    const int64_t local = sched[njobs + p] + rel / m;
-    const int32_t oi = (int32_t)(local / J.ipi), grp = (int32_t)(local % J.ipi);
+    const int32_t oi = (int32_t)(sched[njobs + p] + rel / m);
     const int32_t ind = J.order ? J.order[oi] : oi;
-    if (ind < 0 || ind >= J.pop_size) return;
-    const int32_t ch0 = grp * J.cpi;
-    const int32_t ch1 = ch0 + J.cpi < J.nchunks ? ch0 + J.cpi : J.nchunks;
+    if (ind < 0 || ind >= J.pop_size) return;  // whole workgroup: not a permutation
     const int32_t beg = J.pop_off[ind], end = J.pop_off[ind + 1];
     const int k = end - beg;
-    int32_t *s = s_buf[wave];
-    bool bad = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
-    const int t = bad ? 0 : tol(k, J.approx_permille);
+    const bool bad0 = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
+    const int t = bad0 ? 0 : tol(k, J.approx_permille);
     // pair table when the batch has one and the counters fit; else gather
     const bool use_pairs = J.mode == 1 && t <= PairLimit<KB, WPL>::T;
-    if (!bad) {
-        // stage the series (pair form: one descriptor per step; gather form:
-        // each column's byte offset)
-        int lbad = 0;
-        for (int j = lane; j < k; j += kWave) {
-            const int c = J.pop_cols[beg + j];
-            lbad |= c >= J.cols;
-            if (j > 0) lbad |= c == J.pop_cols[beg + j - 1];
-            if (use_pairs) {
-                if (j > 0) {
-                    const int a = J.pop_cols[beg + j - 1];
-                    const int lo = a < c ? a : c, hi = a < c ? c : a;
-                    const int32_t p = (int32_t)pair_index(lo, hi, J.cols);
-                    s[j] = p | (a > c ? (int32_t)0x80000000 : 0);
-                }
-            } else {
-                s[j] = (int32_t)((uint32_t)c * (uint32_t)J.rows_pad * 2u);
-            }
-        }
-        bad = __ballot(lbad) != 0;
-    }
-    if (bad) {  // malformed: kernel B marks it invalid; never read out of bounds
-        for (int32_t ch = ch0; ch < ch1; ch++) {
-            const int32_t w = ch * 64 + lane;
-            if (w < J.w64) J.support[(int64_t)ind * J.w64 + w] = 0;
-        }
-        return;
-    }
-    const bool neg = J.negative_trends != 0;
-    // WPL chunks at a time: lane words c0*64 + lane + 64 v, v < WPL
-    for (int32_t c0 = ch0; c0 < ch1; c0 += WPL) {
-        if (use_pairs) {
-            const int w = c0 * 64 + lane;
-            const int wlim = J.w64 < ch1 * 64 ? J.w64 : ch1 * 64;
-            uint64_t fit[WPL];
-            if (neg)
-                pairs_dispatch<true, KB, WPL>(J.pairs, J.w64, wlim, s, k, t, w, fit);
-            else
-                pairs_dispatch<false, KB, WPL>(J.pairs, J.w64, wlim, s, k, t, w, fit);
-#pragma unroll
-            for (int v = 0; v < WPL; v++) {
-                const int wv = w + kWave * v, r0 = wv * 64;
-                uint64_t f = fit[v];
-                if (r0 + 64 > J.rows) f &= r0 >= J.rows ? 0ull : ((1ull << (J.rows - r0)) - 1ull);
-                if (wv < wlim) J.support[(int64_t)ind * J.w64 + wv] = f;
-            }
-        } else {
-            const __amdgpu_buffer_rsrc_t rs =
-                make_rsrc(J.ranks, (uint32_t)((size_t)J.cols * J.rows_pad * 2));
-            for (int32_t chunk = c0; chunk < c0 + WPL && chunk < ch1; chunk++) {
-                const int w = chunk * 64 + lane;  // this lane's 64-row word
-                int lo = 0, hi = 0;
-                const int b0 = chunk * 64;
-                for (int b = 0; b < 64 && b0 + b < J.w64; b++) {
-                    const int r = (b0 + b) * kWave + lane;
-                    const uint64_t word = block_support(rs, s, k, t, neg, r * 2, r < J.rows);
-                    lo = writelane((int)(uint32_t)word, b, lo);
-                    hi = writelane((int)(uint32_t)(word >> 32), b, hi);
-                }
-                if (w < J.w64)
-                    J.support[(int64_t)ind * J.w64 + w] =
-                        ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-            }
-        }
-    }
-}
 
-// Kernel B: one wave per individual. Validates the series (length, range,
-// no repeated column), reduces the support words into n, and for each
-// archive member counts the shared columns g and, where the penalty can
-// depend on it or the caller asked for it, the shared rows h; writes count,
-// overlap and fitness. When the size score is 0 the fitness is 0 whatever
-// the penalty, so the members are only visited for the overlap output.
-// Shared columns come from per-column member masks (bit j of memb[c] =
-// member j holds column c), built once per run by leading workgroups of the
-// evaluation kernel: each lane takes one column of the series, and g_j is
-// one ballot. Since h <= n, a
-// member can only overlap too much when 1000 g > theta k, so the shared rows
-// are only counted for those members (or when the output is requested).
-template <int Q>
-__global__ void __launch_bounds__(kThreads)
-    epilogue_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ ind_begins,
-                    int32_t njobs, int64_t total_ind) {
-    __shared__ uint32_t s_bits[kWaves][EBIC_MAX_COLS / 32];
-    constexpr int G = 16 / Q;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int64_t gid = (int64_t)blockIdx.x * kWaves + wave;
-    if (gid >= total_ind) return;
-    const DevJob &J = jobs[find_segment(ind_begins, njobs, gid)];
-    const int32_t i = (int32_t)(gid - J.ind_begin);
-    const int32_t beg = J.pop_off[i], end = J.pop_off[i + 1];
-    const int k = end - beg;
-    uint32_t *bits = s_bits[wave];
-    const int K = J.arch_size;
-    uint64_t *S = J.support + (int64_t)i * J.w64;
-    // every load the individual needs, issued before any of them is used:
-    // its support words, its first 64 columns and their member masks
-    const bool in_regs = J.w64 <= kWave * Q;
-    uint64_t sv[Q];
-#pragma unroll
-    for (int q = 0; q < Q; q++) {
-        const int w = lane + kWave * q;
-        sv[q] = (in_regs && w < J.w64) ? S[w] : 0;
+    // 1. stage and validate the series
+    if (threadIdx.x == 0) {
+        s_bad = bad0;
+        s_done = 0;
+        s_n = 0;
     }
-    bool bad = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
-    const int col0 = (!bad && lane < k) ? J.pop_cols[beg + lane] : -1;
-    const uint64_t memb0 = (J.memb && col0 >= 0 && col0 < J.cols) ? J.memb[col0] : 0ull;
-    if (!bad) {
-        for (int q = lane; q < (J.cols + 31) / 32; q += kWave) bits[q] = 0;
-        __builtin_amdgcn_wave_barrier();
+    if (!bad0)
+        for (int q = threadIdx.x; q < (J.cols + 31) / 32; q += blockDim.x) s_bits[q] = 0;
+    __syncthreads();
+    if (!bad0) {
         int lbad = 0;
-        for (int j = lane; j < k; j += kWave) {
-            const int c = j < kWave ? col0 : J.pop_cols[beg + j];
+        for (int j = threadIdx.x; j < k; j += blockDim.x) {
+            const int c = J.pop_cols[beg + j];
             if (c >= J.cols) {
                 lbad = 1;
             } else {
                 const uint32_t bit = 1u << (c % 32);
-                if (atomicOr(&bits[c / 32], bit) & bit) lbad = 1;
+                if (atomicOr(&s_bits[c / 32], bit) & bit) lbad = 1;
+            }
+            if (use_pairs) {
+                if (j > 0) {
+                    const int a = J.pop_cols[beg + j - 1];
+                    const int lo = a < c ? a : c, hi = a < c ? c : a;
+                    if (hi < J.cols)
+                        s_pd[j] = (int32_t)pair_index(lo, hi, J.cols) |
+                                  (a > c ? (int32_t)0x80000000 : 0);
+                }
+            } else {
+                s_pd[j] = (int32_t)((uint32_t)c * (uint32_t)J.rows_pad * 2u);
             }
         }
-        __builtin_amdgcn_wave_barrier();
-        bad = __ballot(lbad) != 0;
+        if (lbad) s_bad = 1;
     }
+    __syncthreads();
+    const bool bad = s_bad != 0;
+
+    // 2. this wave's item: chunks [ch0, ch1), WPL at a time
+    int nloc = 0;
+    if (wave < J.ipi) {
+        const int32_t ch0 = wave * J.cpi;
+        const int32_t ch1 = ch0 + J.cpi < J.nchunks ? ch0 + J.cpi : J.nchunks;
+        uint64_t *S = J.support + (int64_t)ind * J.w64;
+        if (bad) {
+            for (int32_t w = ch0 * 64 + lane; w < ch1 * 64 && w < J.w64; w += kWave) S[w] = 0;
+        } else {
+            const bool neg = J.negative_trends != 0;
+            for (int32_t c0 = ch0; c0 < ch1; c0 += WPL) {
+                if (use_pairs) {
+                    const int w = c0 * 64 + lane;
+                    const int wlim = J.w64 < ch1 * 64 ? J.w64 : ch1 * 64;
+                    uint64_t fit[WPL];
+                    if (neg)
+                        pairs_dispatch<true, KB, WPL>(J.pairs, J.w64, wlim, s_pd, k, t, w, fit);
+                    else
+                        pairs_dispatch<false, KB, WPL>(J.pairs, J.w64, wlim, s_pd, k, t, w, fit);
+#pragma unroll
+                    for (int v = 0; v < WPL; v++) {
+                        const int wv = w + kWave * v, r0 = wv * 64;
+                        uint64_t f = fit[v];
+                        if (r0 + 64 > J.rows)
+                            f &= r0 >= J.rows ? 0ull : ((1ull << (J.rows - r0)) - 1ull);
+                        if (wv < wlim) {
+                            S[wv] = f;
+                            nloc += __popcll(f);
+                        }
+                    }
+                } else {
+                    const __amdgpu_buffer_rsrc_t rs =
+                        make_rsrc(J.ranks, (uint32_t)((size_t)J.cols * J.rows_pad * 2));
+                    for (int32_t chunk = c0; chunk < c0 + WPL && chunk < ch1; chunk++) {
+                        const int w = chunk * 64 + lane;  // this lane's 64-row word
+                        int lo = 0, hi = 0;
+                        const int b0 = chunk * 64;
+                        for (int b = 0; b < 64 && b0 + b < J.w64; b++) {
+                            const int r = (b0 + b) * kWave + lane;
+                            const uint64_t word =
+                                block_support(rs, s_pd, k, t, neg, r * 2, r < J.rows);
+                            lo = writelane((int)(uint32_t)word, b, lo);
+                            hi = writelane((int)(uint32_t)(word >> 32), b, hi);
+                        }
+                        if (w < J.w64) {
+                            const uint64_t f = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+                            S[w] = f;
+                            nloc += __popcll(f);
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    // 3. the last wave to finish reduces the individual
+    const int nw = wave_sum(nloc);
+    int done = 0;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) {
+        atomicAdd(&s_n, nw);
+        done = atomicAdd(&s_done, 1);
+    }
+    done = __builtin_amdgcn_readfirstlane(done);
+    if (done != nwaves - 1) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int K = J.arch_size;
     if (bad) {
-        for (int w = lane; w < J.w64; w += kWave) S[w] = 0;
         if (J.overlap)
-            for (int j = lane; j < K; j += kWave) J.overlap[(int64_t)i * K + j] = 0;
+            for (int j = lane; j < K; j += kWave) J.overlap[(int64_t)ind * K + j] = 0;
         if (lane == 0) {
-            J.count[i] = -1;
-            J.fitness[i] = -1.0;
+            J.count[ind] = -1;
+            J.fitness[ind] = -1.0;
         }
         return;
     }
-    int c = 0;
-#pragma unroll
-    for (int q = 0; q < Q; q++) c += __popcll(sv[q]);
-    if (!in_regs)
-        for (int w = lane; w < J.w64; w += kWave) c += __popcll(S[w]);
-    const int n = wave_sum(c);
+    const int n = __builtin_amdgcn_readfirstlane(s_n);
     const double score = (n >= J.min_rows && k >= J.k_score_min) ? ldexp((double)n, k) : 0.0;
-    int m = 0;
+    int mover = 0;
     int32_t my_h = 0;  // lane j keeps h of member j
     if (K > 0 && (score > 0.0 || J.overlap)) {
-        // my_g: lane j ends with g_j
+        // g: lane j ends with g_j; members' first 64 columns loaded
+        // kGGroup at a time
         int my_g = 0;
-        if (J.memb) {
-            for (int q0 = 0; q0 < k; q0 += kWave) {
-                const int q = q0 + lane;
-                const uint64_t mask =
-                    q0 == 0 ? memb0 : (q < k ? J.memb[J.pop_cols[beg + q]] : 0ull);
-                for (int j = 0; j < K; j++) {
-                    const int gj = __popcll(__ballot((mask >> j) & 1ull));
-                    if (lane == j) my_g += gj;
-                }
+        for (int j0 = 0; j0 < K; j0 += kGGroup) {
+            int col[kGGroup], mb[kGGroup], me[kGGroup];
+#pragma unroll
+            for (int u = 0; u < kGGroup; u++) {
+                const int j = j0 + u < K ? j0 + u : K - 1;
+                mb[u] = J.arch_off[j] < 0 ? 0 : J.arch_off[j];
+                me[u] = J.arch_off[j + 1] > J.arch_len ? J.arch_len : J.arch_off[j + 1];
+                const int q = mb[u] + lane;
+                col[u] = q < me[u] ? (int)J.arch_cols[q] : -1;
             }
-        } else {
-            for (int j = 0; j < K; j++) {
-                int32_t mb = J.arch_off[j], me = J.arch_off[j + 1];
-                if (mb < 0) mb = 0;
-                if (me > J.arch_len) me = J.arch_len;
-                int g = 0;
-                for (int q0 = mb; q0 < me; q0 += kWave) {
-                    const int q = q0 + lane;
-                    bool hit = false;
-                    if (q < me) {
-                        const int col = J.arch_cols[q];
-                        hit = col < J.cols && ((bits[col / 32] >> (col % 32)) & 1u);
+            auto hit = [&](int c) {
+                return c >= 0 && c < J.cols && ((s_bits[c / 32] >> (c % 32)) & 1u);
+            };
+#pragma unroll
+            for (int u = 0; u < kGGroup; u++) {
+                if (j0 + u < K) {  // uniform; no break, so the loop unrolls fully
+                    int g = __popcll(__ballot(hit(col[u])));
+                    for (int q0 = mb[u] + kWave; q0 < me[u]; q0 += kWave) {
+                        const int q = q0 + lane;
+                        g += __popcll(__ballot(hit(q < me[u] ? (int)J.arch_cols[q] : -1)));
                     }
-                    g += __popcll(__ballot(hit));
+                    if (lane == j0 + u) my_g = g;
                 }
-                if (lane == j) my_g = g;
             }
         }
         // members whose rows must be counted
         const bool my_need = lane < K && n > 0 &&
                              (J.overlap || 1000LL * my_g > (long long)J.overlap_permille * k);
         uint64_t need = __ballot(my_need);
-        // up to G members per pass, all their loads issued together
+        const uint64_t *S = J.support + (int64_t)ind * J.w64;
         while (need) {
-            int js[G];
+            int js[kHGroup];
 #pragma unroll
-            for (int g = 0; g < G; g++) {
+            for (int g = 0; g < kHGroup; g++) {
                 js[g] = need ? __ffsll((unsigned long long)need) - 1 : js[g > 0 ? g - 1 : 0];
                 need &= need - 1;
             }
-            int hp[G];
+            int hp[kHGroup];
 #pragma unroll
-            for (int g = 0; g < G; g++) hp[g] = 0;
-            if (in_regs) {
-                uint64_t a[G][Q];
+            for (int g = 0; g < kHGroup; g++) hp[g] = 0;
+            for (int w0 = lane; w0 < J.w64; w0 += kWave * kHWords) {
+                uint64_t sw[kHWords], aw[kHGroup][kHWords];
 #pragma unroll
-                for (int g = 0; g < G; g++) {
-                    const uint64_t *A = J.arch_support + (int64_t)js[g] * J.w64;
+                for (int u = 0; u < kHWords; u++) {
+                    const int w = w0 + kWave * u;
+                    sw[u] = w < J.w64 ? S[w] : 0ull;
 #pragma unroll
-                    for (int q = 0; q < Q; q++) {
-                        const int w = lane + kWave * q;
-                        a[g][q] = w < J.w64 ? A[w] : 0ull;
-                    }
+                    for (int g = 0; g < kHGroup; g++)
+                        aw[g][u] = w < J.w64 ? J.arch_support[(int64_t)js[g] * J.w64 + w] : 0ull;
                 }
 #pragma unroll
-                for (int g = 0; g < G; g++)
+                for (int g = 0; g < kHGroup; g++)
 #pragma unroll
-                    for (int q = 0; q < Q; q++) hp[g] += __popcll(sv[q] & a[g][q]);
-            } else {
-                for (int w = lane; w < J.w64; w += kWave) {
-                    const uint64_t sw = S[w];
-#pragma unroll
-                    for (int g = 0; g < G; g++)
-                        hp[g] += __popcll(sw & J.arch_support[(int64_t)js[g] * J.w64 + w]);
-                }
+                    for (int u = 0; u < kHWords; u++) hp[g] += __popcll(sw[u] & aw[g][u]);
             }
 #pragma unroll
-            for (int g = 0; g < G; g++) {
+            for (int g = 0; g < kHGroup; g++) {
                 const int h = wave_sum(hp[g]);
                 if (lane == js[g]) my_h = h;  // a repeated member writes the same h
             }
         }
         const bool over = lane < K && 1000LL * my_h * my_g > (long long)J.overlap_permille * n * k;
-        m = __popcll(__ballot(over));
+        mover = __popcll(__ballot(over));
     }
-    if (J.overlap && lane < K) J.overlap[(int64_t)i * K + lane] = my_h;
+    if (J.overlap && lane < K) J.overlap[(int64_t)ind * K + lane] = my_h;
     if (lane == 0) {
-        J.count[i] = n;
-        J.fitness[i] = ldexp(score, -m);
+        J.count[ind] = n;
+        J.fitness[ind] = ldexp(score, -mover);
     }
 }
 
@@ -506,24 +468,21 @@ struct Batch {
     int device = 0;
     int32_t flags = 0;
     std::vector<DevJob> jobs;
-    DevJob *d_jobs = nullptr;  // device: DevJob[njobs] by item count, descending; then
-    int64_t *d_sched = nullptr;       // the item schedule (phase starts, phase rounds)
-    int64_t *d_ind_begins = nullptr;  // and each device job's first individual
+    DevJob *d_jobs = nullptr;  // device: DevJob[njobs] by population size, descending;
+    int64_t *d_sched = nullptr;  // then the schedule (phase starts, phase rounds)
     int32_t cap_jobs = 0;      // capacity of d_jobs / h_stage
     void *h_stage = nullptr;   // pinned staging of the table
     std::vector<void *> scratch;
-    int64_t total_items = 0, total_ind = 0;
-    int32_t njobs = 0;         // kept alive: the graph's kernel arguments
-    uint64_t *d_memb = nullptr;  // member masks of all jobs with an archive
-    size_t memb_cap = 0;       // words
+    int64_t total_ind = 0;     // kept alive: the graph's kernel arguments
+    int32_t njobs = 0;
+    int waves = 1;             // waves per workgroup: the largest items per individual
     int kb = 2;                // pair-bitmap loads in flight (template)
     int wpl = 1;               // 64-row words per lane (template)
     int cpi = 1;               // chunk groups (of wpl chunks) per item
-    int epi_q = 4;             // reduction kernel: support words per lane in registers
     bool tuned = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // timing: three events per profiled run (start, between, end)
+    // timing: two events per profiled run (around the kernel)
     std::vector<hipEvent_t> events;
     int32_t prof_cap = 0, prof_used = 0;
 };
@@ -592,44 +551,26 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
     return d;
 }
 
-// Lay the items out for `cpi` groups of b->wpl chunks per item
-// and queue the table's upload on `stream` from pinned staging, growing the
-// device table when needed.
+// Lay the items out for `cpi` groups of b->wpl chunks per item (more when an
+// individual would need more than kMaxWaves items) and queue the table's
+// upload on `stream` from pinned staging, growing the device table when
+// needed.
 int upload_table(Batch *b, int cpi, hipStream_t stream) {
     b->cpi = cpi;
     const int32_t n = b->njobs;
-    int64_t items = 0;
-    std::vector<int64_t> count(n);
-    for (int i = 0; i < n; i++) {
-        DevJob &d = b->jobs[i];
+    int waves = 1;
+    for (DevJob &d : b->jobs) {
         // whole groups per item, so that no two items share a group
-        const int32_t cpc = cpi * b->wpl;
+        int32_t cpc = cpi * b->wpl;
+        const int32_t need = (d.nchunks + kMaxWaves - 1) / kMaxWaves;
+        if (cpc < need) cpc = (need + b->wpl - 1) / b->wpl * b->wpl;
         d.cpi = cpc < d.nchunks ? cpc : d.nchunks;
         if (d.cpi < 1) d.cpi = 1;
         d.ipi = (d.nchunks + d.cpi - 1) / d.cpi;
-        count[i] = (int64_t)d.pop_size * d.ipi;
-        items += count[i];
+        waves = d.ipi > waves ? d.ipi : waves;
     }
-    b->total_items = items;
-    int32_t wmax = 0;
-    for (const DevJob &d : b->jobs) wmax = d.w64 > wmax ? d.w64 : wmax;
-    b->epi_q = wmax <= 2 * kWave ? 2 : wmax <= 4 * kWave ? 4 : wmax <= 8 * kWave ? 8 : kEpiMaxQ;
-    // member-mask scratch for every job with an archive
-    size_t words = 0;
-    for (const DevJob &d : b->jobs) words += d.arch_size > 0 ? (size_t)d.cols : 0;
-    if (words > b->memb_cap) {
-        if (b->d_memb) (void)hipFree(b->d_memb);
-        b->d_memb = nullptr;
-        b->memb_cap = 0;
-        EBIC_HIP(hipMalloc(reinterpret_cast<void **>(&b->d_memb), words * sizeof(uint64_t)));
-        b->memb_cap = words;
-    }
-    size_t at = 0;
-    for (DevJob &d : b->jobs) {
-        d.memb = d.arch_size > 0 ? b->d_memb + at : nullptr;
-        at += d.arch_size > 0 ? (size_t)d.cols : 0;
-    }
-    const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 3 * n;
+    b->waves = waves;
+    const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 2 * n;
     if (n > b->cap_jobs) {
         if (b->d_jobs) (void)hipFree(b->d_jobs);
         if (b->h_stage) (void)hipHostFree(b->h_stage);
@@ -643,72 +584,45 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
         b->cap_jobs = n;
     }
     b->d_sched = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) + jbytes);
-    b->d_ind_begins = b->d_sched + 2 * n;
-    // Items of all jobs are interleaved round-robin, so that each job's
-    // longest-first order holds across the batch: with the jobs stored by
-    // item count, descending, phase p takes one item of each of the first
-    // n - p jobs per round, over the rounds that those jobs still have.
+    // Individuals of all jobs are interleaved round-robin, so that each
+    // job's longest-first order holds across the batch: with the jobs stored
+    // by population size, descending, phase p takes one individual of each
+    // of the first n - p jobs per round, over the rounds that those jobs
+    // still have.
     std::vector<int> perm(n);
     for (int i = 0; i < n; i++) perm[i] = i;
-    std::stable_sort(perm.begin(), perm.end(),
-                     [&](int a, int c) { return count[a] > count[c]; });
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) {
+        return b->jobs[a].pop_size > b->jobs[c].pop_size;
+    });
     char *h = static_cast<char *>(b->h_stage);
     DevJob *hj = reinterpret_cast<DevJob *>(h);
     int64_t *ph_start = reinterpret_cast<int64_t *>(h + jbytes);
     int64_t *ph_round = ph_start + n;
-    int64_t *ind_begin = ph_start + 2 * n;
-    int64_t inds = 0, start = 0;
+    int64_t start = 0;
     for (int p = 0; p < n; p++) {
         hj[p] = b->jobs[perm[p]];
-        hj[p].ind_begin = inds;
-        inds += hj[p].pop_size;
-        ind_begin[p] = hj[p].ind_begin;
-        const int64_t first = p == 0 ? 0 : count[perm[n - p]];
+        const int64_t first = p == 0 ? 0 : b->jobs[perm[n - p]].pop_size;
         ph_start[p] = start;
         ph_round[p] = first;
-        start += (int64_t)(n - p) * (count[perm[n - 1 - p]] - first);
+        start += (int64_t)(n - p) * (b->jobs[perm[n - 1 - p]].pop_size - first);
     }
-    b->total_ind = inds;
+    b->total_ind = start;
     EBIC_HIP(hipMemcpyAsync(b->d_jobs, h, bytes, hipMemcpyHostToDevice, stream));
     return EBIC_OK;
 }
 
-void *eval_kernel_fn(int kb, int wpl) {
+void *kernel_fn(int kb, int wpl) {
     if (wpl == 2)
-        return kb == 4 ? reinterpret_cast<void *>(eval_items_kernel<4, 2>)
-                       : reinterpret_cast<void *>(eval_items_kernel<2, 2>);
-    return kb == 4 ? reinterpret_cast<void *>(eval_items_kernel<4, 1>)
-                   : reinterpret_cast<void *>(eval_items_kernel<2, 1>);
+        return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 2>)
+                       : reinterpret_cast<void *>(batch_kernel<2, 2>);
+    return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 1>)
+                   : reinterpret_cast<void *>(batch_kernel<2, 1>);
 }
 
-void *epilogue_kernel_fn(int q) {
-    switch (q) {
-        case 2: return reinterpret_cast<void *>(epilogue_kernel<2>);
-        case 4: return reinterpret_cast<void *>(epilogue_kernel<4>);
-        case 8: return reinterpret_cast<void *>(epilogue_kernel<8>);
-        default: return reinterpret_cast<void *>(epilogue_kernel<kEpiMaxQ>);
-    }
-}
-
-unsigned epilogue_grid(const Batch *b) {
-    return (unsigned)((b->total_ind + kWaves - 1) / kWaves);
-}
-
-int launch_epilogue(Batch *b, hipStream_t stream) {
-    void *args[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
-    EBIC_HIP(hipLaunchKernel(epilogue_kernel_fn(b->epi_q), dim3(epilogue_grid(b)), dim3(kThreads),
-                             args, 0, stream));
-    return EBIC_OK;
-}
-
-unsigned eval_grid(const Batch *b) {
-    return (unsigned)((b->total_items + kWaves - 1) / kWaves + b->njobs);
-}
-
-int launch_eval(Batch *b, hipStream_t stream) {
-    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_items};
-    EBIC_HIP(hipLaunchKernel(eval_kernel_fn(b->kb, b->wpl), dim3(eval_grid(b)), dim3(kThreads),
-                             args, 0, stream));
+int launch_batch(Batch *b, hipStream_t stream) {
+    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind};
+    EBIC_HIP(hipLaunchKernel(kernel_fn(b->kb, b->wpl), dim3((unsigned)b->total_ind),
+                             dim3(b->waves * kWave), args, 0, stream));
     return EBIC_OK;
 }
 
@@ -717,22 +631,16 @@ int build_graph(Batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    // two kernel nodes, evaluation then reduction (no stream capture)
-    hipGraphNode_t na = nullptr, nb = nullptr;
-    void *args_a[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_items};
-    void *args_b[] = {&b->d_jobs, &b->d_ind_begins, &b->njobs, &b->total_ind};
-    hipKernelNodeParams pa{}, pb{};
-    pa.func = eval_kernel_fn(b->kb, b->wpl);
-    pa.gridDim = dim3(eval_grid(b));
-    pa.blockDim = dim3(kThreads);
-    pa.kernelParams = args_a;
-    pb.func = epilogue_kernel_fn(b->epi_q);
-    pb.gridDim = dim3(epilogue_grid(b));
-    pb.blockDim = dim3(kThreads);
-    pb.kernelParams = args_b;
+    // one kernel node (no stream capture)
+    hipGraphNode_t node = nullptr;
+    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind};
+    hipKernelNodeParams pk{};
+    pk.func = kernel_fn(b->kb, b->wpl);
+    pk.gridDim = dim3((unsigned)b->total_ind);
+    pk.blockDim = dim3(b->waves * kWave);
+    pk.kernelParams = args;
     hipError_t e = hipGraphCreate(&b->graph, 0);
-    if (e == hipSuccess) e = hipGraphAddKernelNode(&na, b->graph, nullptr, 0, &pa);
-    if (e == hipSuccess) e = hipGraphAddKernelNode(&nb, b->graph, &na, 1, &pb);
+    if (e == hipSuccess) e = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &pk);
     if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return check_hip(e, "batch graph");
     return EBIC_OK;
@@ -842,15 +750,18 @@ int tune(Batch *b, hipStream_t stream) {
         for (int cpi : {1, 2, 4}) {
             if (cpi > 1 && cpi * wpl > maxch) break;
             for (int kb : {2, 4}) {
+                // two words per lane leave room for narrow counters only
+                // with four loads in flight: not a candidate
+                if (wpl == 2 && kb == 4) continue;
                 b->kb = kb;
                 b->wpl = wpl;
                 rc = upload_table(b, cpi, stream);
-                if (rc == EBIC_OK) rc = launch_eval(b, stream);  // warm-up
+                if (rc == EBIC_OK) rc = launch_batch(b, stream);  // warm-up
                 float t[3];
                 for (int r = 0; r < 3 && rc == EBIC_OK; r++) {
                     (void)hipEventRecord(e0, stream);
                     for (int l = 0; l < kTuneLaunches && rc == EBIC_OK; l++)
-                        rc = launch_eval(b, stream);
+                        rc = launch_batch(b, stream);
                     (void)hipEventRecord(e1, stream);
                     (void)hipEventSynchronize(e1);
                     (void)hipEventElapsedTime(&t[r], e0, e1);
@@ -963,22 +874,15 @@ int batch_run(Batch *b, hipStream_t stream) {
         if (rc) return rc;
     }
     hipEvent_t *ev = nullptr;
-    if (b->prof_used < b->prof_cap) ev = &b->events[3 * b->prof_used++];
+    if (b->prof_used < b->prof_cap) ev = &b->events[2 * b->prof_used++];
     if (ev) EBIC_HIP(hipEventRecord(ev[0], stream));
     if (b->exec) {
         EBIC_HIP(hipGraphLaunch(b->exec, stream));
-        if (ev) {
-            EBIC_HIP(hipEventRecord(ev[1], stream));
-            EBIC_HIP(hipEventRecord(ev[2], stream));
-        }
-        return EBIC_OK;
+    } else {
+        int rc = launch_batch(b, stream);
+        if (rc) return rc;
     }
-    int rc = launch_eval(b, stream);
-    if (rc) return rc;
     if (ev) EBIC_HIP(hipEventRecord(ev[1], stream));
-    rc = launch_epilogue(b, stream);
-    if (rc) return rc;
-    if (ev) EBIC_HIP(hipEventRecord(ev[2], stream));
     return EBIC_OK;
 }
 
@@ -1014,7 +918,7 @@ int batch_profile(Batch *b, int32_t n) {
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     b->events.clear();
     b->prof_cap = b->prof_used = 0;
-    for (int32_t i = 0; i < 3 * n; i++) {
+    for (int32_t i = 0; i < 2 * n; i++) {
         hipEvent_t e;
         EBIC_HIP(hipEventCreate(&e));
         b->events.push_back(e);
@@ -1023,14 +927,13 @@ int batch_profile(Batch *b, int32_t n) {
     return EBIC_OK;
 }
 
-int batch_timings(Batch *b, float *ms_eval, float *ms_reduce, int32_t *n) {
-    if (!b || !ms_eval || !n || *n < 0) return fail(EBIC_ERR_INVALID_ARG, "bad arguments");
+int batch_timings(Batch *b, float *ms, int32_t *n) {
+    if (!b || !ms || !n || *n < 0) return fail(EBIC_ERR_INVALID_ARG, "bad arguments");
     const int32_t m = b->prof_used < *n ? b->prof_used : *n;
     for (int32_t i = 0; i < m; i++) {
-        hipEvent_t *ev = &b->events[3 * i];
-        EBIC_HIP(hipEventSynchronize(ev[2]));
-        EBIC_HIP(hipEventElapsedTime(&ms_eval[i], ev[0], ev[1]));
-        if (ms_reduce) EBIC_HIP(hipEventElapsedTime(&ms_reduce[i], ev[1], ev[2]));
+        hipEvent_t *ev = &b->events[2 * i];
+        EBIC_HIP(hipEventSynchronize(ev[1]));
+        EBIC_HIP(hipEventElapsedTime(&ms[i], ev[0], ev[1]));
     }
     *n = m;
     return EBIC_OK;
@@ -1043,7 +946,6 @@ int batch_destroy(Batch *b) {
     if (b->graph) (void)hipGraphDestroy(b->graph);
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
-    if (b->d_memb) (void)hipFree(b->d_memb);
     for (void *p : b->scratch) (void)hipFree(p);
     delete b;
     return EBIC_OK;

@@ -245,9 +245,9 @@ int ebic_batch_profile(ebic_batch *b, int32_t n) {
     return batch_profile(reinterpret_cast<Batch *>(b), n);
 }
 
-int ebic_batch_timings(ebic_batch *b, float *ms_eval, float *ms_reduce, int32_t *n) {
+int ebic_batch_timings(ebic_batch *b, float *ms, int32_t *n) {
     clear_error();
-    return batch_timings(reinterpret_cast<Batch *>(b), ms_eval, ms_reduce, n);
+    return batch_timings(reinterpret_cast<Batch *>(b), ms, n);
 }
 
 int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream) {

@@ -86,6 +86,6 @@ int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb, int32_t *wpl);
 int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb, int32_t wpl);
 int batch_destroy(Batch *b);
 int batch_profile(Batch *b, int32_t n);
-int batch_timings(Batch *b, float *ms_eval, float *ms_reduce, int32_t *n);
+int batch_timings(Batch *b, float *ms, int32_t *n);
 
 }  // namespace ebic

@@ -141,7 +141,6 @@ _SIGNATURES = {
                                          ctypes.POINTER(_i32)]),
     "ebic_batch_set_tuning": (ctypes.c_int, [_vp, _i32, _i32, _i32]),
     "ebic_batch_timings": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_float),
-                                          ctypes.POINTER(ctypes.c_float),
                                           ctypes.POINTER(_i32)]),
 }
 
@@ -454,13 +453,12 @@ class Batch:
         """Record kernel times for the next n runs."""
         _check(lib().ebic_batch_profile(self.handle, n))
 
-    def timings(self, n: int):
-        """(evaluation ms, reduction ms) of up to n recorded runs."""
+    def timings(self, n: int) -> np.ndarray:
+        """Kernel milliseconds of up to n recorded runs."""
         a = (ctypes.c_float * max(n, 1))()
-        b = (ctypes.c_float * max(n, 1))()
         m = _i32(n)
-        _check(lib().ebic_batch_timings(self.handle, a, b, ctypes.byref(m)))
-        return np.array(a[:m.value]), np.array(b[:m.value])
+        _check(lib().ebic_batch_timings(self.handle, a, ctypes.byref(m)))
+        return np.array(a[:m.value])
 
     def close(self) -> None:
         if self.handle:
