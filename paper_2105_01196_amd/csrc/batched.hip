@@ -59,9 +59,11 @@ constexpr int kMaxWaves = 16;     // waves per workgroup: items per individual
 constexpr int kItemRows = 4096;   // 64 lanes x 64 rows, or 64 blocks x 64 rows
 // pair-bitmap loads in flight per wave (KB) and words per lane (WPL) are
 // template parameters, picked per batch by the autotuner
-constexpr int kGGroup = 8;        // archive members whose columns one pass loads
+constexpr int kGGroup = 8;        // archive members whose columns one pass loads (no LDS copy)
 constexpr int kHGroup = 4;        // archive members whose shared rows one pass counts
-constexpr int kHWords = 2;        // support words per lane and pass when counting them
+constexpr int kHWords = 3;        // support words per lane and pass when counting them
+constexpr int kArchLdsCols = 8192;  // largest archive whose columns are copied to LDS (16 KB)
+constexpr int kSupLdsWords = 2048;  // longest support kept in LDS for the reduction (16 KB)
 
 // Segment of a flat index (a job's individuals, a phase of the item
 // schedule): count the segment starts after the first at or below it. The
@@ -246,9 +248,21 @@ __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, int64_t w6
 template <int KB, int WPL>
 __global__ void __launch_bounds__(kMaxWaves * kWave)
     batch_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
-                 int32_t njobs, int64_t total_ind) {
-    __shared__ int32_t s_pd[EBIC_MAX_K];
-    __shared__ uint32_t s_bits[EBIC_MAX_COLS / 32];
+                 int32_t njobs, int64_t total_ind, int32_t sup_words, int32_t bits_words,
+                 int32_t acol_words) {
+    // dynamic LDS: the support words (sup_words, 0 when they stay in global
+    // memory only), the series' step descriptors, the column bitmap, the
+    // archive's offsets and columns (acol_words, 0 when they stay global)
+    extern __shared__ uint64_t s_dyn[];
+    uint64_t *s_sup = s_dyn;
+    int32_t *s_pd = reinterpret_cast<int32_t *>(s_dyn + sup_words);
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(s_pd + EBIC_MAX_K);
+    int32_t *s_aoff = reinterpret_cast<int32_t *>(s_bits + bits_words);
+    uint16_t *s_acols = reinterpret_cast<uint16_t *>(s_aoff + EBIC_MAX_ARCHIVE + 1);
+    // hit masks of the archive's columns, 64 per word (after the columns,
+    // 8-byte aligned)
+    uint64_t *s_ahit = reinterpret_cast<uint64_t *>(
+        reinterpret_cast<uintptr_t>(s_acols + acol_words + 3) & ~(uintptr_t)7);
     __shared__ int32_t s_bad, s_done, s_n;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nwaves = blockDim.x / kWave;
@@ -276,6 +290,17 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     if (!bad0)
         for (int q = threadIdx.x; q < (J.cols + 31) / 32; q += blockDim.x) s_bits[q] = 0;
     __syncthreads();
+    // the archive's offsets and columns, for the reduction (independent loads
+    // in flight with the series')
+    const int K = J.arch_size;
+    const bool arch_lds = K > 0 && J.arch_len <= acol_words;
+    if (arch_lds && !bad0) {
+        for (int q = threadIdx.x; q <= K; q += blockDim.x) {
+            const int32_t o = J.arch_off[q];
+            s_aoff[q] = o < 0 ? 0 : (o > J.arch_len ? J.arch_len : o);
+        }
+        for (int q = threadIdx.x; q < J.arch_len; q += blockDim.x) s_acols[q] = J.arch_cols[q];
+    }
     if (!bad0) {
         int lbad = 0;
         for (int j = threadIdx.x; j < k; j += blockDim.x) {
@@ -302,6 +327,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     }
     __syncthreads();
     const bool bad = s_bad != 0;
+    const bool sup_lds = J.w64 <= sup_words;
 
     // 2. this wave's item: chunks [ch0, ch1), WPL at a time
     int nloc = 0;
@@ -330,6 +356,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                             f &= r0 >= J.rows ? 0ull : ((1ull << (J.rows - r0)) - 1ull);
                         if (wv < wlim) {
                             S[wv] = f;
+                            if (sup_lds) s_sup[wv] = f;
                             nloc += __popcll(f);
                         }
                     }
@@ -350,6 +377,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                         if (w < J.w64) {
                             const uint64_t f = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
                             S[w] = f;
+                            if (sup_lds) s_sup[w] = f;
                             nloc += __popcll(f);
                         }
                     }
@@ -369,7 +397,6 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     done = __builtin_amdgcn_readfirstlane(done);
     if (done != nwaves - 1) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const int K = J.arch_size;
     if (bad) {
         if (J.overlap)
             for (int j = lane; j < K; j += kWave) J.overlap[(int64_t)ind * K + j] = 0;
@@ -384,35 +411,65 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     int mover = 0;
     int32_t my_h = 0;  // lane j keeps h of member j
     if (K > 0 && (score > 0.0 || J.overlap)) {
-        // g: lane j ends with g_j; members' first 64 columns loaded
-        // kGGroup at a time
-        int my_g = 0;
-        for (int j0 = 0; j0 < K; j0 += kGGroup) {
-            int col[kGGroup], mb[kGGroup], me[kGGroup];
-#pragma unroll
-            for (int u = 0; u < kGGroup; u++) {
-                const int j = j0 + u < K ? j0 + u : K - 1;
-                mb[u] = J.arch_off[j] < 0 ? 0 : J.arch_off[j];
-                me[u] = J.arch_off[j + 1] > J.arch_len ? J.arch_len : J.arch_off[j + 1];
-                const int q = mb[u] + lane;
-                col[u] = q < me[u] ? (int)J.arch_cols[q] : -1;
+        auto hit = [&](int c) {
+            return c >= 0 && c < J.cols && ((s_bits[c / 32] >> (c % 32)) & 1u);
+        };
+        int my_g = 0;  // lane j ends with g_j
+        if (arch_lds) {
+            // from LDS: one ballot per 64 archive columns marks those in the
+            // series; lane j then counts the marks in its member's range
+            const int nblk = (J.arch_len + kWave - 1) / kWave;
+#pragma unroll 4
+            for (int bb = 0; bb < nblk; bb++) {
+                const int q = bb * kWave + lane;
+                const uint64_t hm = __ballot(q < J.arch_len && hit(s_acols[q]));
+                if (lane == 0) s_ahit[bb] = hm;
             }
-            auto hit = [&](int c) {
-                return c >= 0 && c < J.cols && ((s_bits[c / 32] >> (c % 32)) & 1u);
+            __builtin_amdgcn_wave_barrier();
+            if (lane < K) {
+                const int mb = s_aoff[lane], me = s_aoff[lane + 1];
+                for (int q0 = mb & ~(kWave - 1); q0 < me; q0 += kWave) {
+                    const int lo = mb > q0 ? mb - q0 : 0;
+                    const int hi = me < q0 + kWave ? me - q0 : kWave;
+                    const uint64_t range =
+                        (hi == kWave ? ~0ull : ((1ull << hi) - 1)) & ~((1ull << lo) - 1);
+                    my_g += __popcll(s_ahit[q0 / kWave] & range);
+                }
+            }
+        } else {
+            // from global memory: lane j holds arch_off[j] (one load for all
+            // members); members' first 64 columns loaded kGGroup at a time
+            const int32_t aoff = lane <= K ? J.arch_off[lane] : 0;
+            const int32_t aoff_k = J.arch_off[K];
+            auto clampo = [&](int32_t o) {
+                return o < 0 ? 0 : (o > J.arch_len ? J.arch_len : o);
             };
+            for (int j0 = 0; j0 < K; j0 += kGGroup) {
+                int col[kGGroup], mb[kGGroup], me[kGGroup];
 #pragma unroll
-            for (int u = 0; u < kGGroup; u++) {
-                if (j0 + u < K) {  // uniform; no break, so the loop unrolls fully
-                    int g = __popcll(__ballot(hit(col[u])));
-                    for (int q0 = mb[u] + kWave; q0 < me[u]; q0 += kWave) {
-                        const int q = q0 + lane;
-                        g += __popcll(__ballot(hit(q < me[u] ? (int)J.arch_cols[q] : -1)));
+                for (int u = 0; u < kGGroup; u++) {
+                    const int j = j0 + u < K ? j0 + u : K - 1;
+                    mb[u] = clampo(__builtin_amdgcn_readlane(aoff, j));
+                    me[u] = clampo(j + 1 < kWave ? __builtin_amdgcn_readlane(aoff, j + 1) : aoff_k);
+                    const int q = mb[u] + lane;
+                    col[u] = q < me[u] ? (int)J.arch_cols[q] : -1;
+                }
+#pragma unroll
+                for (int u = 0; u < kGGroup; u++) {
+                    if (j0 + u < K) {  // uniform; no break, so the loop unrolls fully
+                        int g = __popcll(__ballot(hit(col[u])));
+                        for (int q0 = mb[u] + kWave; q0 < me[u]; q0 += kWave) {
+                            const int q = q0 + lane;
+                            g += __popcll(__ballot(hit(q < me[u] ? (int)J.arch_cols[q] : -1)));
+                        }
+                        if (lane == j0 + u) my_g = g;
                     }
-                    if (lane == j0 + u) my_g = g;
                 }
             }
         }
-        // members whose rows must be counted
+        // members whose rows must be counted: kHGroup per pass, kHWords
+        // words per lane and pass, all archive loads of a pass issued
+        // together; the individual's own words come from LDS when staged
         const bool my_need = lane < K && n > 0 &&
                              (J.overlap || 1000LL * my_g > (long long)J.overlap_permille * k);
         uint64_t need = __ballot(my_need);
@@ -428,19 +485,21 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
 #pragma unroll
             for (int g = 0; g < kHGroup; g++) hp[g] = 0;
             for (int w0 = lane; w0 < J.w64; w0 += kWave * kHWords) {
-                uint64_t sw[kHWords], aw[kHGroup][kHWords];
+                uint64_t aw[kHGroup][kHWords];
 #pragma unroll
                 for (int u = 0; u < kHWords; u++) {
                     const int w = w0 + kWave * u;
-                    sw[u] = w < J.w64 ? S[w] : 0ull;
 #pragma unroll
                     for (int g = 0; g < kHGroup; g++)
                         aw[g][u] = w < J.w64 ? J.arch_support[(int64_t)js[g] * J.w64 + w] : 0ull;
                 }
 #pragma unroll
-                for (int g = 0; g < kHGroup; g++)
+                for (int u = 0; u < kHWords; u++) {
+                    const int w = w0 + kWave * u;
+                    const uint64_t sw = w < J.w64 ? (sup_lds ? s_sup[w] : S[w]) : 0ull;
 #pragma unroll
-                    for (int u = 0; u < kHWords; u++) hp[g] += __popcll(sw[u] & aw[g][u]);
+                    for (int g = 0; g < kHGroup; g++) hp[g] += __popcll(sw & aw[g][u]);
+                }
             }
 #pragma unroll
             for (int g = 0; g < kHGroup; g++) {
@@ -476,6 +535,9 @@ struct Batch {
     int64_t total_ind = 0;     // kept alive: the graph's kernel arguments
     int32_t njobs = 0;
     int waves = 1;             // waves per workgroup: the largest items per individual
+    int32_t sup_words = 0;     // LDS support words per workgroup (0: global only)
+    int32_t bits_words = 1;    // LDS column-bitmap words per workgroup
+    int32_t acol_words = 0;    // LDS archive columns per workgroup (0: global only)
     int kb = 2;                // pair-bitmap loads in flight (template)
     int wpl = 1;               // 64-row words per lane (template)
     int cpi = 1;               // chunk groups (of wpl chunks) per item
@@ -570,6 +632,16 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
         waves = d.ipi > waves ? d.ipi : waves;
     }
     b->waves = waves;
+    int32_t wmax = 0, cmax = 0;
+    for (const DevJob &d : b->jobs) {
+        wmax = d.w64 > wmax ? d.w64 : wmax;
+        cmax = d.cols > cmax ? d.cols : cmax;
+    }
+    b->sup_words = wmax <= kSupLdsWords ? wmax : 0;
+    b->bits_words = (cmax + 31) / 32;
+    int32_t amax = 0;
+    for (const DevJob &d : b->jobs) amax = d.arch_len > amax ? d.arch_len : amax;
+    b->acol_words = amax <= kArchLdsCols ? amax : 0;
     const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 2 * n;
     if (n > b->cap_jobs) {
         if (b->d_jobs) (void)hipFree(b->d_jobs);
@@ -619,10 +691,19 @@ void *kernel_fn(int kb, int wpl) {
                    : reinterpret_cast<void *>(batch_kernel<2, 1>);
 }
 
+size_t lds_bytes(const Batch *b) {
+    // support, step descriptors, column bitmap, archive offsets, archive
+    // columns, 8 bytes of alignment slack, their hit masks
+    return (size_t)b->sup_words * 8 + (size_t)EBIC_MAX_K * 4 + (size_t)b->bits_words * 4 +
+           (size_t)(EBIC_MAX_ARCHIVE + 1) * 4 + (size_t)b->acol_words * 2 + 8 +
+           (size_t)(b->acol_words + kWave - 1) / kWave * 8;
+}
+
 int launch_batch(Batch *b, hipStream_t stream) {
-    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind};
+    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind, &b->sup_words,
+                    &b->bits_words, &b->acol_words};
     EBIC_HIP(hipLaunchKernel(kernel_fn(b->kb, b->wpl), dim3((unsigned)b->total_ind),
-                             dim3(b->waves * kWave), args, 0, stream));
+                             dim3(b->waves * kWave), args, lds_bytes(b), stream));
     return EBIC_OK;
 }
 
@@ -633,11 +714,13 @@ int build_graph(Batch *b) {
     b->graph = nullptr;
     // one kernel node (no stream capture)
     hipGraphNode_t node = nullptr;
-    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind};
+    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind, &b->sup_words,
+                    &b->bits_words, &b->acol_words};
     hipKernelNodeParams pk{};
     pk.func = kernel_fn(b->kb, b->wpl);
     pk.gridDim = dim3((unsigned)b->total_ind);
     pk.blockDim = dim3(b->waves * kWave);
+    pk.sharedMemBytes = (unsigned)lds_bytes(b);
     pk.kernelParams = args;
     hipError_t e = hipGraphCreate(&b->graph, 0);
     if (e == hipSuccess) e = hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &pk);
