@@ -63,6 +63,10 @@ constexpr int kGGroup = 8;        // archive members whose columns one pass load
 constexpr int kHGroup = 4;        // archive members whose shared rows one pass counts
 constexpr int kHWords = 3;        // support words per lane and pass when counting them
 constexpr int kArchLdsCols = 8192;  // largest archive whose columns are copied to LDS (16 KB)
+#ifndef EBIC_PIPE
+#define EBIC_PIPE 0
+#endif
+constexpr int kSchedBatch = 4;   // schedule phases loaded together
 constexpr int kSupLdsWords = 2048;  // longest support kept in LDS for the reduction (16 KB)
 
 // Segment of a flat index (a job's individuals, a phase of the item
@@ -147,6 +151,65 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
         for (int p = 0; p < P; p++) D[v][p] = U[v][p] = ((start >> p) & 1u) ? ~0ull : 0ull;
         dov[v] = uov[v] = 0;
     }
+#if EBIC_PIPE
+    // Software-pipelined: the next group's loads are issued before this
+    // group's bits are used, so two groups are in flight while the exit
+    // check still follows every group. A loaded word is kept raw with its
+    // step's inversion mask, so nothing consumes it before its turn.
+    uint64_t bc[KB][WPL], bn[KB][WPL], ic[KB], in_[KB];
+    auto issue = [&](int j0, uint64_t (&bits)[KB][WPL], uint64_t (&inv)[KB]) {
+#pragma unroll
+        for (int q = 0; q < KB; q++) {
+            const bool en = j0 + q < k;  // uniform
+            const int idx = en ? j0 + q : k - 1;
+            const int pd = __builtin_amdgcn_readfirstlane(s_pd[idx]);
+            const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * w64;
+            inv[q] = pd < 0 ? ~0ull : 0ull;
+#pragma unroll
+            for (int v = 0; v < WPL; v++)
+                bits[q][v] = (en && active[v]) ? vec[w + kWave * v] : 0ull;
+        }
+    };
+    int j = 1;
+    if (j < k) issue(j, bc, ic);
+    while (j < k) {
+        const int n = (k - j) < KB ? (k - j) : KB;
+        const int jn = j + n;
+        issue(jn, bn, in_);  // steps at or past k load nothing
+        uint64_t up[WPL][KB], dn[WPL][KB];
+#pragma unroll
+        for (int q = 0; q < KB; q++) {
+            const uint64_t vm = q < n ? ~0ull : 0ull;  // steps past the end count nothing
+#pragma unroll
+            for (int v = 0; v < WPL; v++) {
+                const uint64_t x = bc[q][v] ^ ic[q];  // 1 = up-step in this row
+                up[v][q] = x & vm;
+                dn[v][q] = ~x & vm;
+            }
+        }
+        bool live = false;
+#pragma unroll
+        for (int v = 0; v < WPL; v++) {
+            uint64_t S[B];
+            PartialSum<KB>::sum(dn[v], S);
+            add_sticky<P, B>(D[v], S, dov[v]);
+            if (NEG) {
+                PartialSum<KB>::sum(up[v], S);
+                add_sticky<P, B>(U[v], S, uov[v]);
+            }
+            const uint64_t dead = dov[v] & (NEG ? uov[v] : ~0ull);
+            live |= active[v] && dead != ~0ull;
+        }
+        j = jn;
+        if (__ballot(live) == 0) break;
+#pragma unroll
+        for (int q = 0; q < KB; q++) {
+            ic[q] = in_[q];
+#pragma unroll
+            for (int v = 0; v < WPL; v++) bc[q][v] = bn[q][v];
+        }
+    }
+#else
     int j = 1;
     while (j < k) {
         const int n = (k - j) < KB ? (k - j) : KB;
@@ -158,7 +221,7 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
             for (int v = 0; v < WPL; v++) x[v] = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
-                const uint64_t *vec = pairs + (int64_t)(pd & 0x7fffffff) * w64;
+                const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * w64;
 #pragma unroll
                 for (int v = 0; v < WPL; v++) {
                     const uint64_t bits = active[v] ? vec[w + kWave * v] : 0ull;
@@ -188,6 +251,7 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
         j += n;
         if (__ballot(live) == 0) break;
     }
+#endif
 #pragma unroll
     for (int v = 0; v < WPL; v++) fit[v] = ~dov[v] | (NEG ? ~uov[v] : 0ull);
 }
@@ -260,21 +324,44 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     int32_t *s_aoff = reinterpret_cast<int32_t *>(s_bits + bits_words);
     uint16_t *s_acols = reinterpret_cast<uint16_t *>(s_aoff + EBIC_MAX_ARCHIVE + 1);
     // hit masks of the archive's columns, 64 per word (after the columns,
-    // 8-byte aligned)
-    uint64_t *s_ahit = reinterpret_cast<uint64_t *>(
-        reinterpret_cast<uintptr_t>(s_acols + acol_words + 3) & ~(uintptr_t)7);
+    // at the next 8-byte boundary; indexed from the LDS base so that the
+    // pointer stays an LDS one)
+    uint64_t *s_ahit =
+        s_dyn + ((size_t)sup_words * 8 + EBIC_MAX_K * 4 + (size_t)bits_words * 4 +
+                 (EBIC_MAX_ARCHIVE + 1) * 4 + (size_t)acol_words * 2 + 7) / 8;
     __shared__ int32_t s_bad, s_done, s_n;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int nwaves = blockDim.x / kWave;
-    const int64_t slot = blockIdx.x;
-    if (slot >= total_ind) return;  // whole workgroup
-    const int p = find_segment(sched, njobs, slot);
-    const int64_t rel = slot - sched[p], m = njobs - p;
+    // the grid has exactly total_ind workgroups
+    const uint32_t slot = blockIdx.x;
+    // phase of this slot: the last phase start at or below it. The starts
+    // and first rounds of kSchedBatch phases are loaded together
+    // (independent scalar loads), then selected in registers.
+    int p = 0;
+    int64_t st = 0, rd = 0;
+    for (int q0 = 0; q0 < njobs; q0 += kSchedBatch) {
+        int64_t qs[kSchedBatch], qr[kSchedBatch];
+#pragma unroll
+        for (int u = 0; u < kSchedBatch; u++) {
+            const int q = q0 + u < njobs ? q0 + u : njobs - 1;
+            qs[u] = sched[q];
+            qr[u] = sched[njobs + q];
+        }
+#pragma unroll
+        for (int u = 0; u < kSchedBatch; u++) {
+            if (q0 + u < njobs && (q0 + u == 0 || qs[u] <= (int64_t)slot)) {
+                p = q0 + u;
+                st = qs[u];
+                rd = qr[u];
+            }
+        }
+    }
+    const uint32_t rel = slot - (uint32_t)st, m = (uint32_t)(njobs - p);
     const DevJob &J = jobs[rel % m];
-    const int32_t oi = (int32_t)(sched[njobs + p] + rel / m);
-    const int32_t ind = J.order ? J.order[oi] : oi;
+    const int32_t oi = (int32_t)(rd + rel / m);
+    const int32_t ind = J.order ? gmem(J.order)[oi] : oi;
     if (ind < 0 || ind >= J.pop_size) return;  // whole workgroup: not a permutation
-    const int32_t beg = J.pop_off[ind], end = J.pop_off[ind + 1];
+    const int32_t beg = gmem(J.pop_off)[ind], end = gmem(J.pop_off)[ind + 1];
     const int k = end - beg;
     const bool bad0 = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
     const int t = bad0 ? 0 : tol(k, J.approx_permille);
@@ -296,15 +383,15 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     const bool arch_lds = K > 0 && J.arch_len <= acol_words;
     if (arch_lds && !bad0) {
         for (int q = threadIdx.x; q <= K; q += blockDim.x) {
-            const int32_t o = J.arch_off[q];
+            const int32_t o = gmem(J.arch_off)[q];
             s_aoff[q] = o < 0 ? 0 : (o > J.arch_len ? J.arch_len : o);
         }
-        for (int q = threadIdx.x; q < J.arch_len; q += blockDim.x) s_acols[q] = J.arch_cols[q];
+        for (int q = threadIdx.x; q < J.arch_len; q += blockDim.x) s_acols[q] = gmem(J.arch_cols)[q];
     }
     if (!bad0) {
         int lbad = 0;
         for (int j = threadIdx.x; j < k; j += blockDim.x) {
-            const int c = J.pop_cols[beg + j];
+            const int c = gmem(J.pop_cols)[beg + j];
             if (c >= J.cols) {
                 lbad = 1;
             } else {
@@ -313,7 +400,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
             }
             if (use_pairs) {
                 if (j > 0) {
-                    const int a = J.pop_cols[beg + j - 1];
+                    const int a = gmem(J.pop_cols)[beg + j - 1];
                     const int lo = a < c ? a : c, hi = a < c ? c : a;
                     if (hi < J.cols)
                         s_pd[j] = (int32_t)pair_index(lo, hi, J.cols) |
@@ -334,7 +421,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     if (wave < J.ipi) {
         const int32_t ch0 = wave * J.cpi;
         const int32_t ch1 = ch0 + J.cpi < J.nchunks ? ch0 + J.cpi : J.nchunks;
-        uint64_t *S = J.support + (int64_t)ind * J.w64;
+        auto *S = gmem(J.support) + (int64_t)ind * J.w64;
         if (bad) {
             for (int32_t w = ch0 * 64 + lane; w < ch1 * 64 && w < J.w64; w += kWave) S[w] = 0;
         } else {
@@ -399,10 +486,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     if (bad) {
         if (J.overlap)
-            for (int j = lane; j < K; j += kWave) J.overlap[(int64_t)ind * K + j] = 0;
+            for (int j = lane; j < K; j += kWave) gmem(J.overlap)[(int64_t)ind * K + j] = 0;
         if (lane == 0) {
-            J.count[ind] = -1;
-            J.fitness[ind] = -1.0;
+            gmem(J.count)[ind] = -1;
+            gmem(J.fitness)[ind] = -1.0;
         }
         return;
     }
@@ -439,8 +526,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
         } else {
             // from global memory: lane j holds arch_off[j] (one load for all
             // members); members' first 64 columns loaded kGGroup at a time
-            const int32_t aoff = lane <= K ? J.arch_off[lane] : 0;
-            const int32_t aoff_k = J.arch_off[K];
+            const int32_t aoff = lane <= K ? gmem(J.arch_off)[lane] : 0;
+            const int32_t aoff_k = gmem(J.arch_off)[K];
             auto clampo = [&](int32_t o) {
                 return o < 0 ? 0 : (o > J.arch_len ? J.arch_len : o);
             };
@@ -452,7 +539,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                     mb[u] = clampo(__builtin_amdgcn_readlane(aoff, j));
                     me[u] = clampo(j + 1 < kWave ? __builtin_amdgcn_readlane(aoff, j + 1) : aoff_k);
                     const int q = mb[u] + lane;
-                    col[u] = q < me[u] ? (int)J.arch_cols[q] : -1;
+                    col[u] = q < me[u] ? (int)gmem(J.arch_cols)[q] : -1;
                 }
 #pragma unroll
                 for (int u = 0; u < kGGroup; u++) {
@@ -460,7 +547,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                         int g = __popcll(__ballot(hit(col[u])));
                         for (int q0 = mb[u] + kWave; q0 < me[u]; q0 += kWave) {
                             const int q = q0 + lane;
-                            g += __popcll(__ballot(hit(q < me[u] ? (int)J.arch_cols[q] : -1)));
+                            g += __popcll(__ballot(hit(q < me[u] ? (int)gmem(J.arch_cols)[q] : -1)));
                         }
                         if (lane == j0 + u) my_g = g;
                     }
@@ -473,7 +560,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
         const bool my_need = lane < K && n > 0 &&
                              (J.overlap || 1000LL * my_g > (long long)J.overlap_permille * k);
         uint64_t need = __ballot(my_need);
-        const uint64_t *S = J.support + (int64_t)ind * J.w64;
+        const auto *S = gmem(J.support) + (int64_t)ind * J.w64;
         while (need) {
             int js[kHGroup];
 #pragma unroll
@@ -491,7 +578,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                     const int w = w0 + kWave * u;
 #pragma unroll
                     for (int g = 0; g < kHGroup; g++)
-                        aw[g][u] = w < J.w64 ? J.arch_support[(int64_t)js[g] * J.w64 + w] : 0ull;
+                        aw[g][u] = w < J.w64 ? gmem(J.arch_support)[(int64_t)js[g] * J.w64 + w] : 0ull;
                 }
 #pragma unroll
                 for (int u = 0; u < kHWords; u++) {
@@ -510,10 +597,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
         const bool over = lane < K && 1000LL * my_h * my_g > (long long)J.overlap_permille * n * k;
         mover = __popcll(__ballot(over));
     }
-    if (J.overlap && lane < K) J.overlap[(int64_t)ind * K + lane] = my_h;
+    if (J.overlap && lane < K) gmem(J.overlap)[(int64_t)ind * K + lane] = my_h;
     if (lane == 0) {
-        J.count[ind] = n;
-        J.fitness[ind] = ldexp(score, -mover);
+        gmem(J.count)[ind] = n;
+        gmem(J.fitness)[ind] = ldexp(score, -mover);
     }
 }
 

@@ -14,6 +14,19 @@ __device__ inline int tol(int k, int approx) {
 // Buffer resource over `bytes` bytes at `p`: loads through it take the
 // per-lane offset in a VGPR and a wave-uniform offset in an SGPR, and the
 // hardware returns 0 for any offset past the end.
+// A pointer into device (global) memory, typed as such: loads and stores
+// through it compile to global_* instructions. Generic pointers compile to
+// flat_* ones, which also count against the LDS/scalar wait counter, so an
+// LDS read issued after them waits for the memory load too.
+template <class T>
+__device__ inline const __attribute__((address_space(1))) T *gmem(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <class T>
+__device__ inline __attribute__((address_space(1))) T *gmem(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
                                              0x00020000);
