@@ -257,11 +257,12 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
 }
 
 // Widest counter the pair path instantiates for KB steps per group and WPL
-// words per lane: what keeps the evaluation kernel within 64 VGPRs (8 waves
-// per SIMD). Items with a larger tolerance (t >= 2^P) take the gather form.
+// words per lane: with one word per lane, what keeps the kernel within 64
+// VGPRs (8 waves per SIMD); with two, the widths past which registers climb
+// steeply. Items with a larger tolerance (t >= 2^P) take the gather form.
 template <int KB, int WPL>
 struct PairLimit {
-    static constexpr int P = WPL == 1 ? (KB == 4 ? 4 : 6) : (KB == 4 ? 3 : 4);
+    static constexpr int P = WPL == 1 ? (KB == 4 ? 6 : 8) : (KB == 4 ? 3 : 4);
     static constexpr int T = (1 << P) - 1;
 };
 
