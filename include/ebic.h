@@ -245,6 +245,8 @@ typedef struct ebic_bicluster {
     int32_t n_cols;
     const uint16_t *cols;
     double score;              /* size score s = n * 2^k */
+    const uint8_t *row_dir;    /* per row: 0 = follows the series' increasing trend
+                                  (within the tolerance), 1 = only the reversed one */
 } ebic_bicluster;
 
 #define EBIC_STOP_GENERATIONS 1 /* the iteration limit was reached            */
@@ -264,6 +266,18 @@ typedef struct ebic_result {
                                            so far (after each evaluation)       */
 } ebic_result;
 
+/* Device memory for the method's runs (ebic_run, sessions): alloc returns
+ * `bytes` of device memory usable on `stream` (NULL on failure, which the
+ * call reports as EBIC_ERR_OOM), release returns it. A NULL allocator means
+ * hipMalloc / hipFree. Every device buffer of a run (matrix, ranks, pair
+ * table, populations, outputs, archive, job table) comes from it; pinned
+ * host staging does not. */
+typedef struct ebic_allocator {
+    void *(*alloc)(void *ctx, size_t bytes, void *stream);
+    void (*release)(void *ctx, void *ptr, void *stream);
+    void *ctx;
+} ebic_allocator;
+
 /* The whole method (Sec. 2.4, steps 1-9) on a host float32 rows x cols
  * row-major matrix: random initial population of series (step 1), GPU
  * evaluation of every population (steps 2 and 7), top-rank list update
@@ -274,15 +288,44 @@ typedef struct ebic_result {
  * same result. The host parts follow the readings stated at the top of this
  * file and in the parameter comments; evaluation uses the pair table when
  * it fits in a quarter of the free device memory, else the gather form
- * (identical results). Device memory is allocated and freed inside the call.
- * Synchronous on `stream`. Errors: EBIC_ERR_INVALID_ARG (parameters:
+ * (identical results). Device memory comes from `alloc` (NULL: hipMalloc)
+ * and is returned before the call ends. Each bicluster carries its rows'
+ * directions. Synchronous on `stream`. Errors: EBIC_ERR_INVALID_ARG (parameters:
  * 2 <= k_min <= k_max <= min(cols, 512), population >= 1, generations >= 1,
  * 1 <= archive_size <= 64, tournament >= 1, max_attempts >= 1,
  * max_tabu_hits >= 1, n_out >= 0), EBIC_ERR_NONFINITE, EBIC_ERR_OOM,
  * EBIC_ERR_DEVICE. On success *out is set. */
 int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
-             void *stream, ebic_result **out);
+             const ebic_allocator *alloc, void *stream, ebic_result **out);
 void ebic_result_free(ebic_result *r);
+
+/* A run of the method that advances in steps and can be checkpointed: the
+ * same computation as ebic_run, whose result it reproduces bit for bit,
+ * however the steps are split and wherever it is checkpointed and restored.
+ * create copies the matrix, ingests it and draws the first population
+ * (step 1). step performs up to `steps` evaluations (each one population
+ * scored against the top-rank list and the host steps that follow, or the
+ * final scoring of the top-rank list, step 9) and sets *done once the run
+ * has finished. checkpoint serialises the run's host state between steps
+ * (parameters, generator state, generation, tabu list and hits, top-rank
+ * list with supports, population, trace, and a hash of the matrix): with
+ * buf NULL it sets *bytes to the size needed; else *bytes must be at least
+ * that size and receives the size written. restore rebuilds a session from
+ * a checkpoint and the same matrix (EBIC_ERR_INVALID_ARG for a malformed
+ * checkpoint or another matrix). result returns the run's result once done
+ * (caller frees it with ebic_result_free). The allocator, when given, must
+ * outlive the session. Errors as ebic_run. */
+typedef struct ebic_session ebic_session;
+int ebic_session_create(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                        uint64_t seed, const ebic_allocator *alloc, void *stream,
+                        ebic_session **out);
+int ebic_session_step(ebic_session *s, int32_t steps, int32_t *done);
+int ebic_session_checkpoint(ebic_session *s, void *buf, size_t *bytes);
+int ebic_session_restore(const float *h_x, int32_t rows, int32_t cols, const void *buf,
+                         size_t bytes, const ebic_allocator *alloc, void *stream,
+                         ebic_session **out);
+int ebic_session_result(ebic_session *s, ebic_result **out);
+void ebic_session_free(ebic_session *s);
 
 /* Job server: continuous batching of many runs of the method (each as in
  * ebic_run) on one GPU. A scheduler thread admits submitted jobs in arrival

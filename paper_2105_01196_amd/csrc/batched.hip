@@ -507,7 +507,6 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
             // from LDS: one ballot per 64 archive columns marks those in the
             // series; lane j then counts the marks in its member's range
             const int nblk = (J.arch_len + kWave - 1) / kWave;
-#pragma unroll 4
             for (int bb = 0; bb < nblk; bb++) {
                 const int q = bb * kWave + lane;
                 const uint64_t hm = __ballot(q < J.arch_len && hit(s_acols[q]));
@@ -618,6 +617,8 @@ struct Batch {
     DevJob *d_jobs = nullptr;  // device: DevJob[njobs] by population size, descending;
     int64_t *d_sched = nullptr;  // then the schedule (phase starts, phase rounds)
     int32_t cap_jobs = 0;      // capacity of d_jobs / h_stage
+    const ebic_allocator *al = nullptr;  // device memory of d_jobs (NULL: hipMalloc)
+    hipStream_t al_stream = nullptr;
     void *h_stage = nullptr;   // pinned staging of the table
     std::vector<void *> scratch;
     int64_t total_ind = 0;     // kept alive: the graph's kernel arguments
@@ -732,13 +733,13 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
     b->acol_words = amax <= kArchLdsCols ? amax : 0;
     const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 2 * n;
     if (n > b->cap_jobs) {
-        if (b->d_jobs) (void)hipFree(b->d_jobs);
+        if (b->d_jobs) device_release(b->al, b->d_jobs, b->al_stream);
         if (b->h_stage) (void)hipHostFree(b->h_stage);
         b->d_jobs = nullptr;
         b->h_stage = nullptr;
         b->cap_jobs = 0;
-        void *mem = nullptr;
-        EBIC_HIP(hipMalloc(&mem, bytes));
+        void *mem = device_alloc(b->al, bytes, b->al_stream);
+        if (!mem) return fail(EBIC_ERR_OOM, "batch job table (%zu bytes)", bytes);
         b->d_jobs = static_cast<DevJob *>(mem);
         EBIC_HIP(hipHostMalloc(&b->h_stage, bytes, hipHostMallocDefault));
         b->cap_jobs = n;
@@ -969,7 +970,8 @@ int tune(Batch *b, hipStream_t stream) {
 // output): the job table and the start arrays go to the device with one
 // asynchronous copy on `stream` from pinned staging, reusing the device
 // table when it is large enough. Creates the batch when *bp is NULL.
-int batch_set(Batch **bp, const ebic_job *jobs, int32_t njobs, hipStream_t stream) {
+int batch_set(Batch **bp, const ebic_job *jobs, int32_t njobs, hipStream_t stream,
+              const ebic_allocator *al) {
     if (!bp || njobs < 1 || !jobs) return fail(EBIC_ERR_INVALID_ARG, "no jobs");
     for (int i = 0; i < njobs; i++) {
         int rc = check_job(&jobs[i], i);
@@ -980,6 +982,8 @@ int batch_set(Batch **bp, const ebic_job *jobs, int32_t njobs, hipStream_t strea
     Batch *b = *bp;
     if (!b) {
         b = new Batch();
+        b->al = al;
+        b->al_stream = stream;
         EBIC_HIP(hipGetDevice(&b->device));
         b->cpi = default_cpi();
         *bp = b;
@@ -1115,7 +1119,7 @@ int batch_destroy(Batch *b) {
     for (hipEvent_t e : b->events) (void)hipEventDestroy(e);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    if (b->d_jobs) device_release(b->al, b->d_jobs, b->al_stream);
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     for (void *p : b->scratch) (void)hipFree(p);
     delete b;

@@ -266,10 +266,43 @@ int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream) {
 }
 
 int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
-             void *stream, ebic_result **out) {
+             const ebic_allocator *alloc, void *stream, ebic_result **out) {
     clear_error();
-    return run_method(h_x, rows, cols, p, seed, static_cast<hipStream_t>(stream), out);
+    return run_method(h_x, rows, cols, p, seed, alloc, static_cast<hipStream_t>(stream), out);
 }
+
+int ebic_session_create(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                        uint64_t seed, const ebic_allocator *alloc, void *stream,
+                        ebic_session **out) {
+    clear_error();
+    return session_create(h_x, rows, cols, p, seed, alloc, static_cast<hipStream_t>(stream),
+                          reinterpret_cast<Session **>(out));
+}
+
+int ebic_session_step(ebic_session *s, int32_t steps, int32_t *done) {
+    clear_error();
+    return session_step(reinterpret_cast<Session *>(s), steps, done);
+}
+
+int ebic_session_checkpoint(ebic_session *s, void *buf, size_t *bytes) {
+    clear_error();
+    return session_checkpoint(reinterpret_cast<Session *>(s), buf, bytes);
+}
+
+int ebic_session_restore(const float *h_x, int32_t rows, int32_t cols, const void *buf,
+                         size_t bytes, const ebic_allocator *alloc, void *stream,
+                         ebic_session **out) {
+    clear_error();
+    return session_restore(h_x, rows, cols, buf, bytes, alloc, static_cast<hipStream_t>(stream),
+                           reinterpret_cast<Session **>(out));
+}
+
+int ebic_session_result(ebic_session *s, ebic_result **out) {
+    clear_error();
+    return session_result(reinterpret_cast<Session *>(s), out);
+}
+
+void ebic_session_free(ebic_session *s) { session_free(reinterpret_cast<Session *>(s)); }
 
 void ebic_result_free(ebic_result *r) {
     if (r) free_result(r);

@@ -67,8 +67,18 @@ int launch_build_pairs(const uint16_t *ranks, int32_t cols, int32_t rows_pad, ui
                        hipStream_t stream);
 
 int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
-               hipStream_t stream, ebic_result **out);
+               const ebic_allocator *al, hipStream_t stream, ebic_result **out);
 void free_result(ebic_result *r);
+
+struct Session;
+int session_create(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                   uint64_t seed, const ebic_allocator *al, hipStream_t stream, Session **out);
+int session_step(Session *s, int32_t steps, int32_t *done);
+int session_checkpoint(Session *s, void *buf, size_t *bytes);
+int session_restore(const float *h_x, int32_t rows, int32_t cols, const void *buf, size_t bytes,
+                    const ebic_allocator *al, hipStream_t stream, Session **out);
+int session_result(Session *s, ebic_result **out);
+void session_free(Session *s);
 
 class Server;
 int server_create(const ebic_server_config *cfg, Server **out);
@@ -81,7 +91,11 @@ void server_destroy(Server *s);
 struct Batch;
 int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out);
 int batch_run(Batch *b, hipStream_t stream);
-int batch_set(Batch **b, const ebic_job *jobs, int32_t njobs, hipStream_t stream);
+int batch_set(Batch **b, const ebic_job *jobs, int32_t njobs, hipStream_t stream,
+              const ebic_allocator *al = nullptr);
+// Device memory from the caller's allocator when one is given, else hipMalloc.
+void *device_alloc(const ebic_allocator *al, size_t bytes, hipStream_t stream);
+void device_release(const ebic_allocator *al, void *p, hipStream_t stream);
 int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb, int32_t *wpl);
 int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb, int32_t wpl);
 int batch_destroy(Batch *b);

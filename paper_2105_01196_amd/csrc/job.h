@@ -17,6 +17,8 @@ namespace ebic {
 class SplitMix64 {
   public:
     explicit SplitMix64(uint64_t seed) : state_(seed) {}
+    uint64_t state() const { return state_; }
+    void set_state(uint64_t s) { state_ = s; }
     uint64_t next() {
         state_ += 0x9E3779B97F4A7C15ULL;
         uint64_t z = state_;
@@ -75,6 +77,7 @@ struct ResultImpl {
     ebic_result pub{};
     std::vector<ebic_bicluster> bcs;
     std::vector<std::vector<int32_t>> rows;
+    std::vector<std::vector<uint8_t>> dirs;
     std::vector<Series> cols;
     std::vector<double> trace;
 };
@@ -83,12 +86,24 @@ template <typename T>
 struct DeviceArray {
     T *p = nullptr;
     size_t n = 0;
-    ~DeviceArray() {
-        if (p) (void)hipFree(p);
+    const ebic_allocator *al = nullptr;
+    hipStream_t st = nullptr;
+    DeviceArray() = default;
+    DeviceArray(const DeviceArray &) = delete;
+    DeviceArray &operator=(const DeviceArray &) = delete;
+    ~DeviceArray() { reset(); }
+    void reset() {
+        if (p) device_release(al, p, st);
+        p = nullptr;
+        n = 0;
     }
-    hipError_t alloc(size_t count) {
+    hipError_t alloc(size_t count, const ebic_allocator *a = nullptr, hipStream_t s = nullptr) {
+        reset();
         n = count ? count : 1;
-        return hipMalloc(reinterpret_cast<void **>(&p), n * sizeof(T));
+        al = a;
+        st = s;
+        p = static_cast<T *>(device_alloc(al, n * sizeof(T), st));
+        return p ? hipSuccess : hipErrorOutOfMemory;
     }
 };
 
@@ -128,6 +143,24 @@ class Job {
     bool done() const { return phase_ == Phase::Done; }
     ResultImpl *take_result() { return res_.release(); }
     int64_t evaluations() const { return evaluations_; }
+    // Device memory from `al` (copied; NULL: hipMalloc); set before setup.
+    void set_allocator(const ebic_allocator *al) {
+        if (al) {
+            alloc_ = *al;
+            al_ = &alloc_;
+        }
+    }
+    const ebic_allocator *allocator() const { return al_; }
+    // The host matrix (rows x cols, row-major), read by the final step for
+    // the rows' directions; it must stay valid while the job runs.
+    void set_host_matrix(const float *hx) { hx_ = hx; }
+    // Host state between steps, as bytes (see ebic_session_checkpoint).
+    void save(std::vector<uint8_t> &out, uint64_t matrix_hash) const;
+    // Reads a checkpoint's header; false if it is not one.
+    static bool peek(const uint8_t *p, size_t n, ebic_params *params, int32_t *rows,
+                     int32_t *cols, uint64_t *matrix_hash);
+    // Restores the host state (after setup); EBIC_ERR_INVALID_ARG if malformed.
+    int load(const uint8_t *p, size_t n);
 
   private:
     enum class Phase { Eval, FinalEval, Done };
@@ -140,6 +173,9 @@ class Job {
     double size_score(int32_t n, int k) const {
         return (n >= p_.min_rows && k >= p_.k_score_min) ? std::ldexp((double)n, k) : 0.0;
     }
+    // Per row: 0 if it follows the series' increasing trend within the
+    // tolerance, else 1 (it is in the support, so the reversed one fits).
+    std::vector<uint8_t> row_directions(const std::vector<int32_t> &rows, const Series &s) const;
     int64_t shared_rows(const uint64_t *a, const uint64_t *b) const {
         int64_t h = 0;
         for (int w = 0; w < W_; w++) h += __builtin_popcountll(a[w] & b[w]);
@@ -156,6 +192,9 @@ class Job {
     SplitMix64 rng_;
     hipStream_t stream_;
     bool neg_;
+    ebic_allocator alloc_{};
+    const ebic_allocator *al_ = nullptr;
+    const float *hx_ = nullptr;
     int32_t R_ = 0, C_ = 0, W_ = 0;
     ebic_matrix m_{};
     DeviceArray<float> d_x_;
@@ -187,5 +226,7 @@ class Job {
 };
 
 int check_run_params(int32_t rows, int32_t cols, const ebic_params *p);
+// 64-bit hash of a float matrix's bytes (FNV-1a over 8-byte words).
+uint64_t matrix_hash(const float *x, size_t n);
 
 }  // namespace ebic

@@ -33,29 +33,29 @@ int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs) {
     R_ = rows;
     C_ = cols;
     const int32_t P = p_.population, K = p_.archive_size, kmax = p_.k_max;
-    RUN_HIP(d_x_.alloc((size_t)rows * cols));
+    RUN_HIP(d_x_.alloc((size_t)rows * cols, al_, stream_));
     RUN_HIP(hipMemcpyAsync(d_x_.p, h_x, sizeof(float) * rows * cols, hipMemcpyHostToDevice,
                            stream_));
-    RUN_HIP(d_ranks_.alloc(ebic_matrix_bytes(rows, cols) / sizeof(uint16_t)));
+    RUN_HIP(d_ranks_.alloc(ebic_matrix_bytes(rows, cols) / sizeof(uint16_t), al_, stream_));
     int rc = ebic_matrix_prepare(d_x_.p, rows, cols, d_ranks_.p, &m_, stream_);
     if (rc) return rc;
     W_ = m_.rows_pad / 64;
     const size_t pair_bytes = ebic_pairs_bytes(rows, cols);
     if (pairs && pair_bytes > 0) {
-        RUN_HIP(d_pairs_.alloc(pair_bytes / sizeof(uint64_t)));
+        RUN_HIP(d_pairs_.alloc(pair_bytes / sizeof(uint64_t), al_, stream_));
         rc = ebic_pairs_prepare(&m_, d_pairs_.p, stream_);
         if (rc) return rc;
     }
     const int32_t nmax = std::max(P, K);
-    RUN_HIP(d_off_.alloc(nmax + 1));
-    RUN_HIP(d_order_.alloc(nmax));
-    RUN_HIP(d_cols_.alloc((size_t)nmax * kmax));
-    RUN_HIP(d_fit_.alloc(nmax));
-    RUN_HIP(d_cnt_.alloc(nmax));
-    RUN_HIP(d_sup_.alloc((size_t)nmax * W_));
-    RUN_HIP(d_asup_.alloc((size_t)K * W_));
-    RUN_HIP(d_aoff_.alloc(K + 1));
-    RUN_HIP(d_acols_.alloc((size_t)K * kmax));
+    RUN_HIP(d_off_.alloc(nmax + 1, al_, stream_));
+    RUN_HIP(d_order_.alloc(nmax, al_, stream_));
+    RUN_HIP(d_cols_.alloc((size_t)nmax * kmax, al_, stream_));
+    RUN_HIP(d_fit_.alloc(nmax, al_, stream_));
+    RUN_HIP(d_cnt_.alloc(nmax, al_, stream_));
+    RUN_HIP(d_sup_.alloc((size_t)nmax * W_, al_, stream_));
+    RUN_HIP(d_asup_.alloc((size_t)K * W_, al_, stream_));
+    RUN_HIP(d_aoff_.alloc(K + 1, al_, stream_));
+    RUN_HIP(d_acols_.alloc((size_t)K * kmax, al_, stream_));
     RUN_HIP(h_off_.alloc(nmax + 1));
     RUN_HIP(h_order_.alloc(nmax));
     RUN_HIP(h_cols_.alloc((size_t)nmax * kmax));
@@ -346,9 +346,9 @@ int Job::finish() {
         std::vector<int32_t> sel(nb), roff(nb + 1, 0);
         std::iota(sel.begin(), sel.end(), 0);
         for (int32_t j = 0; j < nb; j++) roff[j + 1] = roff[j] + count_[j];
-        RUN_HIP(d_sel_.alloc(nb));
-        RUN_HIP(d_roff_.alloc(nb + 1));
-        RUN_HIP(d_rows_.alloc(std::max(roff[nb], 1)));
+        RUN_HIP(d_sel_.alloc(nb, al_, stream_));
+        RUN_HIP(d_roff_.alloc(nb + 1, al_, stream_));
+        RUN_HIP(d_rows_.alloc(std::max(roff[nb], 1), al_, stream_));
         RUN_HIP(hipMemcpyAsync(d_sel_.p, sel.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice,
                                stream_));
         RUN_HIP(hipMemcpyAsync(d_roff_.p, roff.data(), sizeof(int32_t) * (nb + 1),
@@ -363,6 +363,7 @@ int Job::finish() {
         for (int32_t j = 0; j < nb; j++) {
             res->rows.emplace_back(rows.begin() + roff[j], rows.begin() + roff[j + 1]);
             res->cols.push_back(pop_[j]);
+            res->dirs.push_back(row_directions(res->rows[j], pop_[j]));
         }
         for (int32_t j = 0; j < nb; j++) {
             ebic_bicluster b{};
@@ -371,6 +372,7 @@ int Job::finish() {
             b.n_cols = (int32_t)res->cols[j].size();
             b.cols = res->cols[j].data();
             b.score = size_score(count_[j], (int)pop_[j].size());
+            b.row_dir = res->dirs[j].data();
             res->bcs.push_back(b);
         }
     }
@@ -396,40 +398,368 @@ int check_run_params(int32_t rows, int32_t cols, const ebic_params *p) {
     return EBIC_OK;
 }
 
-int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
-               hipStream_t stream, ebic_result **out) {
+void free_result(ebic_result *r) {
+    // pub is the first member of ResultImpl
+    delete reinterpret_cast<ResultImpl *>(r);
+}
+
+}  // namespace ebic
+
+namespace ebic {
+
+void *device_alloc(const ebic_allocator *al, size_t bytes, hipStream_t stream) {
+    if (al && al->alloc) return al->alloc(al->ctx, bytes, stream);
+    void *p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void device_release(const ebic_allocator *al, void *p, hipStream_t stream) {
+    if (!p) return;
+    if (al && al->release)
+        al->release(al->ctx, p, stream);
+    else if (!al || !al->alloc)
+        (void)hipFree(p);
+}
+
+std::vector<uint8_t> Job::row_directions(const std::vector<int32_t> &rows, const Series &s) const {
+    std::vector<uint8_t> dir(rows.size(), 0);
+    if (!hx_ || s.size() < 2) return dir;
+    const int k = (int)s.size();
+    const int t = (int)(((int64_t)(k - 1) * (1000 - p_.approx_permille)) / 1000);
+    for (size_t i = 0; i < rows.size(); i++) {
+        const float *x = hx_ + (size_t)rows[i] * C_;
+        int downs = 0;
+        for (int j = 0; j + 1 < k; j++) {
+            const int a = s[j], b = s[j + 1];
+            // a precedes b in this row: smaller value, ties by column index
+            const bool up = x[a] < x[b] || (x[a] == x[b] && a < b);
+            downs += !up;
+        }
+        dir[i] = downs <= t ? 0 : 1;
+    }
+    return dir;
+}
+
+uint64_t matrix_hash(const float *x, size_t n) {
+    uint64_t h = 0xCBF29CE484222325ULL ^ n;
+    const size_t bytes = n * sizeof(float);
+    const unsigned char *b = reinterpret_cast<const unsigned char *>(x);
+    size_t i = 0;
+    for (; i + 8 <= bytes; i += 8) {
+        uint64_t w;
+        std::memcpy(&w, b + i, 8);
+        h = (h ^ w) * 0x100000001B3ULL;
+    }
+    for (; i < bytes; i++) h = (h ^ b[i]) * 0x100000001B3ULL;
+    return h;
+}
+
+// ---- checkpoint format: a flat little-endian byte stream ----
+
+namespace {
+
+constexpr char kMagic[8] = {'E', 'B', 'I', 'C', 'C', 'K', 'P', '1'};
+constexpr uint32_t kVersion = 1;
+
+struct Writer {
+    std::vector<uint8_t> &out;
+    template <typename T>
+    void put(const T &v) {
+        const uint8_t *p = reinterpret_cast<const uint8_t *>(&v);
+        out.insert(out.end(), p, p + sizeof(T));
+    }
+    void series(const Series &s) {
+        put((uint16_t)s.size());
+        for (uint16_t c : s) put(c);
+    }
+};
+
+struct Reader {
+    const uint8_t *p;
+    size_t n, at = 0;
+    bool ok = true;
+    template <typename T>
+    T get() {
+        T v{};
+        if (!ok || n - at < sizeof(T)) {
+            ok = false;
+            return v;
+        }
+        std::memcpy(&v, p + at, sizeof(T));
+        at += sizeof(T);
+        return v;
+    }
+    Series series(int32_t cols) {
+        const uint16_t k = get<uint16_t>();
+        Series s;
+        if (!ok || k < 2 || k > EBIC_MAX_K) {
+            ok = false;
+            return s;
+        }
+        s.resize(k);
+        for (auto &c : s) {
+            c = get<uint16_t>();
+            if (c >= cols) ok = false;
+        }
+        return s;
+    }
+};
+
+}  // namespace
+
+void Job::save(std::vector<uint8_t> &out, uint64_t mhash) const {
+    out.clear();
+    Writer w{out};
+    for (char c : kMagic) w.put(c);
+    w.put(kVersion);
+    w.put(p_);
+    w.put(R_);
+    w.put(C_);
+    w.put(mhash);
+    w.put(rng_.state());
+    w.put((int32_t)phase_);
+    w.put((int32_t)stop_);
+    w.put(g_);
+    w.put(evaluations_);
+    w.put(tabu_hits_);
+    w.put((uint64_t)res_->trace.size());
+    for (double v : res_->trace) w.put(v);
+    w.put((uint32_t)pop_.size());
+    for (const Series &s : pop_) w.series(s);
+    w.put((uint32_t)archive_.size());
+    for (const Member &m : archive_) {
+        w.series(m.s);
+        w.put(m.n);
+        w.put(m.score);
+        for (int32_t q = 0; q < W_; q++) w.put(m.support[q]);
+    }
+    // the tabu list in a canonical (sorted) order, so that equal states
+    // give equal bytes
+    std::vector<const Series *> tabu;
+    tabu.reserve(tabu_.size());
+    for (const Series &s : tabu_) tabu.push_back(&s);
+    std::sort(tabu.begin(), tabu.end(), [](const Series *a, const Series *b) {
+        return a->size() != b->size() ? a->size() < b->size() : *a < *b;
+    });
+    w.put((uint64_t)tabu.size());
+    for (const Series *s : tabu) w.series(*s);
+    for (char c : kMagic) w.put(c);
+}
+
+bool Job::peek(const uint8_t *p, size_t n, ebic_params *params, int32_t *rows, int32_t *cols,
+               uint64_t *mhash) {
+    Reader r{p, n};
+    for (char c : kMagic)
+        if (r.get<char>() != c) return false;
+    if (r.get<uint32_t>() != kVersion) return false;
+    *params = r.get<ebic_params>();
+    *rows = r.get<int32_t>();
+    *cols = r.get<int32_t>();
+    *mhash = r.get<uint64_t>();
+    return r.ok;
+}
+
+int Job::load(const uint8_t *p, size_t n) {
+    Reader r{p, n};
+    ebic_params params;
+    int32_t rows, cols;
+    uint64_t mhash;
+    if (!peek(p, n, &params, &rows, &cols, &mhash) || rows != R_ || cols != C_)
+        return fail(EBIC_ERR_INVALID_ARG, "not a checkpoint of this run");
+    r.at = sizeof(kMagic) + sizeof(uint32_t) + sizeof(ebic_params) + 2 * sizeof(int32_t) +
+           sizeof(uint64_t);
+    rng_.set_state(r.get<uint64_t>());
+    const int32_t phase = r.get<int32_t>(), stop = r.get<int32_t>();
+    g_ = r.get<int32_t>();
+    evaluations_ = r.get<int64_t>();
+    tabu_hits_ = r.get<int64_t>();
+    if (!r.ok || phase < (int32_t)Phase::Eval || phase > (int32_t)Phase::FinalEval || stop < 0 ||
+        stop > EBIC_STOP_EXHAUSTED || g_ < 0 || g_ > p_.generations)
+        return fail(EBIC_ERR_INVALID_ARG, "malformed checkpoint (state)");
+    phase_ = (Phase)phase;
+    stop_ = stop;
+    const uint64_t nt = r.get<uint64_t>();
+    if (!r.ok || nt != 4 * (uint64_t)g_) return fail(EBIC_ERR_INVALID_ARG, "malformed checkpoint (trace)");
+    res_->trace.resize(nt);
+    for (auto &v : res_->trace) v = r.get<double>();
+    const uint32_t np = r.get<uint32_t>();
+    if (!r.ok || np > (uint32_t)std::max(p_.population, p_.archive_size))
+        return fail(EBIC_ERR_INVALID_ARG, "malformed checkpoint (population)");
+    pop_.clear();
+    for (uint32_t i = 0; i < np && r.ok; i++) pop_.push_back(r.series(C_));
+    const uint32_t na = r.get<uint32_t>();
+    if (!r.ok || na > (uint32_t)p_.archive_size)
+        return fail(EBIC_ERR_INVALID_ARG, "malformed checkpoint (top-rank list)");
+    archive_.clear();
+    for (uint32_t j = 0; j < na && r.ok; j++) {
+        Member m;
+        m.s = r.series(C_);
+        m.n = r.get<int32_t>();
+        m.score = r.get<double>();
+        m.support.resize(W_);
+        for (auto &wd : m.support) wd = r.get<uint64_t>();
+        archive_.push_back(std::move(m));
+    }
+    const uint64_t ntabu = r.get<uint64_t>();
+    tabu_.clear();
+    for (uint64_t i = 0; i < ntabu && r.ok; i++) tabu_.insert(r.series(C_));
+    for (char c : kMagic)
+        if (r.get<char>() != c) r.ok = false;
+    if (!r.ok || r.at != n || tabu_.size() != ntabu)
+        return fail(EBIC_ERR_INVALID_ARG, "malformed checkpoint");
+    use_.assign(C_, 0);
+    return EBIC_OK;
+}
+
+// ---- sessions: a run in steps, with checkpoints ----
+
+struct Session {
+    std::vector<float> own;  // the session's copy of the matrix (unless borrowed)
+    const float *x = nullptr;
+    int32_t rows = 0, cols = 0;
+    hipStream_t stream = nullptr;
+    std::unique_ptr<Job> job;
+    Batch *batch = nullptr;
+    bool taken = false;
+    ~Session() {
+        if (batch) batch_destroy(batch);
+    }
+};
+
+namespace {
+
+// Allocates the job's device state on the session's matrix.
+int session_setup(Session *s, const ebic_params &p, uint64_t seed, const ebic_allocator *al) {
+    size_t free_b = 0, total_b = 0;
+    EBIC_HIP(hipMemGetInfo(&free_b, &total_b));
+    const size_t pair_bytes = ebic_pairs_bytes(s->rows, s->cols);
+    s->job.reset(new Job(p, seed, s->stream));
+    s->job->set_allocator(al);
+    s->job->set_host_matrix(s->x);
+    return s->job->setup(s->x, s->rows, s->cols, pair_bytes > 0 && pair_bytes <= free_b / 4);
+}
+
+int session_open(const float *h_x, int32_t rows, int32_t cols, bool copy, hipStream_t stream,
+                 std::unique_ptr<Session> *out) {
+    std::unique_ptr<Session> s(new Session());
+    s->rows = rows;
+    s->cols = cols;
+    s->stream = stream;
+    if (copy) {
+        s->own.assign(h_x, h_x + (size_t)rows * cols);
+        s->x = s->own.data();
+    } else {
+        s->x = h_x;
+    }
+    *out = std::move(s);
+    return EBIC_OK;
+}
+
+int session_begin(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                  uint64_t seed, const ebic_allocator *al, hipStream_t stream, bool copy,
+                  std::unique_ptr<Session> *out) {
     if (!h_x || !p || !out) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
     int rc = check_run_params(rows, cols, p);
     if (rc) return rc;
-    size_t free_b = 0, total_b = 0;
-    EBIC_HIP(hipMemGetInfo(&free_b, &total_b));
-    const size_t pair_bytes = ebic_pairs_bytes(rows, cols);
-    Job job(*p, seed, stream);
-    rc = job.setup(h_x, rows, cols, pair_bytes > 0 && pair_bytes <= free_b / 4);
+    std::unique_ptr<Session> s;
+    rc = session_open(h_x, rows, cols, copy, stream, &s);
+    if (rc == EBIC_OK) rc = session_setup(s.get(), *p, seed, al);
     if (rc) return rc;
-    job.start();
-    Batch *batch = nullptr;
-    while (rc == EBIC_OK && !job.done()) {
+    s->job->start();
+    *out = std::move(s);
+    return EBIC_OK;
+}
+
+}  // namespace
+
+int session_step(Session *s, int32_t steps, int32_t *done) {
+    if (!s || !s->job || steps < 0) return fail(EBIC_ERR_INVALID_ARG, "bad session or steps");
+    Job &job = *s->job;
+    int rc = EBIC_OK;
+    for (int32_t i = 0; i < steps && rc == EBIC_OK && !job.done(); i++) {
         ebic_job view;
         rc = job.stage(&view);
-        if (rc == EBIC_OK) rc = batch_set(&batch, &view, 1, stream);
-        if (rc == EBIC_OK) rc = batch_run(batch, stream);
+        if (rc == EBIC_OK) rc = batch_set(&s->batch, &view, 1, s->stream, job.allocator());
+        if (rc == EBIC_OK) rc = batch_run(s->batch, s->stream);
         if (rc == EBIC_OK) rc = job.fetch();
         if (rc == EBIC_OK) {
-            hipError_t e = hipStreamSynchronize(stream);
+            hipError_t e = hipStreamSynchronize(s->stream);
             if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
         }
         if (rc == EBIC_OK) rc = job.advance();
     }
-    if (batch) batch_destroy(batch);
+    if (done) *done = job.done() ? 1 : 0;
+    return rc;
+}
+
+int session_create(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                   uint64_t seed, const ebic_allocator *al, hipStream_t stream, Session **out) {
+    if (!out) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
+    std::unique_ptr<Session> s;
+    int rc = session_begin(h_x, rows, cols, p, seed, al, stream, true, &s);
     if (rc) return rc;
-    *out = &job.take_result()->pub;
+    *out = s.release();
     return EBIC_OK;
 }
 
-void free_result(ebic_result *r) {
-    // pub is the first member of ResultImpl
-    delete reinterpret_cast<ResultImpl *>(r);
+int session_checkpoint(Session *s, void *buf, size_t *bytes) {
+    if (!s || !s->job || !bytes) return fail(EBIC_ERR_INVALID_ARG, "bad session or size");
+    if (s->job->done()) return fail(EBIC_ERR_INVALID_ARG, "the run has finished");
+    std::vector<uint8_t> blob;
+    s->job->save(blob, matrix_hash(s->x, (size_t)s->rows * s->cols));
+    if (!buf) {
+        *bytes = blob.size();
+        return EBIC_OK;
+    }
+    if (*bytes < blob.size()) return fail(EBIC_ERR_INVALID_ARG, "buffer too small");
+    std::memcpy(buf, blob.data(), blob.size());
+    *bytes = blob.size();
+    return EBIC_OK;
+}
+
+int session_restore(const float *h_x, int32_t rows, int32_t cols, const void *buf, size_t bytes,
+                    const ebic_allocator *al, hipStream_t stream, Session **out) {
+    if (!h_x || !buf || !out) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
+    const uint8_t *b = static_cast<const uint8_t *>(buf);
+    ebic_params p;
+    int32_t r0, c0;
+    uint64_t mh;
+    if (!Job::peek(b, bytes, &p, &r0, &c0, &mh))
+        return fail(EBIC_ERR_INVALID_ARG, "not a checkpoint");
+    if (r0 != rows || c0 != cols) return fail(EBIC_ERR_INVALID_ARG, "checkpoint of another shape");
+    int rc = check_run_params(rows, cols, &p);
+    if (rc) return rc;
+    if (matrix_hash(h_x, (size_t)rows * cols) != mh)
+        return fail(EBIC_ERR_INVALID_ARG, "checkpoint of another matrix");
+    std::unique_ptr<Session> s;
+    rc = session_open(h_x, rows, cols, true, stream, &s);
+    if (rc == EBIC_OK) rc = session_setup(s.get(), p, 0, al);
+    if (rc == EBIC_OK) rc = s->job->load(b, bytes);
+    if (rc) return rc;
+    *out = s.release();
+    return EBIC_OK;
+}
+
+int session_result(Session *s, ebic_result **out) {
+    if (!s || !s->job || !out) return fail(EBIC_ERR_INVALID_ARG, "bad session");
+    if (!s->job->done() || s->taken) return fail(EBIC_ERR_INVALID_ARG, "no result to take");
+    s->taken = true;
+    *out = &s->job->take_result()->pub;
+    return EBIC_OK;
+}
+
+void session_free(Session *s) { delete s; }
+
+int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
+               const ebic_allocator *al, hipStream_t stream, ebic_result **out) {
+    if (!out) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
+    std::unique_ptr<Session> s;
+    // the caller's matrix stays valid for the whole (synchronous) call
+    int rc = session_begin(h_x, rows, cols, p, seed, al, stream, false, &s);
+    int32_t done = 0;
+    while (rc == EBIC_OK && !done) rc = session_step(s.get(), 1 << 30, &done);
+    if (rc) return rc;
+    return session_result(s.get(), out);
 }
 
 }  // namespace ebic

@@ -319,6 +319,7 @@ void Server::loop() {
         }
         for (auto &j : admit) {
             j->job.reset(new Job(j->params, j->seed, stream_));
+            j->job->set_host_matrix(j->x.data());  // the job's own copy, for row directions
             int rc = j->job->setup(j->x.data(), j->rows, j->cols, j->pairs);
             if (rc == EBIC_OK) {
                 j->job->start();

@@ -72,7 +72,16 @@ class ebic_job(ctypes.Structure):
 
 class ebic_bicluster(ctypes.Structure):
     _fields_ = [("n_rows", _i32), ("rows", ctypes.POINTER(_i32)), ("n_cols", _i32),
-                ("cols", ctypes.POINTER(ctypes.c_uint16)), ("score", ctypes.c_double)]
+                ("cols", ctypes.POINTER(ctypes.c_uint16)), ("score", ctypes.c_double),
+                ("row_dir", ctypes.POINTER(ctypes.c_uint8))]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(_vp, _vp, ctypes.c_size_t, _vp)
+RELEASE_FN = ctypes.CFUNCTYPE(None, _vp, _vp, _vp)
+
+
+class ebic_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("ctx", _vp)]
 
 
 class ebic_result(ctypes.Structure):
@@ -124,7 +133,18 @@ _SIGNATURES = {
     "ebic_batch_destroy": (ctypes.c_int, [_vp]),
     "ebic_evaluate_batched": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _vp]),
     "ebic_run": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params), ctypes.c_uint64,
-                                _vp, ctypes.POINTER(ctypes.POINTER(ebic_result))]),
+                                ctypes.POINTER(ebic_allocator), _vp,
+                                ctypes.POINTER(ctypes.POINTER(ebic_result))]),
+    "ebic_session_create": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params),
+                                           ctypes.c_uint64, ctypes.POINTER(ebic_allocator), _vp,
+                                           ctypes.POINTER(_vp)]),
+    "ebic_session_step": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i32)]),
+    "ebic_session_checkpoint": (ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)]),
+    "ebic_session_restore": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.c_size_t,
+                                            ctypes.POINTER(ebic_allocator), _vp,
+                                            ctypes.POINTER(_vp)]),
+    "ebic_session_result": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.POINTER(ebic_result))]),
+    "ebic_session_free": (None, [_vp]),
     "ebic_result_free": (None, [ctypes.POINTER(ebic_result)]),
     "ebic_server_create": (ctypes.c_int, [ctypes.POINTER(ebic_server_config),
                                           ctypes.POINTER(_vp)]),
@@ -482,6 +502,7 @@ class Bicluster:
     rows: np.ndarray      # int64, ascending
     cols: np.ndarray      # int64, series order
     score: float
+    row_dir: np.ndarray   # uint8 per row: 0 increasing trend, 1 reversed only
 
     @property
     def n(self) -> int:
@@ -508,7 +529,9 @@ def _take_result(res) -> RunResult:
             rows = np.ctypeslib.as_array(b.rows, (b.n_rows,)).astype(np.int64) if b.n_rows \
                 else np.zeros(0, np.int64)
             cols = np.ctypeslib.as_array(b.cols, (b.n_cols,)).astype(np.int64)
-            bcs.append(Bicluster(rows.copy(), cols.copy(), float(b.score)))
+            dirs = np.ctypeslib.as_array(b.row_dir, (b.n_rows,)).copy() if b.n_rows \
+                else np.zeros(0, np.uint8)
+            bcs.append(Bicluster(rows.copy(), cols.copy(), float(b.score), dirs))
         g = r.generations
         trace = np.ctypeslib.as_array(r.trace, (g * 4,)).reshape(g, 4).copy() if g else \
             np.zeros((0, 4))
@@ -517,14 +540,106 @@ def _take_result(res) -> RunResult:
         lib().ebic_result_free(res)
 
 
-def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None) -> RunResult:
+class TorchAllocator:
+    """ebic_allocator backed by torch's caching allocator (device memory of
+    a run then comes from, and returns to, torch's pool). Counts the calls."""
+
+    def __init__(self, device=None):
+        self.device = torch.cuda.current_device() if device is None else device
+        self.allocs = 0
+        self.releases = 0
+        self.live = set()
+
+        def _alloc(ctx, nbytes, stream):
+            try:
+                p = torch.cuda.caching_allocator_alloc(int(nbytes), self.device,
+                                                       stream if stream else None)
+            except RuntimeError:
+                return None
+            self.allocs += 1
+            self.live.add(int(p))
+            return p
+
+        def _release(ctx, ptr, stream):
+            self.releases += 1
+            self.live.discard(int(ptr))
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._a = ALLOC_FN(_alloc)
+        self._r = RELEASE_FN(_release)
+        self.view = ebic_allocator(self._a, self._r, None)
+
+
+def _alloc_ref(alloc):
+    return ctypes.byref(alloc.view) if alloc is not None else None
+
+
+def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None,
+             alloc: Optional[TorchAllocator] = None) -> RunResult:
     """The whole method on a host float32 matrix (synchronous)."""
     x = np.ascontiguousarray(x, dtype=np.float32)
     R, C = x.shape
     res = ctypes.POINTER(ebic_result)()
     _check(lib().ebic_run(x.ctypes.data, R, C, ctypes.byref(params), ctypes.c_uint64(seed),
-                          _stream(stream), ctypes.byref(res)))
+                          _alloc_ref(alloc), _stream(stream), ctypes.byref(res)))
     return _take_result(res)
+
+
+class Session:
+    """A run of the method in steps, with checkpoints (ebic_session_*)."""
+
+    def __init__(self, handle, alloc=None):
+        self.handle = handle
+        self.alloc = alloc  # kept alive while the session holds its memory
+
+    @classmethod
+    def create(cls, x: np.ndarray, params: ebic_params, seed: int, stream=None,
+               alloc: Optional[TorchAllocator] = None) -> "Session":
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        h = _vp()
+        _check(lib().ebic_session_create(x.ctypes.data, x.shape[0], x.shape[1],
+                                         ctypes.byref(params), ctypes.c_uint64(seed),
+                                         _alloc_ref(alloc), _stream(stream), ctypes.byref(h)))
+        return cls(h, alloc)
+
+    @classmethod
+    def restore(cls, x: np.ndarray, blob: bytes, stream=None,
+                alloc: Optional[TorchAllocator] = None) -> "Session":
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        buf = ctypes.create_string_buffer(bytes(blob), len(blob))
+        h = _vp()
+        _check(lib().ebic_session_restore(x.ctypes.data, x.shape[0], x.shape[1], buf, len(blob),
+                                          _alloc_ref(alloc), _stream(stream), ctypes.byref(h)))
+        return cls(h, alloc)
+
+    def step(self, steps: int) -> bool:
+        """Up to `steps` evaluations; True once the run has finished."""
+        done = _i32()
+        _check(lib().ebic_session_step(self.handle, steps, ctypes.byref(done)))
+        return bool(done.value)
+
+    def checkpoint(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        _check(lib().ebic_session_checkpoint(self.handle, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib().ebic_session_checkpoint(self.handle, buf, ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def result(self) -> RunResult:
+        res = ctypes.POINTER(ebic_result)()
+        _check(lib().ebic_session_result(self.handle, ctypes.byref(res)))
+        return _take_result(res)
+
+    def close(self) -> None:
+        if self.handle:
+            lib().ebic_session_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

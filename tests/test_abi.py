@@ -88,7 +88,7 @@ def test_run_rejects_bad_parameters_on_host():
                 dict(archive_size=65), dict(tournament=0), dict(max_tabu_hits=0),
                 dict(generations=0), dict(approx_permille=-1)):
         p = ebic.make_params(**{**dict(k_min=2, k_max=4), **bad})
-        rc = L.ebic_run(X.ctypes.data, 10, 5, ctypes.byref(p), 1, None, ctypes.byref(res))
+        rc = L.ebic_run(X.ctypes.data, 10, 5, ctypes.byref(p), 1, None, None, ctypes.byref(res))
         assert rc == ebic.EBIC_ERR_INVALID_ARG, bad
 
 
@@ -97,3 +97,25 @@ def test_batch_set_tuning_rejects_null_batch_on_host():
     L = ebic.lib()
     assert L.ebic_batch_set_tuning(None, 1, 2, 1) == ebic.EBIC_ERR_INVALID_ARG
     assert L.ebic_last_error()
+
+
+def test_session_restore_rejects_malformed_checkpoints_on_host():
+    """A checkpoint is checked (magic, version, shape, matrix hash, length)
+    before any device work, so these fail on a machine without a GPU."""
+    import numpy as np
+    from paper_2105_01196_amd import ebic
+    L = ebic.lib()
+    X = np.zeros((10, 5), np.float32)
+    h = ctypes.c_void_p()
+    for blob in (b"", b"EBICCKP1", b"NOTACKPT" + bytes(200), bytes(300)):
+        buf = ctypes.create_string_buffer(blob, max(len(blob), 1))
+        rc = L.ebic_session_restore(X.ctypes.data, 10, 5, buf, len(blob), None, None,
+                                    ctypes.byref(h))
+        assert rc == ebic.EBIC_ERR_INVALID_ARG, blob[:8]
+        assert L.ebic_last_error()
+    assert L.ebic_session_step(None, 1, None) == ebic.EBIC_ERR_INVALID_ARG
+    n = ctypes.c_size_t(0)
+    assert L.ebic_session_checkpoint(None, None, ctypes.byref(n)) == ebic.EBIC_ERR_INVALID_ARG
+    res = ctypes.POINTER(ebic.ebic_result)()
+    assert L.ebic_session_result(None, ctypes.byref(res)) == ebic.EBIC_ERR_INVALID_ARG
+    L.ebic_session_free(None)

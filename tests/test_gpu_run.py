@@ -44,7 +44,31 @@ def _lockstep(E, X, kw, seed):
         np.testing.assert_array_equal(a.cols, b.cols)
         np.testing.assert_array_equal(a.rows, b.rows)
         assert a.score == b.score and a.n == b.n
+        _check_directions(X, kw, a)
     return got
+
+
+def _check_directions(X, kw, b):
+    """A row's direction is 0 exactly when it fits the series' increasing
+    trend: the oracle's support of the series with reversed trends off."""
+    inc = oracle.evaluate(X, [list(b.cols)],
+                          params=oracle.make_params(**{**kw, "negative_trends": 0}),
+                          nthreads=NCPU).support[0]
+    np.testing.assert_array_equal(b.row_dir, np.where(inc[b.rows], 0, 1).astype(np.uint8))
+    if not kw["negative_trends"]:
+        assert not b.row_dir.any()
+
+
+def _same_result(a, b):
+    assert (a.generations, a.evaluations, a.tabu_hits, a.stop_reason) == \
+        (b.generations, b.evaluations, b.tabu_hits, b.stop_reason)
+    np.testing.assert_array_equal(a.trace, b.trace)
+    assert len(a.biclusters) == len(b.biclusters)
+    for x, y in zip(a.biclusters, b.biclusters):
+        np.testing.assert_array_equal(x.rows, y.rows)
+        np.testing.assert_array_equal(x.cols, y.cols)
+        np.testing.assert_array_equal(x.row_dir, y.row_dir)
+        assert x.score == y.score
 
 
 def test_tiny_workload_lockstep(E):
@@ -98,3 +122,73 @@ def test_deterministic(E):
     for x, y in zip(a.biclusters, b.biclusters):
         np.testing.assert_array_equal(x.rows, y.rows)
         np.testing.assert_array_equal(x.cols, y.cols)
+
+
+def _plain_kw(generations=30):
+    w = synth.workload(1)
+    return _params(negative_trends=1, k_min=w.k_min, k_max=w.k_max, population=w.population,
+                   generations=generations, n_out=w.n_out)
+
+
+def test_allocator_hook(E):
+    """All device memory of a run from torch's caching allocator: the same
+    result, every allocation returned."""
+    case = synth.workload_matrix(1)
+    kw = _plain_kw(12)
+    ref = E.ebic_run(case.X, E.make_params(**kw), 5)
+    al = E.TorchAllocator()
+    got = E.ebic_run(case.X, E.make_params(**kw), 5, alloc=al)
+    _same_result(got, ref)
+    assert al.allocs > 10 and al.allocs == al.releases and not al.live
+
+
+def test_checkpoint_resume_equivalence(E):
+    """A run checkpointed after 7 steps and restored in a new session ends
+    exactly as the same run uninterrupted; steps of any size give the same
+    run; a checkpoint of the restored session is byte-identical."""
+    case = synth.workload_matrix(1)
+    kw = _plain_kw(30)
+    ref = E.ebic_run(case.X, E.make_params(**kw), 9)
+    s = E.Session.create(case.X, E.make_params(**kw), 9)
+    assert not s.step(7)
+    blob = s.checkpoint()
+    assert not s.step(3)
+    blob10 = s.checkpoint()
+    s.close()
+    r = E.Session.restore(case.X, blob)
+    assert r.checkpoint() == blob
+    assert not r.step(3)
+    assert r.checkpoint() == blob10
+    while not r.step(4):
+        pass
+    _same_result(r.result(), ref)
+    r.close()
+    # one step at a time, with a torch allocator
+    al = E.TorchAllocator()
+    s1 = E.Session.create(case.X, E.make_params(**kw), 9, alloc=al)
+    while not s1.step(1):
+        pass
+    _same_result(s1.result(), ref)
+    with pytest.raises(Exception):
+        s1.result()  # taken once
+    s1.close()
+    assert al.allocs == al.releases and not al.live
+
+
+def test_checkpoint_of_another_matrix_rejected(E):
+    case = synth.workload_matrix(0)
+    s = E.Session.create(case.X, E.make_params(**_params(generations=5)), 3)
+    s.step(2)
+    blob = s.checkpoint()
+    while not s.step(10):
+        pass
+    with pytest.raises(Exception):
+        s.checkpoint()  # finished
+    s.close()
+    other = case.X.copy()
+    other[0, 0] += 1.0
+    with pytest.raises(Exception):
+        E.Session.restore(other, blob)
+    with pytest.raises(Exception):
+        E.Session.restore(case.X, blob[:-1])
+    E.Session.restore(case.X, blob).close()
