@@ -323,11 +323,19 @@ def cpu_baseline(X, seqs):
         if time.perf_counter() - t0 > 4.0 or reps >= 20:
             break
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, over the first 128 individuals
+    one = sample[:128]
+    t1 = time.perf_counter()
+    oracle.evaluate(X, one, params=p, nthreads=1)
+    d1 = time.perf_counter() - t1
     return {"value": reps * len(sample) / dt, "unit": "individual evaluations/s",
             "cores": threads, "kind": "oracle",
             "sample": f"one population of {len(sample)} individuals of the same workload, "
                       f"{reps} passes, empty archive, {threads} OpenMP threads, "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall",
+            "single_thread": {"value": len(one) / d1, "cores": 1,
+                              "sample": f"the population's first {len(one)} individuals, "
+                                        f"one pass, {d1:.1f} s"}}
 
 
 if __name__ == "__main__":
