@@ -82,12 +82,28 @@ typedef struct ebic_params {
     int32_t max_tabu_hits;     /* rejected mutants that end the run (ebic_run)         */
     int32_t tournament;        /* tournament size (ebic_run)                           */
     int32_t max_attempts;      /* mutation attempts per population slot (ebic_run)     */
+    int32_t tie_rule;          /* equal values in a row (EBIC_TIE_*)                    */
 } ebic_params;
+
+/* Equal values in a row (the paper does not say how ties count; a step of a
+ * series goes from column a to column b):
+ * EBIC_TIE_INDEX    the smaller column index comes first: a tie is an up-step
+ *                   when a < b, a down-step otherwise (every step is one or
+ *                   the other);
+ * EBIC_TIE_STRICT   a tie is neither: it breaks the increasing and the
+ *                   decreasing trend alike;
+ * EBIC_TIE_LOOSE    a tie is both: it fits either trend.
+ * The pair table serves EBIC_TIE_INDEX; the batched evaluator scores the
+ * other rules in the gather form. */
+#define EBIC_TIE_INDEX 0
+#define EBIC_TIE_STRICT 1
+#define EBIC_TIE_LOOSE 2
 
 /* A prepared matrix (ebic_matrix_prepare). */
 typedef struct ebic_matrix {
-    const uint16_t *d_ranks;   /* cols x rows_pad, column-major: the position of
-                                  each cell in its row's order (0..cols-1)        */
+    const uint16_t *d_ranks;   /* cols x rows_pad, column-major: for each cell the
+                                  number of cells of its row with a smaller value
+                                  (equal values share it), 0..cols-1              */
     int32_t rows, cols, rows_pad;
     const uint64_t *d_pairs;   /* optional pair table (ebic_pairs_prepare) or NULL */
 } ebic_matrix;

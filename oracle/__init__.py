@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "approx_permille", "negative_trends", "overlap_permille", "min_rows", "k_score_min",
         "k_min", "k_max", "archive_size", "n_out", "population", "generations",
-        "max_tabu_hits", "tournament", "max_attempts")]
+        "max_tabu_hits", "tournament", "max_attempts", "tie_rule")]
 
 
 class _Result(ctypes.Structure):
@@ -60,7 +60,8 @@ class _Result(ctypes.Structure):
 
 DEFAULTS = dict(approx_permille=850, negative_trends=0, overlap_permille=750, min_rows=5,
                 k_score_min=2, k_min=2, k_max=8, archive_size=20, n_out=1, population=200,
-                generations=50, max_tabu_hits=100000, tournament=4, max_attempts=1000)
+                generations=50, max_tabu_hits=100000, tournament=4, max_attempts=1000,
+                tie_rule=0)
 
 
 def make_params(**kw) -> Params:

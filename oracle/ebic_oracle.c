@@ -49,20 +49,40 @@ typedef struct oracle_params {
     int32_t max_tabu_hits;     /* stop once this many mutants were rejected   */
     int32_t tournament;        /* T: tournament size                          */
     int32_t max_attempts;      /* attempts per population slot                */
+    int32_t tie_rule;          /* equal values: 0 by column index, 1 strict,  */
+                               /* 2 loose (see step_counts)                   */
 } oracle_params;
 
 /* ------------------------------------------------------------------------ */
 /* Part 1: evaluation of one individual.                                    */
 /* ------------------------------------------------------------------------ */
 
-/* Row order (reading of ties): column a precedes column b in row r when its
- * value is smaller, or when the values compare equal and a < b. IEEE compare,
- * so -0 == +0. This is a strict total order on the columns of a row. */
-static int precedes(const float *X, int C, int r, int a, int b)
+/* Row order (reading of ties, the paper does not say how equal values
+ * count), for a step from column a to column b of row r; IEEE compares, so
+ * -0 == +0. Adds to *v_inc when the step goes against the increasing trend
+ * and to *v_dec when it goes against the decreasing one.
+ *   rule 0: a precedes b when its value is smaller, or equal and a < b (a
+ *           strict total order): every step goes against exactly one trend;
+ *   rule 1 (strict): a tie goes against both trends;
+ *   rule 2 (loose): a tie goes against neither. */
+static void step_counts(const float *X, int C, int r, int a, int b, int rule,
+                        int *v_inc, int *v_dec)
 {
     float xa = X[(size_t)r * C + a];
     float xb = X[(size_t)r * C + b];
-    return xa < xb || (xa == xb && a < b);
+    if (xa < xb) {
+        *v_dec += 1;
+    } else if (xa > xb) {
+        *v_inc += 1;
+    } else if (rule == 0) {
+        if (a < b)
+            *v_dec += 1;
+        else
+            *v_inc += 1;
+    } else if (rule == 1) {
+        *v_inc += 1;
+        *v_dec += 1;
+    }
 }
 
 /* Tolerance (reading of the approximate-trend threshold, Sec. 2.4): the
@@ -77,13 +97,11 @@ static int tolerance(int k, int approx_permille)
  * against the increasing order; with negative trends on, a row that follows
  * the reversed order counts too (each row once). */
 static int row_fits(const float *X, int C, int r, const uint16_t *s, int k,
-                    int t, int neg)
+                    int t, int neg, int rule)
 {
-    int up = 0;
+    int v_inc = 0, v_dec = 0;  /* steps against each trend */
     for (int j = 0; j + 1 < k; j++)
-        up += precedes(X, C, r, s[j], s[j + 1]);
-    int v_inc = (k - 1) - up;  /* steps against the increasing trend */
-    int v_dec = up;            /* steps against the decreasing trend */
+        step_counts(X, C, r, s[j], s[j + 1], rule, &v_inc, &v_dec);
     return v_inc <= t || (neg && v_dec <= t);
 }
 
@@ -129,7 +147,7 @@ static void eval_individual(const float *X, int R, int C, const uint16_t *s, int
     int t = tolerance(k, p->approx_permille);
     int n = 0;
     for (int r = 0; r < R; r++) {
-        support[r] = (uint8_t)row_fits(X, C, r, s, k, t, p->negative_trends);
+        support[r] = (uint8_t)row_fits(X, C, r, s, k, t, p->negative_trends, p->tie_rule);
         n += support[r];
     }
     int m = 0;

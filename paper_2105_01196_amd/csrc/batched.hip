@@ -46,7 +46,7 @@ struct DevJob {
     const uint64_t *arch_support;
     const int32_t *arch_off;
     const uint16_t *arch_cols;
-    int32_t approx_permille, negative_trends, overlap_permille, min_rows, k_score_min;
+    int32_t approx_permille, negative_trends, overlap_permille, min_rows, k_score_min, tie_rule;
     double *fitness;
     int32_t *count;
     uint64_t *support;
@@ -366,8 +366,10 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     const int k = end - beg;
     const bool bad0 = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
     const int t = bad0 ? 0 : tol(k, J.approx_permille);
-    // pair table when the batch has one and the counters fit; else gather
-    const bool use_pairs = J.mode == 1 && t <= PairLimit<KB, WPL>::T;
+    // pair table when the batch has one, it serves the tie rule and the
+    // counters fit; else gather
+    const bool use_pairs =
+        J.mode == 1 && J.tie_rule == EBIC_TIE_INDEX && t <= PairLimit<KB, WPL>::T;
 
     // 1. stage and validate the series
     if (threadIdx.x == 0) {
@@ -458,7 +460,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                         for (int b = 0; b < 64 && b0 + b < J.w64; b++) {
                             const int r = (b0 + b) * kWave + lane;
                             const uint64_t word =
-                                block_support(rs, s_pd, k, t, neg, r * 2, r < J.rows);
+                                block_support(rs, s_pd, k, t, neg, J.tie_rule, r * 2, r < J.rows);
                             lo = writelane((int)(uint32_t)word, b, lo);
                             hi = writelane((int)(uint32_t)(word >> 32), b, hi);
                         }
@@ -695,6 +697,7 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
     d.overlap_permille = j.params.overlap_permille;
     d.min_rows = j.params.min_rows;
     d.k_score_min = j.params.k_score_min;
+    d.tie_rule = j.params.tie_rule;
     d.fitness = j.out.d_fitness;
     d.count = j.out.d_count;
     d.support = j.out.d_support;

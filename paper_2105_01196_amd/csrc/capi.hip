@@ -40,6 +40,8 @@ int check_eval_params(const ebic_params *p) {
         return fail(EBIC_ERR_INVALID_ARG, "negative_trends must be 0 or 1");
     if (p->min_rows < 0 || p->k_score_min < 0)
         return fail(EBIC_ERR_INVALID_ARG, "min_rows and k_score_min must be >= 0");
+    if (p->tie_rule < EBIC_TIE_INDEX || p->tie_rule > EBIC_TIE_LOOSE)
+        return fail(EBIC_ERR_INVALID_ARG, "tie_rule %d is not an EBIC_TIE_* value", p->tie_rule);
     return EBIC_OK;
 }
 
@@ -182,6 +184,7 @@ int ebic_evaluate(const ebic_matrix *m, const ebic_population *pop, const ebic_a
     j.overlap_permille = p->overlap_permille;
     j.min_rows = p->min_rows;
     j.k_score_min = p->k_score_min;
+    j.tie_rule = p->tie_rule;
     j.fitness = out->d_fitness;
     j.count = out->d_count;
     j.support = out->d_support;
@@ -199,7 +202,7 @@ int ebic_pairs_prepare(ebic_matrix *m, uint64_t *d_pairs, void *stream) {
     int rc = check_matrix(m);
     if (rc) return rc;
     if (!d_pairs) return fail(EBIC_ERR_INVALID_ARG, "pair table is NULL");
-    rc = launch_build_pairs(m->d_ranks, m->cols, m->rows_pad, d_pairs,
+    rc = launch_build_pairs(m->d_ranks, m->rows, m->cols, m->rows_pad, d_pairs,
                             static_cast<hipStream_t>(stream));
     if (rc) return rc;
     m->d_pairs = d_pairs;

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "ebic.h"
+
 namespace ebic {
 
 __device__ inline int tol(int k, int approx) {
@@ -36,34 +38,64 @@ __device__ inline int load_rank(__amdgpu_buffer_rsrc_t rs, int lane_off, int col
     return __builtin_amdgcn_raw_buffer_load_b16(rs, lane_off, col_off, 0);
 }
 
-// Gather form of the trend test for one 64-row block: lane = row, s_off
-// holds each series column's byte offset in the column-major rank matrix,
-// lane_off this lane's row offset. Returns the block's support word. Exits
-// early once every row of the block has broken both trends beyond the
-// tolerance t.
-__device__ inline uint64_t block_support(__amdgpu_buffer_rsrc_t rs, const int32_t *s_off, int k,
-                                         int t, int neg, int lane_off, bool valid_row) {
-    int prev = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[0]));
-    int up = 0;
+// Support word of 64 rows (lane = row) for a series whose columns' byte
+// offsets into the rank matrix sit in s_off[0..k). A step a -> b fits the
+// increasing trend when rank[a] < rank[b] + fu and the decreasing one when
+// rank[b] < rank[a] + fd, with, by tie rule: column index fu = [a < b],
+// fd = [a > b] (then exactly one of the two holds); strict fu = fd = 0;
+// loose fu = fd = 1 (offsets are in column order, so a < b is off_a < off_b).
+// A row fits when at most t steps break the increasing trend, or (neg) at
+// most t break the decreasing one. The wave stops once every row is out.
+template <int RULE>
+__device__ inline uint64_t block_support_rule(__amdgpu_buffer_rsrc_t rs, const int32_t *s_off,
+                                              int k, int t, int neg, int lane_off,
+                                              bool valid_row) {
+    int off_prev = __builtin_amdgcn_readfirstlane(s_off[0]);
+    int prev = load_rank(rs, lane_off, off_prev);
+    int inc_bad = 0, dec_bad = 0;  // steps against each trend
+    auto step = [&](int off, int cur) {
+        const int fu = RULE == EBIC_TIE_INDEX ? (off_prev < off) : (RULE == EBIC_TIE_LOOSE);
+        const int fd = RULE == EBIC_TIE_INDEX ? (off_prev > off) : (RULE == EBIC_TIE_LOOSE);
+        inc_bad += !(prev < cur + fu);
+        if (RULE != EBIC_TIE_INDEX) dec_bad += !(cur < prev + fd);
+        prev = cur;
+        off_prev = off;
+    };
     int j = 1;
     for (; j + 3 < k; j += 4) {
-        const int a = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j]));
-        const int b = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j + 1]));
-        const int c = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j + 2]));
-        const int d = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j + 3]));
-        up += (prev < a) + (a < b) + (b < c) + (c < d);
-        prev = d;
+        int off[4], r[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            off[q] = __builtin_amdgcn_readfirstlane(s_off[j + q]);
+            r[q] = load_rank(rs, lane_off, off[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) step(off[q], r[q]);
         const int done = j + 3;  // steps examined so far
-        const bool dead = !valid_row || ((done - up > t) && (!neg || up > t));
+        // with the column-index rule every step breaks exactly one trend
+        const int dbad = RULE == EBIC_TIE_INDEX ? done - inc_bad : dec_bad;
+        const bool dead = !valid_row || (inc_bad > t && (!neg || dbad > t));
         if (__ballot(!dead) == 0) return 0;
     }
     for (; j < k; j++) {
-        const int cur = load_rank(rs, lane_off, __builtin_amdgcn_readfirstlane(s_off[j]));
-        up += prev < cur;
-        prev = cur;
+        const int off = __builtin_amdgcn_readfirstlane(s_off[j]);
+        step(off, load_rank(rs, lane_off, off));
     }
-    const bool fit = valid_row && (((k - 1 - up) <= t) || (neg && up <= t));
+    const int dbad = RULE == EBIC_TIE_INDEX ? (k - 1) - inc_bad : dec_bad;
+    const bool fit = valid_row && (inc_bad <= t || (neg && dbad <= t));
     return __ballot(fit);
+}
+
+__device__ inline uint64_t block_support(__amdgpu_buffer_rsrc_t rs, const int32_t *s_off, int k,
+                                         int t, int neg, int rule, int lane_off, bool valid_row) {
+    switch (rule) {
+        case EBIC_TIE_STRICT:
+            return block_support_rule<EBIC_TIE_STRICT>(rs, s_off, k, t, neg, lane_off, valid_row);
+        case EBIC_TIE_LOOSE:
+            return block_support_rule<EBIC_TIE_LOOSE>(rs, s_off, k, t, neg, lane_off, valid_row);
+        default:
+            return block_support_rule<EBIC_TIE_INDEX>(rs, s_off, k, t, neg, lane_off, valid_row);
+    }
 }
 
 // v_writelane_b32: returns `old` with lane `lane` set to the wave-uniform

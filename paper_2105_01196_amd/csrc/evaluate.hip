@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(kEvalThreads) evaluate_plain_kernel(EvalJob a)
     int32_t hacc = 0;  // lane j < K: rows shared with member j
     for (int w = wave; w < a.words; w += kEvalWaves) {
         const int r = w * kWave + lane;
-        const uint64_t word = block_support(rs, s_off, k, t, neg, r * 2, r < a.rows);
+        const uint64_t word = block_support(rs, s_off, k, t, neg, a.tie_rule, r * 2, r < a.rows);
         if (a.support && lane == 0) a.support[(size_t)i * a.words + w] = word;
         cnt += __popcll(word);
         if (lane < K) hacc += __popcll(word & a.arch_support[(size_t)lane * a.words + w]);

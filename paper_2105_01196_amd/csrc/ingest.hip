@@ -1,9 +1,10 @@
 // Matrix ingest: finiteness check and per-row ranks.
 //
-// The trend test only ever asks whether column a precedes column b in a row
-// (value order, ties broken by the smaller column index). Replacing every
-// row by the rank of each of its cells in that order keeps every such answer
-// and turns the test into one 16-bit integer compare. The ranks are stored
+// The trend test only ever compares two cells of a row: smaller, equal or
+// larger. Replacing every cell by the number of cells of its row with a
+// smaller value (equal values share it) keeps every such answer and turns
+// the test into one 16-bit integer compare; how a tie counts (by column
+// index, against both trends or for both) is the evaluator's choice. The ranks are stored
 // column-major (cols x rows_pad), so a wavefront reading one column for 64
 // consecutive rows touches 128 contiguous bytes. The paper keeps the matrix
 // resident on the GPU and only ships populations per generation (Sec. 2.4,
@@ -24,10 +25,8 @@ __global__ void __launch_bounds__(256) check_finite_kernel(const float *__restri
 }
 
 // One workgroup per row: stage the row in LDS, then each thread ranks its
-// columns by counting the cells that precede them. For column c the cells
-// before it in index order precede it when <= (ties go to the smaller index),
-// the cells after it when < . Padding rows (r >= rows) get rank 0; the
-// evaluators mask them out.
+// columns by counting the cells with a smaller value. Padding rows
+// (r >= rows) get rank 0; the evaluators mask them out.
 __global__ void __launch_bounds__(256) rank_rows_kernel(const float *__restrict__ x, int32_t rows,
                                                         int32_t cols, int32_t rows_pad,
                                                         uint16_t *__restrict__ ranks) {
@@ -44,8 +43,7 @@ __global__ void __launch_bounds__(256) rank_rows_kernel(const float *__restrict_
     for (int32_t c = threadIdx.x; c < cols; c += blockDim.x) {
         const float v = s_row[c];
         int32_t rank = 0;
-        for (int32_t d = 0; d < c; d++) rank += s_row[d] <= v;
-        for (int32_t d = c + 1; d < cols; d++) rank += s_row[d] < v;
+        for (int32_t d = 0; d < cols; d++) rank += s_row[d] < v;
         ranks[(size_t)c * rows_pad + r] = (uint16_t)rank;
     }
 }

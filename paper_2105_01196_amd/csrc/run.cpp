@@ -428,11 +428,14 @@ std::vector<uint8_t> Job::row_directions(const std::vector<int32_t> &rows, const
     const int t = (int)(((int64_t)(k - 1) * (1000 - p_.approx_permille)) / 1000);
     for (size_t i = 0; i < rows.size(); i++) {
         const float *x = hx_ + (size_t)rows[i] * C_;
-        int downs = 0;
+        int downs = 0;  // steps against the increasing trend
         for (int j = 0; j + 1 < k; j++) {
             const int a = s[j], b = s[j + 1];
-            // a precedes b in this row: smaller value, ties by column index
-            const bool up = x[a] < x[b] || (x[a] == x[b] && a < b);
+            // the step fits the increasing trend: a smaller value, or a tie
+            // that the tie rule lets through
+            const bool tie_ok = p_.tie_rule == EBIC_TIE_LOOSE ||
+                                (p_.tie_rule == EBIC_TIE_INDEX && a < b);
+            const bool up = x[a] < x[b] || (x[a] == x[b] && tie_ok);
             downs += !up;
         }
         dir[i] = downs <= t ? 0 : 1;

@@ -43,7 +43,7 @@ class ebic_params(ctypes.Structure):
     _fields_ = [(n, _i32) for n in (
         "approx_permille", "negative_trends", "overlap_permille", "min_rows", "k_score_min",
         "k_min", "k_max", "archive_size", "n_out", "population", "generations",
-        "max_tabu_hits", "tournament", "max_attempts")]
+        "max_tabu_hits", "tournament", "max_attempts", "tie_rule")]
 
 
 class ebic_matrix(ctypes.Structure):
@@ -108,6 +108,9 @@ class ebic_server_metrics(ctypes.Structure):
 EBIC_STOP_GENERATIONS = 1
 EBIC_STOP_TABU = 2
 EBIC_STOP_EXHAUSTED = 3
+EBIC_TIE_INDEX = 0
+EBIC_TIE_STRICT = 1
+EBIC_TIE_LOOSE = 2
 EBIC_BATCH_GRAPH = 1
 EBIC_BATCH_GATHER = 2
 EBIC_BATCH_TUNE = 4
@@ -209,7 +212,7 @@ def _to_device_bytes(a: np.ndarray, device) -> torch.Tensor:
 DEFAULT_PARAMS = dict(approx_permille=850, negative_trends=0, overlap_permille=750,
                       min_rows=5, k_score_min=2, k_min=2, k_max=8, archive_size=20, n_out=1,
                       population=200, generations=50, max_tabu_hits=100000, tournament=4,
-                      max_attempts=1000)
+                      max_attempts=1000, tie_rule=0)
 
 
 def make_params(**kw) -> ebic_params:

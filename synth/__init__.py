@@ -73,12 +73,37 @@ def _background(rng: np.random.Generator, kind: str, shape) -> np.ndarray:
     raise ValueError(kind)
 
 
+PATTERNS = ("trend", "shift", "scale", "shift-scale", "constant-row")
+
+
+def _pattern_rows(rng: np.random.Generator, pattern: str, nb: int, kb: int) -> np.ndarray:
+    """nb x kb values whose every row increases along the columns (in the
+    planted order) for the shift, scale and shift-scale patterns: column
+    effects b_j drawn and sorted ascending, row effects a_i (positive for
+    scale) and c_i drawn per row: shift a_i + b_j, scale a_i * b_j,
+    shift-scale a_i * b_j + c_i. constant-row repeats one value per row (every
+    step a tie)."""
+    b = np.sort(rng.uniform(0.5, 2.0, kb))
+    if pattern == "shift":
+        return rng.normal(0.0, 1.0, (nb, 1)) + b
+    if pattern == "scale":
+        return rng.uniform(0.5, 2.0, (nb, 1)) * b
+    if pattern == "shift-scale":
+        return rng.uniform(0.5, 2.0, (nb, 1)) * b + rng.normal(0.0, 1.0, (nb, 1))
+    if pattern == "constant-row":
+        return np.repeat(rng.normal(0.0, 1.0, (nb, 1)), kb, axis=1)
+    raise ValueError(f"unknown pattern {pattern!r}; one of {PATTERNS}")
+
+
 def planted_matrix(R: int, C: int, *, background: str, n_planted: int,
                    rows_range: Sequence[int], cols_range: Sequence[int],
                    sigma: float, reverse_odd: bool = False, strict: bool = False,
-                   seed: int, name: str = "") -> MatrixCase:
+                   seed: int, name: str = "", pattern: str = "trend") -> MatrixCase:
     """Background matrix with ``n_planted`` disjoint-row trend biclusters.
 
+    ``pattern`` "trend": each planted row is its own sorted background draw;
+    otherwise the bicluster's rows follow one of the paper's benchmark types
+    (shift, scale, shift-scale, constant-row; see _pattern_rows).
     ``strict`` redraws a planted row until its values are pairwise distinct
     after the float32 cast (a strictly monotone planted trend with no ties).
     """
@@ -96,6 +121,15 @@ def planted_matrix(R: int, C: int, *, background: str, n_planted: int,
         available[rows] = False
         cols = rng.choice(C, size=kb, replace=False)
         rev = bool(reverse_odd and (b % 2 == 1))
+        if pattern != "trend":
+            v = _pattern_rows(rng, pattern, nb, kb)
+            if rev:
+                v = v[:, ::-1]
+            if sigma > 0:
+                v = v + rng.normal(0.0, sigma, v.shape)
+            X[np.ix_(rows, cols)] = v
+            truth.append(Planted(rows=rows, cols=cols.astype(np.int64), reversed=rev))
+            continue
         for r in rows:
             while True:
                 v = np.sort(_background(rng, background, kb))

@@ -202,6 +202,44 @@ def test_set_tuning_rejects_other_shapes(E):
     b.close()
 
 
+@pytest.mark.parametrize("rule", [0, 1, 2])
+def test_tie_rules(E, rule):
+    """Tie-heavy rows and constant-row biclusters under each tie rule: the
+    column-index rule on the pair table, the others in the gather form (the
+    matrix has a table either way), both forms of the batch equal."""
+    X = synth.tie_matrix(777, 64, levels=3, seed=31)
+    case = synth.planted_matrix(500, 40, background="normal", n_planted=3,
+                                rows_range=(40, 60), cols_range=(4, 12), sigma=0.0,
+                                seed=32, pattern="constant-row")
+    rng = np.random.default_rng(33 + rule)
+    for M in (X, case.X):
+        C = M.shape[1]
+        seqs = [list(rng.permutation(C)[:int(k)]) for k in rng.integers(2, min(C, 64) + 1, 150)]
+        seqs += [list(t.cols) for t in getattr(case, "truth", [])] if M is case.X else []
+        for neg in (0, 1):
+            for approx in (1000, 850, 500):
+                kw = _kw(approx_permille=approx, negative_trends=neg, min_rows=1,
+                         tie_rule=rule)
+                _run(E, M, seqs, kw)
+                _run(E, M, seqs, kw, gather=True)
+
+
+def test_pattern_biclusters(E):
+    """The paper's benchmark types planted (shift, scale, shift-scale): their
+    series keep every planted row, in both forms."""
+    for pattern in ("shift", "scale", "shift-scale"):
+        case = synth.planted_matrix(2000, 60, background="lognormal", n_planted=4,
+                                    rows_range=(50, 200), cols_range=(5, 20), sigma=0.0,
+                                    reverse_odd=True, seed=34, pattern=pattern)
+        seqs = [list(t.cols) for t in case.truth]
+        kw = _kw(approx_permille=1000, negative_trends=1, min_rows=1)
+        job = _run(E, case.X, seqs, kw)
+        flags = E.support_to_flags(job.out.support.cpu().numpy().view(np.uint64)[:len(seqs)],
+                                   case.R)
+        for i, t in enumerate(case.truth):
+            assert flags[i][t.rows].all(), pattern
+
+
 def test_multi_job_batch(E):
     """Jobs on different matrices and parameters in one launch, each equal to
     its own oracle evaluation; one job in gather form (no table)."""

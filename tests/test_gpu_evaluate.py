@@ -85,6 +85,15 @@ def test_brute_force_tiny(E, kind, approx, neg):
                                               min_rows=1, k_score_min=2))
 
 
+@pytest.mark.parametrize("rule", [1, 2])
+@pytest.mark.parametrize("approx,neg", [(1000, 0), (1000, 1), (700, 0), (0, 1)])
+def test_brute_force_tie_rules(E, rule, approx, neg):
+    """Strict (a tie against both trends) and loose (against neither)."""
+    X = synth.tie_matrix(8, 6, levels=3, seed=12)
+    _check(E, X, _all_series(6, 6), _params(approx_permille=approx, negative_trends=neg,
+                                              min_rows=1, k_score_min=2, tie_rule=rule))
+
+
 def test_tiny_workload(E):
     case = synth.workload_matrix(0)
     seqs = synth.workload_population(0, case)

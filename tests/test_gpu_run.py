@@ -192,3 +192,16 @@ def test_checkpoint_of_another_matrix_rejected(E):
     with pytest.raises(Exception):
         E.Session.restore(case.X, blob[:-1])
     E.Session.restore(case.X, blob).close()
+
+
+@pytest.mark.parametrize("rule", [1, 2])
+def test_tie_rule_lockstep(E, rule):
+    """The loop under the strict and loose tie rules on constant-row
+    biclusters (every planted step a tie): the library follows the oracle."""
+    case = synth.planted_matrix(200, 16, background="normal", n_planted=2,
+                                rows_range=(20, 30), cols_range=(4, 6), sigma=0.0, seed=35,
+                                pattern="constant-row")
+    got = _lockstep(E, case.X, _params(negative_trends=1, tie_rule=rule, generations=30,
+                                       n_out=3), 12)
+    if rule == 2 and got.biclusters:
+        assert got.biclusters[0].n >= 20  # a constant-row bicluster fits the loose rule

@@ -153,6 +153,61 @@ def test_invariants():
         prev = c
 
 
+def _sequences(levels, k):
+    """Every sequence over 0..levels-1 of length k, one per row."""
+    return np.array(list(itertools.product(range(levels), repeat=k)), dtype=np.float32)
+
+
+def test_tie_rules_closed_forms():
+    """Rows = all 3^k sequences over {0, 1, 2}, exact trends (t = 0): the
+    fitting rows are the strictly increasing sequences, C(3, k) of them, or
+    the non-decreasing ones, C(k+2, k) by stars and bars, as each tie rule
+    says; along the reversed series the column-index rule turns strict."""
+    from math import comb
+    for k in range(2, 6):
+        X = _sequences(3, k)
+        ident, rev = list(range(k)), list(range(k))[::-1]
+        inc, nondec = comb(3, k), comb(k + 2, k)
+        cases = [(1, ident, 0, inc), (2, ident, 0, nondec), (0, ident, 0, nondec),
+                 (1, rev, 0, inc), (2, rev, 0, nondec), (0, rev, 0, inc),
+                 # with reversed trends: both directions, the 3 constant rows
+                 # counted once under the loose rule
+                 (1, ident, 1, 2 * inc), (2, ident, 1, 2 * nondec - 3),
+                 (0, ident, 1, nondec + inc)]
+        for rule, series, neg, want in cases:
+            p = oracle.make_params(approx_permille=1000, negative_trends=neg, min_rows=1,
+                                   k_score_min=2, tie_rule=rule)
+            assert oracle.evaluate(X, [series], params=p).count[0] == want, (k, rule, series, neg)
+
+
+def test_tie_rules_agree_without_ties():
+    rng = np.random.default_rng(21)
+    X = synth.random_matrix(60, 10, seed=22)
+    seqs = [list(rng.permutation(10)[:int(rng.integers(2, 11))]) for _ in range(80)]
+    for neg in (0, 1):
+        for approx in (1000, 800, 500):
+            sup = [oracle.evaluate(X, seqs, params=oracle.make_params(
+                approx_permille=approx, negative_trends=neg, min_rows=1, k_score_min=2,
+                tie_rule=rule)).support for rule in (0, 1, 2)]
+            np.testing.assert_array_equal(sup[0], sup[1])
+            np.testing.assert_array_equal(sup[0], sup[2])
+
+
+def test_tie_rules_nest():
+    """A tie counts against both trends (strict), one (column index) or none
+    (loose), so the supports nest: strict within index within loose."""
+    rng = np.random.default_rng(23)
+    X = synth.tie_matrix(80, 10, levels=3, seed=24)
+    seqs = [list(rng.permutation(10)[:int(rng.integers(2, 11))]) for _ in range(80)]
+    for neg in (0, 1):
+        for approx in (1000, 800, 500):
+            s0, s1, s2 = [oracle.evaluate(X, seqs, params=oracle.make_params(
+                approx_permille=approx, negative_trends=neg, min_rows=1, k_score_min=2,
+                tie_rule=rule)).support for rule in (0, 1, 2)]
+            assert not (s1 & ~s0).any() and not (s0 & ~s2).any()
+            assert (s1 != s2).any()
+
+
 def test_fitness_identities():
     case = synth.workload_matrix(0)
     X = case.X
