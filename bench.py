@@ -47,6 +47,10 @@ def parse():
                     help="instead of the evaluation step, run the job-server mix: JOBS jobs "
                          "with Poisson arrivals, and print its own JSON line")
     ap.add_argument("--serving-gens", type=int, default=30)
+    ap.add_argument("--recovery", type=int, default=0, metavar="WORKLOAD",
+                    help="instead of the evaluation step, run the whole method on a planted "
+                         "workload (1 or 2) with its parameters and print the clustering "
+                         "error of the biclusters found against the planted ones")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of rocprofv3) and exit")
@@ -108,6 +112,9 @@ def main():
         return
     if args.gpus == 1 and args.serving:
         serving(args)
+        return
+    if args.gpus == 1 and args.recovery:
+        recovery(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the evaluation path "
@@ -306,6 +313,39 @@ def serving(args):
         "matrix_generation_s": gen_s,
     }
     print(json.dumps(line), flush=True)
+
+
+def recovery(args):
+    """ebic_run on a planted workload with its own parameters; the
+    clustering error (Sec. 2.2, Eq. 1) of the biclusters found against the
+    planted ones, reported as D_max/|U| (1 = perfect) beside Eq. (1)'s
+    value."""
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_2105_01196_amd import ebic as E
+    wi = args.recovery
+    w = synth.workload(wi)
+    case = synth.workload_matrix(wi)
+    p = E.make_params(approx_permille=850, negative_trends=w.negative_trends,
+                      overlap_permille=750, min_rows=5, k_min=w.k_min, k_max=w.k_max,
+                      archive_size=w.archive_size, n_out=w.n_out, population=w.population,
+                      generations=w.generations, max_tabu_hits=100000, tournament=4,
+                      max_attempts=1000)
+    E.ebic_run(case.X, p, synth.GA_SEED + wi)  # warm-up (first-use costs)
+    t0 = time.perf_counter()
+    res = E.ebic_run(case.X, p, synth.GA_SEED + wi)
+    wall = time.perf_counter() - t0
+    truth = [(t.rows, t.cols) for t in case.truth]
+    score, ce = E.ebic_ce_score(res.biclusters, truth, case.R, case.C)
+    print(json.dumps({
+        "metric": "clustering error of ebic_run vs the planted biclusters (D_max/|U|)",
+        "value": score, "unit": "fraction of the union of cells", "higher_is_better": True,
+        "eq1_value": ce, "n_gpus": 1, "data": "synthetic",
+        "config": {"workload": w.name, "planted": len(truth), "found": len(res.biclusters),
+                   "generations": res.generations, "population": w.population,
+                   "negative_trends": w.negative_trends},
+        "wall_s": wall, "evaluations": res.evaluations,
+        "evaluations_per_s": res.evaluations / wall}), flush=True)
 
 
 def cpu_baseline(X, seqs):

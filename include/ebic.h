@@ -315,6 +315,21 @@ int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
              const ebic_allocator *alloc, void *stream, ebic_result **out);
 void ebic_result_free(ebic_result *r);
 
+/* Clustering error (Sec. 2.2, Eq. 1) of detected biclusters against a
+ * ground truth on a rows x cols matrix, for scoring recovery: the confusion
+ * matrix counts the cells each detected bicluster shares with each true one
+ * (rows x columns, so |rows ∩ rows'| * |cols ∩ cols'|), D_max is the largest
+ * total of a one-to-one assignment between the two sets (Munkres), and U is
+ * the union of the cells of all biclusters of both sets. *score = D_max/|U|
+ * (1 = perfect match, 0 = nothing shared: the paper's text reads CE this
+ * way); *ce = (|U| - D_max)/|U|, Eq. 1 as printed. Both sets empty (or all
+ * biclusters empty): score 1, ce 0. Only n_rows/rows/n_cols/cols of each
+ * bicluster are read (e.g. straight from an ebic_result); order and repeats
+ * do not matter. Host-only, synchronous. Errors: EBIC_ERR_INVALID_ARG (NULL,
+ * negative counts, an index outside the matrix). */
+int ebic_ce_score(const ebic_bicluster *found, int32_t n_found, const ebic_bicluster *truth,
+                  int32_t n_truth, int32_t rows, int32_t cols, double *score, double *ce);
+
 /* A run of the method that advances in steps and can be checkpointed: the
  * same computation as ebic_run, whose result it reproduces bit for bit,
  * however the steps are split and wherever it is checkpointed and restored.

@@ -222,3 +222,32 @@ def splitmix64_stream(seed: int, count: int) -> List[int]:
 def uniform_stream(seed: int, bounds: Sequence[int]) -> List[int]:
     st = ctypes.c_uint64(seed)
     return [int(lib().oracle_uniform(ctypes.byref(st), ctypes.c_uint64(b))) for b in bounds]
+
+
+def ce_score(found, truth):
+    """Clustering error (Sec. 2.2, Eq. 1) of detected biclusters against the
+    truth, each a sequence of (rows, cols): the confusion matrix counts the
+    matrix cells (row, col) two biclusters share, D_max is its largest total
+    over one-to-one assignments of detected to true biclusters (a library
+    assignment solver is the one step taken from elsewhere), U is the set of
+    all cells of all biclusters of both sets. Returns (D_max/|U|,
+    (|U| - D_max)/|U|): the text reads 1 as a perfect match, the printed
+    Eq. (1) is the second value. Both empty: (1.0, 0.0)."""
+    from scipy.optimize import linear_sum_assignment
+
+    def cells(b):
+        rows, cols = b
+        return {(int(r), int(c)) for r in rows for c in cols}
+
+    fc = [cells(b) for b in found]
+    tc = [cells(b) for b in truth]
+    union = set().union(*fc, *tc)
+    if not union:
+        return 1.0, 0.0
+    d_max = 0
+    if fc and tc:
+        m = np.array([[len(a & b) for b in tc] for a in fc], dtype=np.int64)
+        i, j = linear_sum_assignment(m, maximize=True)
+        d_max = int(m[i, j].sum())
+    u = len(union)
+    return d_max / u, (u - d_max) / u

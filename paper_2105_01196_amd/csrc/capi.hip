@@ -307,6 +307,12 @@ int ebic_session_result(ebic_session *s, ebic_result **out) {
 
 void ebic_session_free(ebic_session *s) { session_free(reinterpret_cast<Session *>(s)); }
 
+int ebic_ce_score(const ebic_bicluster *found, int32_t n_found, const ebic_bicluster *truth,
+                  int32_t n_truth, int32_t rows, int32_t cols, double *score, double *ce) {
+    clear_error();
+    return ce_score(found, n_found, truth, n_truth, rows, cols, score, ce);
+}
+
 void ebic_result_free(ebic_result *r) {
     if (r) free_result(r);
 }

@@ -149,6 +149,10 @@ _SIGNATURES = {
     "ebic_session_result": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.POINTER(ebic_result))]),
     "ebic_session_free": (None, [_vp]),
     "ebic_result_free": (None, [ctypes.POINTER(ebic_result)]),
+    "ebic_ce_score": (ctypes.c_int, [ctypes.POINTER(ebic_bicluster), _i32,
+                                     ctypes.POINTER(ebic_bicluster), _i32, _i32, _i32,
+                                     ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]),
     "ebic_server_create": (ctypes.c_int, [ctypes.POINTER(ebic_server_config),
                                           ctypes.POINTER(_vp)]),
     "ebic_server_submit": (ctypes.c_int, [_vp, _vp, _i32, _i32, ctypes.POINTER(ebic_params),
@@ -586,6 +590,32 @@ def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None,
     _check(lib().ebic_run(x.ctypes.data, R, C, ctypes.byref(params), ctypes.c_uint64(seed),
                           _alloc_ref(alloc), _stream(stream), ctypes.byref(res)))
     return _take_result(res)
+
+
+def _bicluster_views(bics):
+    """ctypes views of (rows, cols) pairs; the arrays are kept alive in keep."""
+    keep, views = [], (ebic_bicluster * max(len(bics), 1))()
+    for i, (rows, cols) in enumerate(bics):
+        r = np.ascontiguousarray(rows, dtype=np.int32)
+        c = np.ascontiguousarray(cols, dtype=np.uint16)
+        keep += [r, c]
+        views[i] = ebic_bicluster(int(r.size), r.ctypes.data_as(ctypes.POINTER(_i32)),
+                                  int(c.size), c.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                  0.0, None)
+    return views, keep
+
+
+def ebic_ce_score(found, truth, rows: int, cols: int):
+    """(score D_max/|U|, Eq. 1 value (|U| - D_max)/|U|) of detected biclusters
+    against the truth; each a sequence of (rows, cols) or Bicluster."""
+    def pairs(bs):
+        return [(b.rows, b.cols) if isinstance(b, Bicluster) else (b[0], b[1]) for b in bs]
+    fv, k1 = _bicluster_views(pairs(found))
+    tv, k2 = _bicluster_views(pairs(truth))
+    score, ce = ctypes.c_double(), ctypes.c_double()
+    _check(lib().ebic_ce_score(fv, len(found), tv, len(truth), rows, cols,
+                               ctypes.byref(score), ctypes.byref(ce)))
+    return score.value, ce.value
 
 
 class Session:

@@ -85,6 +85,11 @@ def test_strong_plant_recovered(E):
     top = got.biclusters[0]
     np.testing.assert_array_equal(top.cols, t.cols)
     assert set(t.rows.tolist()) <= set(top.rows.tolist())
+    # clustering error of the top bicluster against the plant: library and
+    # oracle agree; every planted cell is found, so D_max/|U| = 30 / n
+    score, ce = E.ebic_ce_score([top], [(t.rows, t.cols)], case.R, case.C)
+    assert (score, ce) == oracle.ce_score([(top.rows, top.cols)], [(t.rows, t.cols)])
+    assert score == 30 / top.n and score >= 0.5
 
 
 def test_plain_workload_lockstep(E):

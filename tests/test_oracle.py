@@ -342,3 +342,42 @@ def test_run_stops_on_tabu_hits():
     assert res.generations < 1000
     if res.stop_reason == 2:
         assert res.tabu_hits == 30
+
+
+def _random_bics(rng, n, R, C):
+    return [(rng.choice(R, int(rng.integers(1, 9)), replace=False),
+             rng.choice(C, int(rng.integers(1, 6)), replace=False)) for _ in range(n)]
+
+
+def test_ce_score_special_cases():
+    a = [([0, 1, 2], [0, 1]), ([5, 6], [2, 3, 4])]
+    assert oracle.ce_score(a, a) == (1.0, 0.0)
+    assert oracle.ce_score(a, [([8, 9], [5])]) == (0.0, 1.0)
+    assert oracle.ce_score([], []) == (1.0, 0.0)
+    assert oracle.ce_score(a, []) == (0.0, 1.0)
+    # worked by hand: one shared cell (1, 1); 4 + 4 - 1 = 7 cells in all
+    assert oracle.ce_score([([0, 1], [0, 1])], [([1, 2], [1, 2])]) == (1 / 7, 6 / 7)
+    # order and repeats of rows / columns do not matter
+    assert oracle.ce_score([([2, 0, 1, 1], [1, 0])], [([0, 1, 2], [0, 1])]) == (1.0, 0.0)
+
+
+def test_ce_score_brute_force_assignment():
+    """D_max against every injective assignment of the smaller set, on small
+    random sets (including unequal sizes)."""
+    rng = np.random.default_rng(41)
+    for trial in range(60):
+        nf, nt = int(rng.integers(0, 5)), int(rng.integers(0, 5))
+        f, t = _random_bics(rng, nf, 12, 8), _random_bics(rng, nt, 12, 8)
+        cells = lambda b: {(int(r), int(c)) for r in b[0] for c in b[1]}
+        m = [[len(cells(x) & cells(y)) for y in t] for x in f]
+        best = 0
+        if nf <= nt:
+            for perm in itertools.permutations(range(nt), nf):
+                best = max(best, sum(m[i][perm[i]] for i in range(nf)))
+        else:
+            for perm in itertools.permutations(range(nf), nt):
+                best = max(best, sum(m[perm[j]][j] for j in range(nt)))
+        u = len(set().union(*[cells(x) for x in f + t]))
+        got = oracle.ce_score(f, t)
+        if u:
+            assert got == (best / u, (u - best) / u), trial
