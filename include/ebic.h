@@ -384,6 +384,9 @@ typedef struct ebic_server_metrics {
     double mean_latency_s;
     double busy_s;              /* time with at least one active job           */
     size_t hbm_in_use, hbm_budget;
+    double stage_s;             /* ticks' host packing and uploads             */
+    double device_s;            /* ticks' launch, downloads and wait           */
+    double host_s;              /* ticks' host steps of the jobs               */
 } ebic_server_metrics;
 
 /* Creates the server on the current device; the scheduler thread uses a

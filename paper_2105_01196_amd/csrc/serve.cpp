@@ -112,7 +112,7 @@ class Server {
     std::vector<double> latencies_;
     int64_t next_id_ = 1, submitted_ = 0, completed_ = 0, failed_ = 0, evaluations_ = 0;
     int64_t ticks_ = 0, n_active_ = 0;
-    double busy_s_ = 0;
+    double busy_s_ = 0, stage_s_ = 0, device_s_ = 0, host_s_ = 0;
     size_t budget_ = 0, in_use_ = 0;
     int32_t max_active_ = 64;
     bool stop_ = false;
@@ -218,6 +218,9 @@ void Server::stats(ebic_server_metrics *st) {
         st->mean_latency_s = sum / l.size();
     }
     st->busy_s = busy_s_;
+    st->stage_s = stage_s_;
+    st->device_s = device_s_;
+    st->host_s = host_s_;
     st->hbm_in_use = in_use_;
     st->hbm_budget = budget_;
 }
@@ -238,6 +241,7 @@ void Server::finish_job(const std::shared_ptr<ServerJob> &j, int status, const c
 void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
     std::vector<ebic_job> views(active.size());
     std::vector<int> src(active.size(), EBIC_OK);
+    const double t0 = now_s();
     // host packing and uploads of every job in parallel (uploads are queued
     // on the one stream; the launch below is queued after all of them)
     pool_->run(active.size(), [&](size_t i) {
@@ -247,6 +251,7 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
     int rc = EBIC_OK;
     for (int v : src)
         if (v != EBIC_OK) rc = v;
+    const double t1 = now_s();
     if (rc == EBIC_OK) rc = batch_set(&batch_, views.data(), (int32_t)views.size(), stream_);
     if (rc == EBIC_OK) rc = batch_run(batch_, stream_);
     for (size_t i = 0; i < active.size() && rc == EBIC_OK; i++) rc = active[i]->job->fetch();
@@ -254,6 +259,7 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
         hipError_t e = hipStreamSynchronize(stream_);
         if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
     }
+    const double t2 = now_s();
     std::vector<int> st(active.size(), rc);
     std::vector<std::string> msg(active.size(), rc ? ebic_last_error() : "");
     if (rc == EBIC_OK)
@@ -262,8 +268,12 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
             st[i] = active[i]->job->advance();
             if (st[i]) msg[i] = ebic_last_error();
         });
+    const double t3 = now_s();
     std::lock_guard<std::mutex> lk(mu_);
     ticks_++;
+    stage_s_ += t1 - t0;
+    device_s_ += t2 - t1;
+    host_s_ += t3 - t2;
     std::vector<std::shared_ptr<ServerJob>> keep;
     for (size_t i = 0; i < active.size(); i++) {
         auto &j = active[i];
