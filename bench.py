@@ -309,7 +309,8 @@ def serving(args):
         "p99_latency_s": st["p99_latency_s"], "mean_latency_s": st["mean_latency_s"],
         "ticks": st["ticks"], "evaluations": evals,
         "tick_phases_s": {"stage": st["stage_s"], "device": st["device_s"],
-                          "host_steps": st["host_s"]},
+                          "host_steps": st["host_s"], "setup_beside_ticks": st["setup_s"],
+                          "release": st["release_s"], "ticks_total": st["busy_s"]},
         "sequential_runs": {"wall_s": seq, "value": evals / seq},
         "results_identical_alone_and_mixed": bool(same),
         "matrix_generation_s": gen_s,

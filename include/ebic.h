@@ -363,10 +363,12 @@ void ebic_session_free(ebic_session *s);
  * order while their device footprint (matrix, ranks, pair table when it
  * takes at most an eighth of the budget, population, outputs, archive) fits
  * in the HBM budget and a slot is free; every admitted job keeps its state
- * resident on the device; each scheduler tick scores the current populations
- * of all active jobs in one batched launch, then runs their host steps. A
- * finished job frees its memory and slot, and queued jobs are admitted at
- * the next tick. Each job's result is identical to ebic_run with the same
+ * resident on the device. A preparer thread sets admitted jobs up (upload,
+ * ranks, pair table, first population) on a stream of its own while the
+ * scheduler keeps ticking; a prepared job joins at the next tick. Each tick
+ * scores the current populations of all active jobs in one batched launch,
+ * then runs their host steps. A finished job frees its memory and slot, and
+ * queued jobs are admitted at the next tick. Each job's result is identical to ebic_run with the same
  * matrix, parameters and seed. */
 typedef struct ebic_server ebic_server;
 
@@ -387,10 +389,12 @@ typedef struct ebic_server_metrics {
     double stage_s;             /* ticks' host packing and uploads             */
     double device_s;            /* ticks' launch, downloads and wait           */
     double host_s;              /* ticks' host steps of the jobs               */
+    double setup_s;             /* admitted jobs' setup, beside the ticks      */
+    double release_s;           /* ended jobs' frees                           */
 } ebic_server_metrics;
 
-/* Creates the server on the current device; the scheduler thread uses a
- * stream of its own. Errors: EBIC_ERR_INVALID_ARG, EBIC_ERR_DEVICE. */
+/* Creates the server on the current device; the scheduler and preparer
+ * threads use a stream each. Errors: EBIC_ERR_INVALID_ARG, EBIC_ERR_DEVICE. */
 int ebic_server_create(const ebic_server_config *cfg, ebic_server **out);
 /* Queues a job (the host matrix is copied; parameters validated as for
  * ebic_run); never waits for the GPU. *job_id identifies it. Errors:

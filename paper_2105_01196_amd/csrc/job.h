@@ -151,6 +151,9 @@ class Job {
         }
     }
     const ebic_allocator *allocator() const { return al_; }
+    // The stream later steps queue on (set up on one stream, run on another);
+    // the caller has synchronized the old one.
+    void set_stream(hipStream_t s) { stream_ = s; }
     // The host matrix (rows x cols, row-major), read by the final step for
     // the rows' directions; it must stay valid while the job runs.
     void set_host_matrix(const float *hx) { hx_ = hx; }
@@ -221,7 +224,7 @@ class Job {
     std::vector<double> fitness_;
     std::vector<int32_t> count_;
     std::vector<int32_t> use_;
-    std::vector<char> in_;  // scratch: columns of the series being mutated
+    Series sorted_;  // scratch: the columns of the series being mutated, sorted
     std::unique_ptr<ResultImpl> res_{new ResultImpl()};
 };
 

@@ -183,16 +183,16 @@ int Job::tournament(const std::vector<double> &key, int n) {
 }
 
 int Job::unused_column(const Series &s) {
-    int pick = rng_.below_int((int64_t)C_ - (int64_t)s.size());
-    if (in_.size() != (size_t)C_) in_.assign(C_, 0);
-    for (uint16_t c : s) in_[c] = 1;
-    int found = -1;
-    for (int c = 0; c < C_ && found < 0; c++) {
-        if (in_[c]) continue;
-        if (pick-- == 0) found = c;
+    // the pick-th (from 0) column outside s in ascending order: every column
+    // of s at or below the running answer pushes it one further
+    int x = rng_.below_int((int64_t)C_ - (int64_t)s.size());
+    sorted_.assign(s.begin(), s.end());
+    std::sort(sorted_.begin(), sorted_.end());
+    for (uint16_t c : sorted_) {
+        if (c > x) break;
+        x++;
     }
-    for (uint16_t c : s) in_[c] = 0;
-    return found;
+    return x;
 }
 
 Series Job::mutate(const std::vector<Series> &pop, const std::vector<double> &key) {

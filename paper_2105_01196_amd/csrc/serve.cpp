@@ -1,8 +1,11 @@
 // Job server: continuous batching of many runs of the method on one GPU.
 //
-// A scheduler thread owns a stream and the batch. Each tick it admits
+// A scheduler thread owns a stream and the batch. Before each tick it admits
 // queued jobs whose device footprint fits the remaining HBM budget (arrival
-// order, so a large job is never starved by smaller ones behind it), stages
+// order, so a large job is never starved by smaller ones behind it) and
+// hands them to a preparer thread, which sets them up on a second stream
+// (allocation, upload, ranks, pair table, first population) while the ticks
+// go on; prepared jobs join the active set at the next tick. A tick stages
 // the population of every active job, scores them all in one batched
 // launch, downloads, and runs each job's host steps. Finished jobs release
 // their device memory and slot.
@@ -12,6 +15,7 @@
 #include <deque>
 #include <functional>
 #include <mutex>
+#include <numeric>
 #include <thread>
 #include <unordered_map>
 
@@ -84,8 +88,10 @@ struct ServerJob {
     size_t footprint = 0;
     std::unique_ptr<Job> job;
     double t_submit = 0, t_done = 0;
-    int status = EBIC_PENDING;
+    int status = EBIC_PENDING;  // published under the server's lock
     std::string error;
+    int end_status = EBIC_OK;   // set by the thread that ends the job, then published
+    std::string end_error;
     ResultImpl *result = nullptr;
 };
 
@@ -102,25 +108,35 @@ class Server {
 
   private:
     void loop();
+    void prepare_loop();
     void tick(std::vector<std::shared_ptr<ServerJob>> &active);
     void finish_job(const std::shared_ptr<ServerJob> &j, int status, const char *err);
+    void release_loop();
+    void end_jobs(const std::vector<std::shared_ptr<ServerJob>> &ended);
+    bool admissible() const;
 
     std::mutex mu_;
-    std::condition_variable cv_work_, cv_done_;
+    std::condition_variable cv_work_, cv_done_, cv_prep_, cv_rel_;
     std::deque<std::shared_ptr<ServerJob>> queue_;
+    // admitted, waiting for the preparer; prepared, waiting for a tick;
+    // ended, waiting for their memory to be freed
+    std::deque<std::shared_ptr<ServerJob>> prep_q_, ready_, rel_q_;
     std::unordered_map<int64_t, std::shared_ptr<ServerJob>> jobs_;
     std::vector<double> latencies_;
     int64_t next_id_ = 1, submitted_ = 0, completed_ = 0, failed_ = 0, evaluations_ = 0;
-    int64_t ticks_ = 0, n_active_ = 0;
-    double busy_s_ = 0, stage_s_ = 0, device_s_ = 0, host_s_ = 0;
+    int64_t ticks_ = 0;
+    int64_t n_active_ = 0;  // admitted, result not yet published
+    int64_t n_held_ = 0;    // admitted, memory not yet freed (the slots in use)
+    bool rel_quit_ = false;
+    double busy_s_ = 0, stage_s_ = 0, device_s_ = 0, host_s_ = 0, setup_s_ = 0, release_s_ = 0;
     size_t budget_ = 0, in_use_ = 0;
     int32_t max_active_ = 64;
     bool stop_ = false;
     int device_ = 0;
-    hipStream_t stream_ = nullptr;
+    hipStream_t stream_ = nullptr, prep_stream_ = nullptr;
     Batch *batch_ = nullptr;
     std::unique_ptr<WorkerPool> pool_;
-    std::thread thread_;
+    std::thread thread_, prep_thread_, rel_thread_;
 };
 
 int Server::init(const ebic_server_config *cfg) {
@@ -130,8 +146,11 @@ int Server::init(const ebic_server_config *cfg) {
     budget_ = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : free_b / 10 * 8;
     max_active_ = (cfg && cfg->max_active > 0) ? cfg->max_active : 64;
     EBIC_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
+    EBIC_HIP(hipStreamCreateWithFlags(&prep_stream_, hipStreamNonBlocking));
     const unsigned hw = std::thread::hardware_concurrency();
     pool_.reset(new WorkerPool((int)std::max(1u, std::min(hw ? hw : 1u, 16u))));
+    prep_thread_ = std::thread([this] { prepare_loop(); });
+    rel_thread_ = std::thread([this] { release_loop(); });
     thread_ = std::thread([this] { loop(); });
     return EBIC_OK;
 }
@@ -142,10 +161,21 @@ Server::~Server() {
         stop_ = true;
     }
     cv_work_.notify_all();
+    cv_prep_.notify_all();
+    // the scheduler ends once every admitted job is done, so the preparer
+    // has nothing left when it is told to stop
     if (thread_.joinable()) thread_.join();
+    if (prep_thread_.joinable()) prep_thread_.join();
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        rel_quit_ = true;  // nothing ends any more; free what is left
+    }
+    cv_rel_.notify_all();
+    if (rel_thread_.joinable()) rel_thread_.join();
     pool_.reset();
     if (batch_) batch_destroy(batch_);
     if (stream_) (void)hipStreamDestroy(stream_);
+    if (prep_stream_) (void)hipStreamDestroy(prep_stream_);
     for (auto &kv : jobs_) delete kv.second->result;
 }
 
@@ -221,6 +251,8 @@ void Server::stats(ebic_server_metrics *st) {
     st->stage_s = stage_s_;
     st->device_s = device_s_;
     st->host_s = host_s_;
+    st->setup_s = setup_s_;
+    st->release_s = release_s_;
     st->hbm_in_use = in_use_;
     st->hbm_budget = budget_;
 }
@@ -241,10 +273,18 @@ void Server::finish_job(const std::shared_ptr<ServerJob> &j, int status, const c
 void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
     std::vector<ebic_job> views(active.size());
     std::vector<int> src(active.size(), EBIC_OK);
+    // the pool takes the largest populations first, so the slowest job's
+    // host work does not start last
+    std::vector<size_t> lpt(active.size());
+    std::iota(lpt.begin(), lpt.end(), 0);
+    std::stable_sort(lpt.begin(), lpt.end(), [&](size_t a, size_t b) {
+        return active[a]->params.population > active[b]->params.population;
+    });
     const double t0 = now_s();
     // host packing and uploads of every job in parallel (uploads are queued
     // on the one stream; the launch below is queued after all of them)
-    pool_->run(active.size(), [&](size_t i) {
+    pool_->run(active.size(), [&](size_t q) {
+        const size_t i = lpt[q];
         (void)hipSetDevice(device_);
         src[i] = active[i]->job->stage(&views[i]);
     });
@@ -263,92 +303,186 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
     std::vector<int> st(active.size(), rc);
     std::vector<std::string> msg(active.size(), rc ? ebic_last_error() : "");
     if (rc == EBIC_OK)
-        pool_->run(active.size(), [&](size_t i) {
+        pool_->run(active.size(), [&](size_t q) {
+            const size_t i = lpt[q];
             (void)hipSetDevice(device_);
             st[i] = active[i]->job->advance();
             if (st[i]) msg[i] = ebic_last_error();
         });
     const double t3 = now_s();
-    std::lock_guard<std::mutex> lk(mu_);
-    ticks_++;
-    stage_s_ += t1 - t0;
-    device_s_ += t2 - t1;
-    host_s_ += t3 - t2;
-    std::vector<std::shared_ptr<ServerJob>> keep;
+    std::vector<std::shared_ptr<ServerJob>> keep, ended;
     for (size_t i = 0; i < active.size(); i++) {
         auto &j = active[i];
         if (st[i] == EBIC_OK && !j->job->done()) {
             keep.push_back(j);
             continue;
         }
-        if (st[i] == EBIC_OK) {
-            evaluations_ += j->job->evaluations();
+        j->end_status = st[i];
+        if (st[i] == EBIC_OK)
             j->result = j->job->take_result();
-        }
-        finish_job(j, st[i], st[i] ? msg[i].c_str() : nullptr);
-        j->job.reset();  // device memory back to the budget
-        j->x.clear();
-        j->x.shrink_to_fit();
-        in_use_ -= j->footprint;
+        else
+            j->end_error = msg[i];
+        ended.push_back(j);
+    }
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        ticks_++;
+        stage_s_ += t1 - t0;
+        device_s_ += t2 - t1;
+        host_s_ += t3 - t2;
     }
     active.swap(keep);
-    n_active_ = (int64_t)active.size();
+    end_jobs(ended);
+}
+
+// Publishes the ended jobs' results (status in ServerJob::end_status)
+// and hands them to the releaser; their footprint and slot stay taken until
+// their memory is freed.
+void Server::end_jobs(const std::vector<std::shared_ptr<ServerJob>> &ended) {
+    if (ended.empty()) return;
+    {
+        std::lock_guard<std::mutex> lk(mu_);
+        for (auto &j : ended) {
+            const int status = j->end_status;
+            if (status == EBIC_OK) evaluations_ += j->job->evaluations();
+            finish_job(j, status, status ? j->end_error.c_str() : nullptr);
+            rel_q_.push_back(j);
+        }
+        n_active_ -= (int64_t)ended.size();
+    }
     cv_done_.notify_all();
+    cv_rel_.notify_all();
+}
+
+// Frees ended jobs' device and host memory on a thread of its own (a device
+// free waits for all the GPU's queued work), then returns their footprint
+// and slot to admission.
+void Server::release_loop() {
+    (void)hipSetDevice(device_);
+    for (;;) {
+        std::vector<std::shared_ptr<ServerJob>> gone;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_rel_.wait(lk, [&] { return rel_quit_ || !rel_q_.empty(); });
+            if (rel_q_.empty()) return;
+            gone.assign(rel_q_.begin(), rel_q_.end());
+            rel_q_.clear();
+        }
+        const double t0 = now_s();
+        for (auto &j : gone) {
+            j->job.reset();
+            j->x.clear();
+            j->x.shrink_to_fit();
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            release_s_ += now_s() - t0;
+            for (auto &j : gone) in_use_ -= j->footprint;
+            n_held_ -= (int64_t)gone.size();
+        }
+        cv_work_.notify_all();
+    }
+}
+
+// With mu_ held: whether the queue's head can be decided now (admitted, or
+// failed for exceeding the whole budget).
+bool Server::admissible() const {
+    if (queue_.empty()) return false;
+    const size_t f = queue_.front()->footprint;
+    return f > budget_ || (in_use_ + f <= budget_ && n_held_ < max_active_);
+}
+
+void Server::prepare_loop() {
+    (void)hipSetDevice(device_);
+    for (;;) {
+        std::shared_ptr<ServerJob> j;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_prep_.wait(lk, [&] { return stop_ || !prep_q_.empty(); });
+            if (prep_q_.empty()) return;  // stopping, and nothing admitted is left
+            j = prep_q_.front();
+            prep_q_.pop_front();
+        }
+        const double t0 = now_s();
+        j->job.reset(new Job(j->params, j->seed, prep_stream_));
+        j->job->set_host_matrix(j->x.data());  // the job's own copy, for row directions
+        int rc = j->job->setup(j->x.data(), j->rows, j->cols, j->pairs);
+        if (rc == EBIC_OK) {
+            const hipError_t e = hipStreamSynchronize(prep_stream_);
+            if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
+        }
+        std::string err;
+        if (rc == EBIC_OK) {
+            j->job->start();
+            j->job->set_stream(stream_);
+        } else {
+            err = ebic_last_error();
+        }
+        const double t1 = now_s();
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            setup_s_ += t1 - t0;
+            if (rc == EBIC_OK) ready_.push_back(j);
+        }
+        if (rc != EBIC_OK) {
+            j->end_status = rc;
+            j->end_error = err;
+            end_jobs({j});
+        }
+        cv_work_.notify_all();
+    }
 }
 
 void Server::loop() {
     (void)hipSetDevice(device_);
     std::vector<std::shared_ptr<ServerJob>> active;
     for (;;) {
-        std::vector<std::shared_ptr<ServerJob>> admit;
         {
             std::unique_lock<std::mutex> lk(mu_);
-            cv_work_.wait(lk, [&] { return stop_ || !queue_.empty() || !active.empty(); });
-            if (stop_) {  // queued jobs are dropped; active ones finish
+            cv_work_.wait(lk, [&] {
+                return stop_ || !active.empty() || !ready_.empty() || admissible();
+            });
+            if (stop_ && !queue_.empty()) {  // queued jobs are dropped; admitted ones finish
                 while (!queue_.empty()) {
                     finish_job(queue_.front(), EBIC_ERR_CAPACITY, "server stopped");
                     queue_.pop_front();
                 }
                 cv_done_.notify_all();
-                if (active.empty()) break;
             }
-            while (!queue_.empty() && (int32_t)(active.size() + admit.size()) < max_active_) {
-                auto &j = queue_.front();
+            if (stop_ && n_active_ == 0) break;
+            bool admitted = false;
+            while (admissible()) {
+                auto j = queue_.front();
+                queue_.pop_front();
                 if (j->footprint > budget_) {
                     finish_job(j, EBIC_ERR_CAPACITY, "footprint exceeds the HBM budget");
-                    queue_.pop_front();
                     cv_done_.notify_all();
                     continue;
                 }
-                if (in_use_ + j->footprint > budget_) break;
                 in_use_ += j->footprint;
-                admit.push_back(j);
-                queue_.pop_front();
+                n_active_++;  // admitted jobs count as active
+                n_held_++;
+                prep_q_.push_back(j);
+                admitted = true;
             }
-            n_active_ = (int64_t)(active.size() + admit.size());  // admitted count as active
-        }
-        for (auto &j : admit) {
-            j->job.reset(new Job(j->params, j->seed, stream_));
-            j->job->set_host_matrix(j->x.data());  // the job's own copy, for row directions
-            int rc = j->job->setup(j->x.data(), j->rows, j->cols, j->pairs);
-            if (rc == EBIC_OK) {
-                j->job->start();
-                active.push_back(j);
-            } else {
-                std::lock_guard<std::mutex> lk(mu_);
-                finish_job(j, rc, ebic_last_error());
-                j->job.reset();
-                in_use_ -= j->footprint;
-                n_active_--;
-                cv_done_.notify_all();
+            if (admitted) cv_prep_.notify_all();
+            while (!ready_.empty()) {
+                active.push_back(ready_.front());
+                ready_.pop_front();
             }
         }
-        if (active.empty()) continue;
+        if (active.empty()) {
+            // nothing to tick: wait for the preparer or a release
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_work_.wait(lk, [&] { return !ready_.empty() || admissible() || (stop_ && n_active_ == 0); });
+            continue;
+        }
         const double t0 = now_s();
         tick(active);
         std::lock_guard<std::mutex> lk(mu_);
         busy_s_ += now_s() - t0;
     }
+    cv_prep_.notify_all();
 }
 
 int server_create(const ebic_server_config *cfg, Server **out) {

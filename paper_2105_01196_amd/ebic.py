@@ -103,7 +103,8 @@ class ebic_server_metrics(ctypes.Structure):
                 ("p99_latency_s", ctypes.c_double), ("mean_latency_s", ctypes.c_double),
                 ("busy_s", ctypes.c_double), ("hbm_in_use", ctypes.c_size_t),
                 ("hbm_budget", ctypes.c_size_t), ("stage_s", ctypes.c_double),
-                ("device_s", ctypes.c_double), ("host_s", ctypes.c_double)]
+                ("device_s", ctypes.c_double), ("host_s", ctypes.c_double),
+                ("setup_s", ctypes.c_double), ("release_s", ctypes.c_double)]
 
 
 EBIC_STOP_GENERATIONS = 1
