@@ -6,7 +6,7 @@
 #include <cmath>
 #include <memory>
 #include <numeric>
-#include <unordered_set>
+#include <iterator>
 #include <vector>
 
 #include "internal.h"
@@ -43,21 +43,92 @@ class SplitMix64 {
 
 using Series = std::vector<uint16_t>;
 
-struct SeriesHash {
-    size_t operator()(const Series &s) const {
-        uint64_t h = 0x84222325CBF29CE4ULL ^ s.size();
-        for (uint16_t c : s) h = (h ^ c) * 0x100000001B3ULL;
-        return (size_t)h;
-    }
-};
-
 // With negative trends a series and its reverse have the same support; the
 // smaller of the two stands for both in the tabu list and the top-rank list.
-inline Series canonical(const Series &s, bool neg) {
-    if (!neg) return s;
-    Series r(s.rbegin(), s.rend());
-    return std::lexicographical_compare(r.begin(), r.end(), s.begin(), s.end()) ? r : s;
+inline bool reverse_smaller(const uint16_t *s, size_t k) {
+    for (size_t i = 0; i < k; i++)
+        if (s[k - 1 - i] != s[i]) return s[k - 1 - i] < s[i];
+    return false;
 }
+inline Series canonical(const Series &s, bool neg) {
+    if (!neg || !reverse_smaller(s.data(), s.size())) return s;
+    return Series(s.rbegin(), s.rend());
+}
+// Whether canonical(s, neg) equals the canonical series c, without a copy.
+inline bool same_canonical(const Series &s, const Series &c, bool neg) {
+    if (s.size() != c.size()) return false;
+    return std::equal(s.begin(), s.end(), c.begin()) ||
+           (neg && std::equal(s.rbegin(), s.rend(), c.begin()));
+}
+
+// The tabu list (Sec. 2.4, step 6): a set of canonical series, open
+// addressing over one flat arena of columns, so an insert allocates only
+// when a buffer doubles.
+class TabuSet {
+  public:
+    // Inserts canonical(s, neg); false if it was present.
+    bool insert(const uint16_t *s, size_t k, bool neg) {
+        const uint16_t *c = s;
+        if (neg && reverse_smaller(s, k)) {
+            scratch_.assign(std::reverse_iterator<const uint16_t *>(s + k),
+                            std::reverse_iterator<const uint16_t *>(s));
+            c = scratch_.data();
+        }
+        uint64_t h = 0x84222325CBF29CE4ULL ^ k;
+        for (size_t i = 0; i < k; i++) h = (h ^ c[i]) * 0x100000001B3ULL;
+        h ^= h >> 31;
+        h *= 0x94D049BB133111EBULL;
+        h ^= h >> 29;
+        if (2 * (n_ + 1) > slots_.size()) grow();
+        const size_t mask = slots_.size() - 1;
+        for (size_t i = (size_t)h & mask;; i = (i + 1) & mask) {
+            Slot &e = slots_[i];
+            if (e.len1 == 0) {
+                e.hash = h;
+                e.off = arena_.size();
+                e.len1 = (uint32_t)k + 1;
+                arena_.insert(arena_.end(), c, c + k);
+                n_++;
+                return true;
+            }
+            if (e.hash == h && e.len1 == k + 1 && std::equal(c, c + k, arena_.data() + e.off))
+                return false;
+        }
+    }
+    bool insert(const Series &s, bool neg) { return insert(s.data(), s.size(), neg); }
+    size_t size() const { return n_; }
+    void clear() {
+        slots_.clear();
+        arena_.clear();
+        n_ = 0;
+    }
+    // f(columns, length) for every member, in no particular order.
+    template <class F>
+    void for_each(F &&f) const {
+        for (const Slot &e : slots_)
+            if (e.len1) f(arena_.data() + e.off, (size_t)e.len1 - 1);
+    }
+
+  private:
+    struct Slot {
+        uint64_t hash = 0, off = 0;
+        uint32_t len1 = 0;  // length + 1; 0 marks a free slot
+    };
+    void grow() {
+        std::vector<Slot> old(std::max<size_t>(1024, 2 * slots_.size()));
+        old.swap(slots_);
+        const size_t mask = slots_.size() - 1;
+        for (const Slot &e : old) {
+            if (!e.len1) continue;
+            size_t i = (size_t)e.hash & mask;
+            while (slots_[i].len1) i = (i + 1) & mask;
+            slots_[i] = e;
+        }
+    }
+    std::vector<Slot> slots_;
+    std::vector<uint16_t> arena_, scratch_;
+    size_t n_ = 0;
+};
 
 // Top-rank order: larger score first, then the lexicographically smaller
 // series (a proper prefix first).
@@ -218,7 +289,7 @@ class Job {
     int64_t evaluations_ = 0;
     std::vector<Series> pop_;   // being scored (or the final list)
     int32_t staged_P_ = 0;
-    std::unordered_set<Series, SeriesHash> tabu_;
+    TabuSet tabu_;
     int64_t tabu_hits_ = 0;
     std::vector<Member> archive_;
     std::vector<double> fitness_;

@@ -12,7 +12,6 @@
 #include <cstring>
 #include <memory>
 #include <numeric>
-#include <unordered_set>
 #include <vector>
 
 #include "job.h"
@@ -134,14 +133,19 @@ void Job::update_archive(const std::vector<Series> &pop) {
     std::vector<double> score(pop.size());
     for (size_t i = 0; i < pop.size(); i++) {
         score[i] = size_score(count_[i], (int)pop[i].size());
-        if (score[i] > 0 &&
-            std::find(listed.begin(), listed.end(), canonical(pop[i], neg_)) == listed.end())
+        if (score[i] > 0 && std::none_of(listed.begin(), listed.end(), [&](const Series &c) {
+                return same_canonical(pop[i], c, neg_);
+            }))
             cand.push_back((int32_t)i);
     }
-    std::sort(cand.begin(), cand.end(), [&](int32_t a, int32_t b) {
-        return ranks_above(score[a], pop[a], score[b], pop[b]);
-    });
-    for (int32_t i : cand) {
+    // candidates best first; usually only the first few are looked at, so
+    // they come off a heap instead of a full sort (the series are distinct,
+    // so the order is the same)
+    auto worse = [&](int32_t a, int32_t b) { return ranks_above(score[b], pop[b], score[a], pop[a]); };
+    std::make_heap(cand.begin(), cand.end(), worse);
+    for (auto end = cand.end(); end != cand.begin();) {
+        std::pop_heap(cand.begin(), end, worse);
+        const int32_t i = *--end;
         const Series &s = pop[i];
         if ((int32_t)archive_.size() == K &&
             !ranks_above(score[i], s, archive_.back().score, archive_.back().s))
@@ -260,7 +264,7 @@ void Job::start() {
                 std::swap(ident[j], ident[j + rng_.below_int(C_ - j)]);
                 s[j] = (uint16_t)ident[j];
             }
-            if (!tabu_.insert(canonical(s, neg_)).second) continue;
+            if (!tabu_.insert(s, neg_)) continue;
             pop_.push_back(std::move(s));
             break;
         }
@@ -325,7 +329,7 @@ void Job::next_population() {
             }
             Series child = mutate(pop_, key);
             if ((int)child.size() < p_.k_min || (int)child.size() > p_.k_max) continue;
-            if (!tabu_.insert(canonical(child, neg_)).second) {
+            if (!tabu_.insert(child, neg_)) {
                 if (++tabu_hits_ >= p_.max_tabu_hits) {
                     stop_ = EBIC_STOP_TABU;
                     break;
@@ -538,14 +542,14 @@ void Job::save(std::vector<uint8_t> &out, uint64_t mhash) const {
     }
     // the tabu list in a canonical (sorted) order, so that equal states
     // give equal bytes
-    std::vector<const Series *> tabu;
+    std::vector<Series> tabu;
     tabu.reserve(tabu_.size());
-    for (const Series &s : tabu_) tabu.push_back(&s);
-    std::sort(tabu.begin(), tabu.end(), [](const Series *a, const Series *b) {
-        return a->size() != b->size() ? a->size() < b->size() : *a < *b;
+    tabu_.for_each([&](const uint16_t *c, size_t k) { tabu.emplace_back(c, c + k); });
+    std::sort(tabu.begin(), tabu.end(), [](const Series &a, const Series &b) {
+        return a.size() != b.size() ? a.size() < b.size() : a < b;
     });
     w.put((uint64_t)tabu.size());
-    for (const Series *s : tabu) w.series(*s);
+    for (const Series &s : tabu) w.series(s);
     for (char c : kMagic) w.put(c);
 }
 
@@ -605,7 +609,7 @@ int Job::load(const uint8_t *p, size_t n) {
     }
     const uint64_t ntabu = r.get<uint64_t>();
     tabu_.clear();
-    for (uint64_t i = 0; i < ntabu && r.ok; i++) tabu_.insert(r.series(C_));
+    for (uint64_t i = 0; i < ntabu && r.ok; i++) tabu_.insert(r.series(C_), neg_);
     for (char c : kMagic)
         if (r.get<char>() != c) r.ok = false;
     if (!r.ok || r.at != n || tabu_.size() != ntabu)
