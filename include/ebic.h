@@ -386,8 +386,8 @@ typedef struct ebic_server_metrics {
     double mean_latency_s;
     double busy_s;              /* time with at least one active job           */
     size_t hbm_in_use, hbm_budget;
-    double stage_s;             /* ticks' host packing and uploads             */
-    double device_s;            /* ticks' launch, downloads and wait           */
+    double stage_s;             /* ticks' host packing                         */
+    double device_s;            /* ticks' upload, launch, download and wait    */
     double host_s;              /* ticks' host steps of the jobs               */
     double setup_s;             /* admitted jobs' setup, beside the ticks      */
     double release_s;           /* ended jobs' frees                           */

@@ -186,8 +186,16 @@ struct PinnedArray {
         if (p) (void)hipHostFree(p);
     }
     hipError_t alloc(size_t count) {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
         n = count ? count : 1;
-        return hipHostMalloc(reinterpret_cast<void **>(&p), n * sizeof(T), hipHostMallocDefault);
+        const hipError_t e =
+            hipHostMalloc(reinterpret_cast<void **>(&p), n * sizeof(T), hipHostMallocDefault);
+        if (e != hipSuccess) {
+            p = nullptr;
+            n = 0;
+        }
+        return e;
     }
 };
 
@@ -210,6 +218,14 @@ class Job {
     void start();                     // step 1
     int stage(ebic_job *job);         // upload what is to be scored next
     int fetch();                      // queue the outputs' download
+    // Staging through buffers shared by many jobs (one upload and one
+    // download for all of them): the byte sizes of this job's input and
+    // output slices for the next stage, then the packing of its inputs into
+    // h_in (whose device copy is d_in) with its outputs directed to d_out;
+    // advance() then reads them from h_out, the host copy of d_out. Both
+    // slices start 256-byte aligned.
+    void slice_bytes(size_t *in_bytes, size_t *out_bytes) const;
+    void stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out, uint8_t *d_out);
     int advance();                    // host steps after the scores arrived
     bool done() const { return phase_ == Phase::Done; }
     ResultImpl *take_result() { return res_.release(); }
@@ -289,6 +305,19 @@ class Job {
     int64_t evaluations_ = 0;
     std::vector<Series> pop_;   // being scored (or the final list)
     int32_t staged_P_ = 0;
+    // where advance() reads the scores: the job's own pinned arrays, or its
+    // slice of a shared download
+    const double *got_fit_ = nullptr;
+    const int32_t *got_cnt_ = nullptr;
+    const uint64_t *got_sup_ = nullptr;
+    const uint64_t *got_dsup_ = nullptr;  // the same supports on the device
+    struct Slices {
+        size_t off, cols, order, asup, aoff, acols, in_bytes;
+        size_t fit, cnt, sup, out_bytes;
+    };
+    Slices slices() const;
+    void pack(int32_t *off, uint16_t *cols, int32_t *order, uint64_t *asup, int32_t *aoff,
+              uint16_t *acols) const;
     TabuSet tabu_;
     int64_t tabu_hits_ = 0;
     std::vector<Member> archive_;

@@ -67,21 +67,36 @@ int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs) {
     return EBIC_OK;
 }
 
-int Job::stage(ebic_job *job) {
+// The population compressed (longest series first in the processing order)
+// and, while generations run, the top-rank list the overlap is taken against.
+void Job::pack(int32_t *off, uint16_t *cols, int32_t *order, uint64_t *asup, int32_t *aoff,
+               uint16_t *acols) const {
     const std::vector<Series> &pop = pop_;
-    const bool with_archive = phase_ == Phase::Eval;
     const int32_t P = (int32_t)pop.size();
-    const int32_t K = with_archive ? (int32_t)archive_.size() : 0;
-    staged_P_ = P;
-    // compressed population, longest series first
-    h_off_.p[0] = 0;
+    const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
+    off[0] = 0;
     for (int32_t i = 0; i < P; i++) {
-        std::copy(pop[i].begin(), pop[i].end(), h_cols_.p + h_off_.p[i]);
-        h_off_.p[i + 1] = h_off_.p[i] + (int32_t)pop[i].size();
+        std::copy(pop[i].begin(), pop[i].end(), cols + off[i]);
+        off[i + 1] = off[i] + (int32_t)pop[i].size();
     }
-    std::iota(h_order_.p, h_order_.p + P, 0);
-    std::stable_sort(h_order_.p, h_order_.p + P,
+    std::iota(order, order + P, 0);
+    std::stable_sort(order, order + P,
                      [&](int32_t a, int32_t b) { return pop[a].size() > pop[b].size(); });
+    if (K == 0) return;
+    aoff[0] = 0;
+    for (int32_t j = 0; j < K; j++) {
+        const Member &a = archive_[j];
+        std::copy(a.support.begin(), a.support.end(), asup + (size_t)j * W_);
+        std::copy(a.s.begin(), a.s.end(), acols + aoff[j]);
+        aoff[j + 1] = aoff[j] + (int32_t)a.s.size();
+    }
+}
+
+int Job::stage(ebic_job *job) {
+    const int32_t P = (int32_t)pop_.size();
+    const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
+    staged_P_ = P;
+    pack(h_off_.p, h_cols_.p, h_order_.p, h_asup_.p, h_aoff_.p, h_acols_.p);
     const int32_t len = h_off_.p[P];
     RUN_HIP(hipMemcpyAsync(d_off_.p, h_off_.p, sizeof(int32_t) * (P + 1), hipMemcpyHostToDevice,
                            stream_));
@@ -90,13 +105,6 @@ int Job::stage(ebic_job *job) {
     RUN_HIP(hipMemcpyAsync(d_order_.p, h_order_.p, sizeof(int32_t) * std::max(P, 1),
                            hipMemcpyHostToDevice, stream_));
     if (K > 0) {
-        h_aoff_.p[0] = 0;
-        for (int32_t j = 0; j < K; j++) {
-            const Member &a = archive_[j];
-            std::copy(a.support.begin(), a.support.end(), h_asup_.p + (size_t)j * W_);
-            std::copy(a.s.begin(), a.s.end(), h_acols_.p + h_aoff_.p[j]);
-            h_aoff_.p[j + 1] = h_aoff_.p[j] + (int32_t)a.s.size();
-        }
         RUN_HIP(hipMemcpyAsync(d_asup_.p, h_asup_.p, sizeof(uint64_t) * K * W_,
                                hipMemcpyHostToDevice, stream_));
         RUN_HIP(hipMemcpyAsync(d_aoff_.p, h_aoff_.p, sizeof(int32_t) * (K + 1),
@@ -110,7 +118,76 @@ int Job::stage(ebic_job *job) {
     job->archive = ebic_archive{K, (int32_t)d_acols_.n, d_asup_.p, d_aoff_.p, d_acols_.p};
     job->params = p_;
     job->out = ebic_eval_out{d_fit_.p, d_cnt_.p, d_sup_.p, nullptr};
+    got_fit_ = h_fit_.p;
+    got_cnt_ = h_cnt_.p;
+    got_sup_ = h_sup_.p;
+    got_dsup_ = d_sup_.p;
     return EBIC_OK;
+}
+
+Job::Slices Job::slices() const {
+    const int32_t P = (int32_t)pop_.size();
+    const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
+    size_t len = 0, alen = 0;
+    for (const Series &q : pop_) len += q.size();
+    for (int32_t j = 0; j < K; j++) alen += archive_[j].s.size();
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    Slices l{};
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t here = at;
+        at = up(at + bytes);
+        return here;
+    };
+    l.off = take(sizeof(int32_t) * (P + 1));
+    l.cols = take(sizeof(uint16_t) * std::max<size_t>(len, 1));
+    l.order = take(sizeof(int32_t) * std::max(P, 1));
+    l.asup = take(sizeof(uint64_t) * K * W_);
+    l.aoff = take(sizeof(int32_t) * (K + 1));
+    l.acols = take(sizeof(uint16_t) * std::max<size_t>(alen, 1));
+    l.in_bytes = at;
+    at = 0;
+    l.fit = take(sizeof(double) * std::max(P, 1));
+    l.cnt = take(sizeof(int32_t) * std::max(P, 1));
+    l.sup = take(sizeof(uint64_t) * std::max(P, 1) * W_);
+    l.out_bytes = at;
+    return l;
+}
+
+void Job::slice_bytes(size_t *in_bytes, size_t *out_bytes) const {
+    const Slices l = slices();
+    *in_bytes = l.in_bytes;
+    *out_bytes = l.out_bytes;
+}
+
+void Job::stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out,
+                     uint8_t *d_out) {
+    const Slices l = slices();
+    const int32_t P = (int32_t)pop_.size();
+    const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
+    staged_P_ = P;
+    auto *off = reinterpret_cast<int32_t *>(h_in + l.off);
+    auto *aoff = reinterpret_cast<int32_t *>(h_in + l.aoff);
+    pack(off, reinterpret_cast<uint16_t *>(h_in + l.cols),
+         reinterpret_cast<int32_t *>(h_in + l.order), reinterpret_cast<uint64_t *>(h_in + l.asup),
+         aoff, reinterpret_cast<uint16_t *>(h_in + l.acols));
+    *job = ebic_job{};
+    job->matrix = m_;
+    job->population = ebic_population{P, off[P], reinterpret_cast<const int32_t *>(d_in + l.off),
+                                      reinterpret_cast<const uint16_t *>(d_in + l.cols),
+                                      reinterpret_cast<const int32_t *>(d_in + l.order)};
+    job->archive = ebic_archive{K, K > 0 ? aoff[K] : 0,
+                                reinterpret_cast<const uint64_t *>(d_in + l.asup),
+                                reinterpret_cast<const int32_t *>(d_in + l.aoff),
+                                reinterpret_cast<const uint16_t *>(d_in + l.acols)};
+    job->params = p_;
+    job->out = ebic_eval_out{reinterpret_cast<double *>(d_out + l.fit),
+                             reinterpret_cast<int32_t *>(d_out + l.cnt),
+                             reinterpret_cast<uint64_t *>(d_out + l.sup), nullptr};
+    got_fit_ = reinterpret_cast<const double *>(h_out + l.fit);
+    got_cnt_ = reinterpret_cast<const int32_t *>(h_out + l.cnt);
+    got_sup_ = reinterpret_cast<const uint64_t *>(h_out + l.sup);
+    got_dsup_ = reinterpret_cast<const uint64_t *>(d_out + l.sup);
 }
 
 int Job::fetch() {
@@ -150,7 +227,7 @@ void Job::update_archive(const std::vector<Series> &pop) {
         if ((int32_t)archive_.size() == K &&
             !ranks_above(score[i], s, archive_.back().score, archive_.back().s))
             break;
-        const uint64_t *sup = h_sup_.p + (size_t)i * W_;
+        const uint64_t *sup = got_sup_ + (size_t)i * W_;
         const int64_t n = count_[i], k = (int64_t)s.size();
         std::vector<size_t> clash;
         bool beats = true;
@@ -274,8 +351,8 @@ void Job::start() {
 
 int Job::advance() {
     const int32_t P = staged_P_;
-    fitness_.assign(h_fit_.p, h_fit_.p + P);
-    count_.assign(h_cnt_.p, h_cnt_.p + P);
+    fitness_.assign(got_fit_, got_fit_ + P);
+    count_.assign(got_cnt_, got_cnt_ + P);
     for (int32_t i = 0; i < P; i++)
         if (count_[i] < 0) return fail(EBIC_ERR_DEVICE, "internal: invalid individual %d", i);
     if (phase_ == Phase::FinalEval) return finish();
@@ -357,7 +434,7 @@ int Job::finish() {
                                stream_));
         RUN_HIP(hipMemcpyAsync(d_roff_.p, roff.data(), sizeof(int32_t) * (nb + 1),
                                hipMemcpyHostToDevice, stream_));
-        int rc = launch_support_rows(d_sup_.p, nb, W_, d_sel_.p, nb, d_roff_.p, d_rows_.p,
+        int rc = launch_support_rows(got_dsup_, nb, W_, d_sel_.p, nb, d_roff_.p, d_rows_.p,
                                      stream_);
         if (rc) return rc;
         std::vector<int32_t> rows(std::max(roff[nb], 1));

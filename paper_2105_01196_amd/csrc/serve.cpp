@@ -5,10 +5,11 @@
 // order, so a large job is never starved by smaller ones behind it) and
 // hands them to a preparer thread, which sets them up on a second stream
 // (allocation, upload, ranks, pair table, first population) while the ticks
-// go on; prepared jobs join the active set at the next tick. A tick stages
-// the population of every active job, scores them all in one batched
-// launch, downloads, and runs each job's host steps. Finished jobs release
-// their device memory and slot.
+// go on; prepared jobs join the active set at the next tick. A tick packs
+// the population and top-rank list of every active job into one shared
+// staging buffer, uploads it with one copy, scores all jobs in one batched
+// launch, downloads every output with one copy, and runs each job's host
+// steps. Finished jobs release their device memory and slot.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -114,6 +115,7 @@ class Server {
     void release_loop();
     void end_jobs(const std::vector<std::shared_ptr<ServerJob>> &ended);
     bool admissible() const;
+    int grow_arenas(size_t in_bytes, size_t out_bytes);
 
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_, cv_prep_, cv_rel_;
@@ -135,6 +137,10 @@ class Server {
     int device_ = 0;
     hipStream_t stream_ = nullptr, prep_stream_ = nullptr;
     Batch *batch_ = nullptr;
+    // one tick's inputs of all jobs (uploaded by one copy) and outputs
+    // (downloaded by one copy); they grow to the largest tick seen
+    PinnedArray<uint8_t> h_in_, h_out_;
+    DeviceArray<uint8_t> d_in_, d_out_;
     std::unique_ptr<WorkerPool> pool_;
     std::thread thread_, prep_thread_, rel_thread_;
 };
@@ -270,38 +276,62 @@ void Server::finish_job(const std::shared_ptr<ServerJob> &j, int status, const c
     }
 }
 
+int Server::grow_arenas(size_t in_bytes, size_t out_bytes) {
+    auto room = [](size_t x) { return x + x / 4 + 4096; };
+    if (in_bytes > h_in_.n) {
+        EBIC_HIP(h_in_.alloc(room(in_bytes)));
+        EBIC_HIP(d_in_.alloc(h_in_.n));
+    }
+    if (out_bytes > h_out_.n) {
+        EBIC_HIP(h_out_.alloc(room(out_bytes)));
+        EBIC_HIP(d_out_.alloc(h_out_.n));
+    }
+    return EBIC_OK;
+}
+
 void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
-    std::vector<ebic_job> views(active.size());
-    std::vector<int> src(active.size(), EBIC_OK);
+    const size_t n = active.size();
+    std::vector<ebic_job> views(n);
     // the pool takes the largest populations first, so the slowest job's
     // host work does not start last
-    std::vector<size_t> lpt(active.size());
+    std::vector<size_t> lpt(n);
     std::iota(lpt.begin(), lpt.end(), 0);
     std::stable_sort(lpt.begin(), lpt.end(), [&](size_t a, size_t b) {
         return active[a]->params.population > active[b]->params.population;
     });
     const double t0 = now_s();
-    // host packing and uploads of every job in parallel (uploads are queued
-    // on the one stream; the launch below is queued after all of them)
-    pool_->run(active.size(), [&](size_t q) {
-        const size_t i = lpt[q];
-        (void)hipSetDevice(device_);
-        src[i] = active[i]->job->stage(&views[i]);
-    });
-    int rc = EBIC_OK;
-    for (int v : src)
-        if (v != EBIC_OK) rc = v;
+    // every job's slices of the shared staging buffers
+    std::vector<size_t> in_at(n + 1, 0), out_at(n + 1, 0);
+    for (size_t i = 0; i < n; i++) {
+        size_t ib = 0, ob = 0;
+        active[i]->job->slice_bytes(&ib, &ob);
+        in_at[i + 1] = in_at[i] + ib;
+        out_at[i + 1] = out_at[i] + ob;
+    }
+    int rc = grow_arenas(in_at[n], out_at[n]);
+    // host packing of every job in parallel, then one upload
+    if (rc == EBIC_OK)
+        pool_->run(n, [&](size_t q) {
+            const size_t i = lpt[q];
+            active[i]->job->stage_into(&views[i], h_in_.p + in_at[i], d_in_.p + in_at[i],
+                                       h_out_.p + out_at[i], d_out_.p + out_at[i]);
+        });
     const double t1 = now_s();
-    if (rc == EBIC_OK) rc = batch_set(&batch_, views.data(), (int32_t)views.size(), stream_);
-    if (rc == EBIC_OK) rc = batch_run(batch_, stream_);
-    for (size_t i = 0; i < active.size() && rc == EBIC_OK; i++) rc = active[i]->job->fetch();
     if (rc == EBIC_OK) {
-        hipError_t e = hipStreamSynchronize(stream_);
-        if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
+        const hipError_t e =
+            hipMemcpyAsync(d_in_.p, h_in_.p, in_at[n], hipMemcpyHostToDevice, stream_);
+        if (e != hipSuccess) rc = check_hip(e, "hipMemcpyAsync");
+    }
+    if (rc == EBIC_OK) rc = batch_set(&batch_, views.data(), (int32_t)n, stream_);
+    if (rc == EBIC_OK) rc = batch_run(batch_, stream_);
+    if (rc == EBIC_OK) {
+        hipError_t e = hipMemcpyAsync(h_out_.p, d_out_.p, out_at[n], hipMemcpyDeviceToHost, stream_);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream_);
+        if (e != hipSuccess) rc = check_hip(e, "download");
     }
     const double t2 = now_s();
-    std::vector<int> st(active.size(), rc);
-    std::vector<std::string> msg(active.size(), rc ? ebic_last_error() : "");
+    std::vector<int> st(n, rc);
+    std::vector<std::string> msg(n, rc ? ebic_last_error() : "");
     if (rc == EBIC_OK)
         pool_->run(active.size(), [&](size_t q) {
             const size_t i = lpt[q];
