@@ -161,4 +161,21 @@ int launch_support_rows(const uint64_t *support, int32_t size, int32_t words, co
     return EBIC_OK;
 }
 
+namespace {
+constexpr int kGatherThreads = 256;
+
+__global__ void __launch_bounds__(kGatherThreads)
+    gather_spans_kernel(const WordSpan *__restrict__ spans, uint64_t *__restrict__ dst) {
+    const WordSpan sp = spans[blockIdx.x];
+    for (int64_t w = threadIdx.x; w < sp.words; w += kGatherThreads) dst[sp.dst_at + w] = sp.src[w];
+}
+}  // namespace
+
+int launch_gather_spans(const WordSpan *d_spans, int32_t n, uint64_t *dst, hipStream_t stream) {
+    if (n <= 0) return EBIC_OK;
+    gather_spans_kernel<<<n, kGatherThreads, 0, stream>>>(d_spans, dst);
+    EBIC_HIP(hipGetLastError());
+    return EBIC_OK;
+}
+
 }  // namespace ebic

@@ -59,6 +59,14 @@ struct EvalJob {
 };
 
 int launch_evaluate_plain(const EvalJob &job, hipStream_t stream);
+// A run of 64-bit words to copy: `words` words from src to dst + dst_at.
+struct WordSpan {
+    const uint64_t *src;
+    uint64_t dst_at;
+    int64_t words;
+};
+// Copies n spans (d_spans on the device) into dst, a workgroup per span.
+int launch_gather_spans(const WordSpan *d_spans, int32_t n, uint64_t *dst, hipStream_t stream);
 int launch_support_rows(const uint64_t *support, int32_t size, int32_t words, const int32_t *sel,
                         int32_t n_sel, const int32_t *row_off, int32_t *rows, hipStream_t stream);
 int launch_prepare(const float *x, int32_t rows, int32_t cols, uint16_t *ranks, int *flag,

@@ -219,13 +219,25 @@ class Job {
     int stage(ebic_job *job);         // upload what is to be scored next
     int fetch();                      // queue the outputs' download
     // Staging through buffers shared by many jobs (one upload and one
-    // download for all of them): the byte sizes of this job's input and
-    // output slices for the next stage, then the packing of its inputs into
-    // h_in (whose device copy is d_in) with its outputs directed to d_out;
-    // advance() then reads them from h_out, the host copy of d_out. Both
-    // slices start 256-byte aligned.
-    void slice_bytes(size_t *in_bytes, size_t *out_bytes) const;
-    void stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out, uint8_t *d_out);
+    // download for all of them): the byte sizes of this job's slices for the
+    // next stage (inputs; scores and counts; supports), then the packing of
+    // its inputs into h_in (whose device copy is d_in), with its scores and
+    // counts directed to d_out (read back from h_out, its host copy) and its
+    // supports to d_sup (left on the device). Slices start 256-byte aligned.
+    void slice_bytes(size_t *in_bytes, size_t *out_bytes, size_t *sup_bytes) const;
+    void stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out, uint8_t *d_out,
+                    uint8_t *d_sup);
+    // After a stage_into's scores have arrived: reads them and orders the
+    // candidates for the top-rank list; *first (may be NULL) gets the first
+    // up to `m` of them, the individuals whose supports the list update will
+    // look at first (none in the final evaluation).
+    int plan(size_t m, std::vector<int32_t> *first);
+    // Host copies of the supports of plan()'s first candidates, in that
+    // order, W words each; others are fetched from the device one by one.
+    void set_first_supports(const uint64_t *h) { first_sup_ = h; }
+    // The supports' words (rows_pad / 64) and their device copy.
+    int32_t words() const { return W_; }
+    const uint64_t *device_supports() const { return got_dsup_; }
     int advance();                    // host steps after the scores arrived
     bool done() const { return phase_ == Phase::Done; }
     ResultImpl *take_result() { return res_.release(); }
@@ -254,7 +266,10 @@ class Job {
 
   private:
     enum class Phase { Eval, FinalEval, Done };
-    void update_archive(const std::vector<Series> &pop);
+    int take_scores();
+    void order_candidates(size_t m);
+    int update_archive();
+    const uint64_t *support_of(int32_t i, size_t pos);
     void next_population();
     int finish();
     int tournament(const std::vector<double> &key, int n);
@@ -311,9 +326,18 @@ class Job {
     const int32_t *got_cnt_ = nullptr;
     const uint64_t *got_sup_ = nullptr;
     const uint64_t *got_dsup_ = nullptr;  // the same supports on the device
+    // the top-rank list update's candidates: scores, the ones not yet taken
+    // (a heap, best on top, in its first heap_n_ entries), the first ones
+    // taken off it in order, and their supports when the host has only those
+    std::vector<double> score_;
+    std::vector<int32_t> cand_, first_;
+    size_t heap_n_ = 0;
+    bool planned_ = false;
+    const uint64_t *first_sup_ = nullptr;
+    std::vector<uint64_t> fetched_;
     struct Slices {
         size_t off, cols, order, asup, aoff, acols, in_bytes;
-        size_t fit, cnt, sup, out_bytes;
+        size_t fit, cnt, out_bytes, sup_bytes;
     };
     Slices slices() const;
     void pack(int32_t *off, uint16_t *cols, int32_t *order, uint64_t *asup, int32_t *aoff,

@@ -122,6 +122,7 @@ int Job::stage(ebic_job *job) {
     got_cnt_ = h_cnt_.p;
     got_sup_ = h_sup_.p;
     got_dsup_ = d_sup_.p;
+    first_sup_ = nullptr;
     return EBIC_OK;
 }
 
@@ -149,19 +150,20 @@ Job::Slices Job::slices() const {
     at = 0;
     l.fit = take(sizeof(double) * std::max(P, 1));
     l.cnt = take(sizeof(int32_t) * std::max(P, 1));
-    l.sup = take(sizeof(uint64_t) * std::max(P, 1) * W_);
     l.out_bytes = at;
+    l.sup_bytes = up(sizeof(uint64_t) * std::max(P, 1) * W_);
     return l;
 }
 
-void Job::slice_bytes(size_t *in_bytes, size_t *out_bytes) const {
+void Job::slice_bytes(size_t *in_bytes, size_t *out_bytes, size_t *sup_bytes) const {
     const Slices l = slices();
     *in_bytes = l.in_bytes;
     *out_bytes = l.out_bytes;
+    *sup_bytes = l.sup_bytes;
 }
 
-void Job::stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out,
-                     uint8_t *d_out) {
+void Job::stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out, uint8_t *d_out,
+                     uint8_t *d_sup) {
     const Slices l = slices();
     const int32_t P = (int32_t)pop_.size();
     const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
@@ -183,11 +185,12 @@ void Job::stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out
     job->params = p_;
     job->out = ebic_eval_out{reinterpret_cast<double *>(d_out + l.fit),
                              reinterpret_cast<int32_t *>(d_out + l.cnt),
-                             reinterpret_cast<uint64_t *>(d_out + l.sup), nullptr};
+                             reinterpret_cast<uint64_t *>(d_sup), nullptr};
     got_fit_ = reinterpret_cast<const double *>(h_out + l.fit);
     got_cnt_ = reinterpret_cast<const int32_t *>(h_out + l.cnt);
-    got_sup_ = reinterpret_cast<const uint64_t *>(h_out + l.sup);
-    got_dsup_ = reinterpret_cast<const uint64_t *>(d_out + l.sup);
+    got_sup_ = nullptr;  // the supports stay on the device
+    got_dsup_ = reinterpret_cast<const uint64_t *>(d_sup);
+    first_sup_ = nullptr;
 }
 
 int Job::fetch() {
@@ -202,32 +205,72 @@ int Job::fetch() {
     return EBIC_OK;
 }
 
-void Job::update_archive(const std::vector<Series> &pop) {
-    const int32_t K = p_.archive_size;
+// Steps 3 and 7, first part: the size scores of the population and its
+// candidates for the top-rank list (a positive score, not listed already),
+// kept on a heap best first; the first `m` come off it into first_.
+// Usually only the first few are ever looked at, hence a heap rather than a
+// full sort (the series are distinct, so the order is the same).
+void Job::order_candidates(size_t m) {
+    const std::vector<Series> &pop = pop_;
     std::vector<Series> listed;
     for (const Member &a : archive_) listed.push_back(canonical(a.s, neg_));
-    std::vector<int32_t> cand;
-    std::vector<double> score(pop.size());
+    cand_.clear();
+    first_.clear();
+    score_.assign(pop.size(), 0.0);
     for (size_t i = 0; i < pop.size(); i++) {
-        score[i] = size_score(count_[i], (int)pop[i].size());
-        if (score[i] > 0 && std::none_of(listed.begin(), listed.end(), [&](const Series &c) {
+        score_[i] = size_score(count_[i], (int)pop[i].size());
+        if (score_[i] > 0 && std::none_of(listed.begin(), listed.end(), [&](const Series &c) {
                 return same_canonical(pop[i], c, neg_);
             }))
-            cand.push_back((int32_t)i);
+            cand_.push_back((int32_t)i);
     }
-    // candidates best first; usually only the first few are looked at, so
-    // they come off a heap instead of a full sort (the series are distinct,
-    // so the order is the same)
-    auto worse = [&](int32_t a, int32_t b) { return ranks_above(score[b], pop[b], score[a], pop[a]); };
-    std::make_heap(cand.begin(), cand.end(), worse);
-    for (auto end = cand.end(); end != cand.begin();) {
-        std::pop_heap(cand.begin(), end, worse);
-        const int32_t i = *--end;
+    auto worse = [&](int32_t a, int32_t b) {
+        return ranks_above(score_[b], pop[b], score_[a], pop[a]);
+    };
+    std::make_heap(cand_.begin(), cand_.end(), worse);
+    heap_n_ = cand_.size();
+    while (first_.size() < m && heap_n_ > 0) {
+        std::pop_heap(cand_.begin(), cand_.begin() + heap_n_, worse);
+        first_.push_back(cand_[--heap_n_]);
+    }
+}
+
+// The support of pop_[i], the pos-th candidate taken.
+const uint64_t *Job::support_of(int32_t i, size_t pos) {
+    if (got_sup_) return got_sup_ + (size_t)i * W_;
+    if (first_sup_ && pos < first_.size()) return first_sup_ + pos * W_;
+    fetched_.resize(W_);
+    if (hipMemcpy(fetched_.data(), got_dsup_ + (size_t)i * W_, sizeof(uint64_t) * W_,
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return nullptr;
+    return fetched_.data();
+}
+
+// Steps 3 and 7, second part: candidates in rank order enter the list
+// unless they clash with (overlap too much) a member that ranks above them;
+// members they clash with and outrank leave it.
+int Job::update_archive() {
+    const std::vector<Series> &pop = pop_;
+    const int32_t K = p_.archive_size;
+    auto worse = [&](int32_t a, int32_t b) {
+        return ranks_above(score_[b], pop[b], score_[a], pop[a]);
+    };
+    for (size_t pos = 0;; pos++) {
+        int32_t i;
+        if (pos < first_.size()) {
+            i = first_[pos];
+        } else if (heap_n_ > 0) {
+            std::pop_heap(cand_.begin(), cand_.begin() + heap_n_, worse);
+            i = cand_[--heap_n_];
+        } else {
+            break;
+        }
         const Series &s = pop[i];
         if ((int32_t)archive_.size() == K &&
-            !ranks_above(score[i], s, archive_.back().score, archive_.back().s))
+            !ranks_above(score_[i], s, archive_.back().score, archive_.back().s))
             break;
-        const uint64_t *sup = got_sup_ + (size_t)i * W_;
+        const uint64_t *sup = support_of(i, pos);
+        if (!sup) return fail(EBIC_ERR_DEVICE, "support download failed");
         const int64_t n = count_[i], k = (int64_t)s.size();
         std::vector<size_t> clash;
         bool beats = true;
@@ -236,7 +279,7 @@ void Job::update_archive(const std::vector<Series> &pop) {
             const int64_t g = shared_cols(s, archive_[j].s);
             if (1000 * h * g > (int64_t)p_.overlap_permille * n * k) {
                 clash.push_back(j);
-                if (!ranks_above(score[i], s, archive_[j].score, archive_[j].s)) beats = false;
+                if (!ranks_above(score_[i], s, archive_[j].score, archive_[j].s)) beats = false;
             }
         }
         if (!clash.empty() && !beats) continue;
@@ -245,13 +288,14 @@ void Job::update_archive(const std::vector<Series> &pop) {
         m.s = s;
         m.support.assign(sup, sup + W_);
         m.n = count_[i];
-        m.score = score[i];
+        m.score = score_[i];
         auto at = std::find_if(archive_.begin(), archive_.end(), [&](const Member &a) {
             return !ranks_above(a.score, a.s, m.score, m.s);
         });
         archive_.insert(at, std::move(m));
         if ((int32_t)archive_.size() > K) archive_.pop_back();
     }
+    return EBIC_OK;
 }
 
 int Job::tournament(const std::vector<double> &key, int n) {
@@ -349,16 +393,38 @@ void Job::start() {
     phase_ = Phase::Eval;
 }
 
-int Job::advance() {
+int Job::take_scores() {
     const int32_t P = staged_P_;
     fitness_.assign(got_fit_, got_fit_ + P);
     count_.assign(got_cnt_, got_cnt_ + P);
     for (int32_t i = 0; i < P; i++)
         if (count_[i] < 0) return fail(EBIC_ERR_DEVICE, "internal: invalid individual %d", i);
+    return EBIC_OK;
+}
+
+int Job::plan(size_t m, std::vector<int32_t> *first) {
+    int rc = take_scores();
+    if (rc) return rc;
+    if (phase_ == Phase::Eval) order_candidates(m);
+    else first_.clear();
+    planned_ = true;
+    if (first) *first = first_;
+    return EBIC_OK;
+}
+
+int Job::advance() {
+    const int32_t P = staged_P_;
+    if (!planned_) {
+        int rc = take_scores();
+        if (rc) return rc;
+        if (phase_ == Phase::Eval) order_candidates(0);
+    }
+    planned_ = false;
     if (phase_ == Phase::FinalEval) return finish();
     // steps 3 and 7: top-rank list
     evaluations_ += P;
-    update_archive(pop_);
+    int rc = update_archive();
+    if (rc) return rc;
     ResultImpl *res = res_.get();
     res->trace.push_back((double)P);
     res->trace.push_back((double)archive_.size());

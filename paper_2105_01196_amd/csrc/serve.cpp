@@ -115,7 +115,9 @@ class Server {
     void release_loop();
     void end_jobs(const std::vector<std::shared_ptr<ServerJob>> &ended);
     bool admissible() const;
-    int grow_arenas(size_t in_bytes, size_t out_bytes);
+    int fetch_first_supports(const std::vector<std::shared_ptr<ServerJob>> &active,
+                             const std::vector<std::vector<int32_t>> &first,
+                             std::vector<size_t> *at);
 
     std::mutex mu_;
     std::condition_variable cv_work_, cv_done_, cv_prep_, cv_rel_;
@@ -137,10 +139,16 @@ class Server {
     int device_ = 0;
     hipStream_t stream_ = nullptr, prep_stream_ = nullptr;
     Batch *batch_ = nullptr;
-    // one tick's inputs of all jobs (uploaded by one copy) and outputs
-    // (downloaded by one copy); they grow to the largest tick seen
+    // One tick's inputs of all jobs (uploaded by one copy), scores and
+    // counts (downloaded by one copy) and supports (left on the device); the
+    // spans that gather the supports the top-rank list updates look at, and
+    // those supports (one copy each way). All grow to the largest tick seen.
     PinnedArray<uint8_t> h_in_, h_out_;
-    DeviceArray<uint8_t> d_in_, d_out_;
+    DeviceArray<uint8_t> d_in_, d_out_, d_sup_;
+    PinnedArray<WordSpan> h_spans_;
+    DeviceArray<WordSpan> d_spans_;
+    PinnedArray<uint64_t> h_first_;
+    DeviceArray<uint64_t> d_first_;
     std::unique_ptr<WorkerPool> pool_;
     std::thread thread_, prep_thread_, rel_thread_;
 };
@@ -276,16 +284,56 @@ void Server::finish_job(const std::shared_ptr<ServerJob> &j, int status, const c
     }
 }
 
-int Server::grow_arenas(size_t in_bytes, size_t out_bytes) {
-    auto room = [](size_t x) { return x + x / 4 + 4096; };
-    if (in_bytes > h_in_.n) {
-        EBIC_HIP(h_in_.alloc(room(in_bytes)));
-        EBIC_HIP(d_in_.alloc(h_in_.n));
+namespace {
+// Grows a pinned host buffer and its device twin to hold `count` elements.
+template <typename T>
+int grow(PinnedArray<T> &h, DeviceArray<T> &d, size_t count) {
+    if (count <= h.n && h.p) return EBIC_OK;
+    const size_t room = count + count / 4 + 512;
+    EBIC_HIP(h.alloc(room));
+    EBIC_HIP(d.alloc(room));
+    return EBIC_OK;
+}
+template <typename T>
+int grow(DeviceArray<T> &d, size_t count) {
+    if (count <= d.n && d.p) return EBIC_OK;
+    EBIC_HIP(d.alloc(count + count / 4 + 512));
+    return EBIC_OK;
+}
+}  // namespace
+
+// Downloads, for every job, the supports of the candidates its top-rank list
+// update looks at first (gathered on the device into one buffer); job i's
+// land at h_first_.p + (*at)[i].
+int Server::fetch_first_supports(const std::vector<std::shared_ptr<ServerJob>> &active,
+                                 const std::vector<std::vector<int32_t>> &first,
+                                 std::vector<size_t> *at) {
+    const size_t n = active.size();
+    at->assign(n + 1, 0);
+    size_t spans = 0;
+    for (size_t i = 0; i < n; i++) {
+        (*at)[i + 1] = (*at)[i] + first[i].size() * (size_t)active[i]->job->words();
+        spans += first[i].size();
     }
-    if (out_bytes > h_out_.n) {
-        EBIC_HIP(h_out_.alloc(room(out_bytes)));
-        EBIC_HIP(d_out_.alloc(h_out_.n));
+    if (spans == 0) return EBIC_OK;
+    int rc = grow(h_spans_, d_spans_, spans);
+    if (rc == EBIC_OK) rc = grow(h_first_, d_first_, (*at)[n]);
+    if (rc) return rc;
+    size_t q = 0;
+    for (size_t i = 0; i < n; i++) {
+        const Job &jb = *active[i]->job;
+        const int64_t W = jb.words();
+        for (size_t pos = 0; pos < first[i].size(); pos++)
+            h_spans_.p[q++] = WordSpan{jb.device_supports() + (size_t)first[i][pos] * W,
+                                       (uint64_t)((*at)[i] + pos * W), W};
     }
+    EBIC_HIP(hipMemcpyAsync(d_spans_.p, h_spans_.p, sizeof(WordSpan) * spans,
+                            hipMemcpyHostToDevice, stream_));
+    rc = launch_gather_spans(d_spans_.p, (int32_t)spans, d_first_.p, stream_);
+    if (rc) return rc;
+    EBIC_HIP(hipMemcpyAsync(h_first_.p, d_first_.p, sizeof(uint64_t) * (*at)[n],
+                            hipMemcpyDeviceToHost, stream_));
+    EBIC_HIP(hipStreamSynchronize(stream_));
     return EBIC_OK;
 }
 
@@ -301,20 +349,24 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
     });
     const double t0 = now_s();
     // every job's slices of the shared staging buffers
-    std::vector<size_t> in_at(n + 1, 0), out_at(n + 1, 0);
+    std::vector<size_t> in_at(n + 1, 0), out_at(n + 1, 0), sup_at(n + 1, 0);
     for (size_t i = 0; i < n; i++) {
-        size_t ib = 0, ob = 0;
-        active[i]->job->slice_bytes(&ib, &ob);
+        size_t ib = 0, ob = 0, sb = 0;
+        active[i]->job->slice_bytes(&ib, &ob, &sb);
         in_at[i + 1] = in_at[i] + ib;
         out_at[i + 1] = out_at[i] + ob;
+        sup_at[i + 1] = sup_at[i] + sb;
     }
-    int rc = grow_arenas(in_at[n], out_at[n]);
+    int rc = grow(h_in_, d_in_, in_at[n]);
+    if (rc == EBIC_OK) rc = grow(h_out_, d_out_, out_at[n]);
+    if (rc == EBIC_OK) rc = grow(d_sup_, sup_at[n]);
     // host packing of every job in parallel, then one upload
     if (rc == EBIC_OK)
         pool_->run(n, [&](size_t q) {
             const size_t i = lpt[q];
             active[i]->job->stage_into(&views[i], h_in_.p + in_at[i], d_in_.p + in_at[i],
-                                       h_out_.p + out_at[i], d_out_.p + out_at[i]);
+                                       h_out_.p + out_at[i], d_out_.p + out_at[i],
+                                       d_sup_.p + sup_at[i]);
         });
     const double t1 = now_s();
     if (rc == EBIC_OK) {
@@ -329,13 +381,41 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
         if (e == hipSuccess) e = hipStreamSynchronize(stream_);
         if (e != hipSuccess) rc = check_hip(e, "download");
     }
-    const double t2 = now_s();
     std::vector<int> st(n, rc);
     std::vector<std::string> msg(n, rc ? ebic_last_error() : "");
+    // which candidates' supports each top-rank list update looks at first
+    std::vector<std::vector<int32_t>> first(n);
+    const double t2a = now_s();
     if (rc == EBIC_OK)
-        pool_->run(active.size(), [&](size_t q) {
+        pool_->run(n, [&](size_t q) {
             const size_t i = lpt[q];
+            const size_t m = 2 * (size_t)std::max(active[i]->params.archive_size, 0) + 8;
+            st[i] = active[i]->job->plan(m, &first[i]);
+            if (st[i]) {
+                msg[i] = ebic_last_error();
+                first[i].clear();
+            }
+        });
+    const double t2b = now_s();
+    std::vector<size_t> first_at;
+    if (rc == EBIC_OK) {
+        rc = fetch_first_supports(active, first, &first_at);
+        if (rc) {
+            const std::string e = ebic_last_error();
+            for (size_t i = 0; i < n; i++)
+                if (st[i] == EBIC_OK) {
+                    st[i] = rc;
+                    msg[i] = e;
+                }
+        }
+    }
+    const double t2 = now_s();
+    if (rc == EBIC_OK)
+        pool_->run(n, [&](size_t q) {
+            const size_t i = lpt[q];
+            if (st[i]) return;
             (void)hipSetDevice(device_);
+            if (!first[i].empty()) active[i]->job->set_first_supports(h_first_.p + first_at[i]);
             st[i] = active[i]->job->advance();
             if (st[i]) msg[i] = ebic_last_error();
         });
@@ -358,8 +438,8 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
         std::lock_guard<std::mutex> lk(mu_);
         ticks_++;
         stage_s_ += t1 - t0;
-        device_s_ += t2 - t1;
-        host_s_ += t3 - t2;
+        device_s_ += (t2a - t1) + (t2 - t2b);
+        host_s_ += (t2b - t2a) + (t3 - t2);
     }
     active.swap(keep);
     end_jobs(ended);
