@@ -363,8 +363,8 @@ void ebic_session_free(ebic_session *s);
  * order while their device footprint (matrix, ranks, pair table when it
  * takes at most an eighth of the budget, population, outputs, archive) fits
  * in the HBM budget and a slot is free; every admitted job keeps its state
- * resident on the device. A preparer thread sets admitted jobs up (upload,
- * ranks, pair table, first population) on a stream of its own while the
+ * resident on the device. Preparer threads set admitted jobs up (upload,
+ * ranks, pair table, first population) on streams of their own while the
  * scheduler keeps ticking; a prepared job joins at the next tick. Each tick
  * scores the current populations of all active jobs in one batched launch,
  * then runs their host steps. A finished job frees its memory and slot, and
@@ -393,8 +393,8 @@ typedef struct ebic_server_metrics {
     double release_s;           /* ended jobs' frees                           */
 } ebic_server_metrics;
 
-/* Creates the server on the current device; the scheduler and preparer
- * threads use a stream each. Errors: EBIC_ERR_INVALID_ARG, EBIC_ERR_DEVICE. */
+/* Creates the server on the current device; the scheduler and each
+ * preparer thread use a stream of their own. Errors: EBIC_ERR_INVALID_ARG, EBIC_ERR_DEVICE. */
 int ebic_server_create(const ebic_server_config *cfg, ebic_server **out);
 /* Queues a job (the host matrix is copied; parameters validated as for
  * ebic_run); never waits for the GPU. *job_id identifies it. Errors:

@@ -213,8 +213,10 @@ class Job {
     // Device bytes a job of this shape holds (matrix, ranks, pair table when
     // used, population, outputs, archive).
     static size_t footprint(int32_t rows, int32_t cols, const ebic_params &p, bool pairs);
-    // Allocate, ingest the matrix, build the pair table when `pairs`.
-    int setup(const float *h_x, int32_t rows, int32_t cols, bool pairs);
+    // Allocate, ingest the matrix, build the pair table when `pairs`; with
+    // own_staging false the job is only ever staged through stage_into()
+    // and gets no staging buffers of its own.
+    int setup(const float *h_x, int32_t rows, int32_t cols, bool pairs, bool own_staging = true);
     void start();                     // step 1
     int stage(ebic_job *job);         // upload what is to be scored next
     int fetch();                      // queue the outputs' download

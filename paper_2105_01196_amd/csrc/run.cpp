@@ -28,7 +28,7 @@ size_t Job::footprint(int32_t rows, int32_t cols, const ebic_params &p, bool pai
     return b + (1 << 20);  // slack for allocation granularity
 }
 
-int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs) {
+int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs, bool own_staging) {
     R_ = rows;
     C_ = cols;
     const int32_t P = p_.population, K = p_.archive_size, kmax = p_.k_max;
@@ -45,6 +45,7 @@ int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs) {
         rc = ebic_pairs_prepare(&m_, d_pairs_.p, stream_);
         if (rc) return rc;
     }
+    if (!own_staging) return EBIC_OK;  // stage_into() only
     const int32_t nmax = std::max(P, K);
     RUN_HIP(d_off_.alloc(nmax + 1, al_, stream_));
     RUN_HIP(d_order_.alloc(nmax, al_, stream_));
@@ -93,6 +94,7 @@ void Job::pack(int32_t *off, uint16_t *cols, int32_t *order, uint64_t *asup, int
 }
 
 int Job::stage(ebic_job *job) {
+    if (!h_off_.p) return fail(EBIC_ERR_INVALID_ARG, "internal: the job has no staging buffers");
     const int32_t P = (int32_t)pop_.size();
     const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
     staged_P_ = P;

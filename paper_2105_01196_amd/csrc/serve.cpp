@@ -3,7 +3,7 @@
 // A scheduler thread owns a stream and the batch. Before each tick it admits
 // queued jobs whose device footprint fits the remaining HBM budget (arrival
 // order, so a large job is never starved by smaller ones behind it) and
-// hands them to a preparer thread, which sets them up on a second stream
+// hands them to preparer threads, which set them up on streams of their own
 // (allocation, upload, ranks, pair table, first population) while the ticks
 // go on; prepared jobs join the active set at the next tick. A tick packs
 // the population and top-rank list of every active job into one shared
@@ -24,6 +24,9 @@
 
 namespace ebic {
 namespace {
+
+// Threads (each with a stream) setting admitted jobs up beside the ticks.
+constexpr int kPreparers = 3;
 
 double now_s() {
     using namespace std::chrono;
@@ -109,7 +112,7 @@ class Server {
 
   private:
     void loop();
-    void prepare_loop();
+    void prepare_loop(hipStream_t stream);
     void tick(std::vector<std::shared_ptr<ServerJob>> &active);
     void finish_job(const std::shared_ptr<ServerJob> &j, int status, const char *err);
     void release_loop();
@@ -137,7 +140,8 @@ class Server {
     int32_t max_active_ = 64;
     bool stop_ = false;
     int device_ = 0;
-    hipStream_t stream_ = nullptr, prep_stream_ = nullptr;
+    hipStream_t stream_ = nullptr;
+    std::vector<hipStream_t> prep_streams_;  // one per preparer thread
     Batch *batch_ = nullptr;
     // One tick's inputs of all jobs (uploaded by one copy), scores and
     // counts (downloaded by one copy) and supports (left on the device); the
@@ -150,7 +154,8 @@ class Server {
     PinnedArray<uint64_t> h_first_;
     DeviceArray<uint64_t> d_first_;
     std::unique_ptr<WorkerPool> pool_;
-    std::thread thread_, prep_thread_, rel_thread_;
+    std::thread thread_, rel_thread_;
+    std::vector<std::thread> prep_threads_;
 };
 
 int Server::init(const ebic_server_config *cfg) {
@@ -160,10 +165,14 @@ int Server::init(const ebic_server_config *cfg) {
     budget_ = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : free_b / 10 * 8;
     max_active_ = (cfg && cfg->max_active > 0) ? cfg->max_active : 64;
     EBIC_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
-    EBIC_HIP(hipStreamCreateWithFlags(&prep_stream_, hipStreamNonBlocking));
+    for (int w = 0; w < kPreparers; w++) {
+        hipStream_t st = nullptr;
+        EBIC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        prep_streams_.push_back(st);
+    }
     const unsigned hw = std::thread::hardware_concurrency();
     pool_.reset(new WorkerPool((int)std::max(1u, std::min(hw ? hw : 1u, 16u))));
-    prep_thread_ = std::thread([this] { prepare_loop(); });
+    for (hipStream_t st : prep_streams_) prep_threads_.emplace_back([this, st] { prepare_loop(st); });
     rel_thread_ = std::thread([this] { release_loop(); });
     thread_ = std::thread([this] { loop(); });
     return EBIC_OK;
@@ -176,10 +185,10 @@ Server::~Server() {
     }
     cv_work_.notify_all();
     cv_prep_.notify_all();
-    // the scheduler ends once every admitted job is done, so the preparer
-    // has nothing left when it is told to stop
+    // the scheduler ends once every admitted job is done, so the preparers
+    // have nothing left when they are told to stop
     if (thread_.joinable()) thread_.join();
-    if (prep_thread_.joinable()) prep_thread_.join();
+    for (auto &t : prep_threads_) t.join();
     {
         std::lock_guard<std::mutex> lk(mu_);
         rel_quit_ = true;  // nothing ends any more; free what is left
@@ -189,7 +198,7 @@ Server::~Server() {
     pool_.reset();
     if (batch_) batch_destroy(batch_);
     if (stream_) (void)hipStreamDestroy(stream_);
-    if (prep_stream_) (void)hipStreamDestroy(prep_stream_);
+    for (hipStream_t st : prep_streams_) (void)hipStreamDestroy(st);
     for (auto &kv : jobs_) delete kv.second->result;
 }
 
@@ -502,7 +511,7 @@ bool Server::admissible() const {
     return f > budget_ || (in_use_ + f <= budget_ && n_held_ < max_active_);
 }
 
-void Server::prepare_loop() {
+void Server::prepare_loop(hipStream_t stream) {
     (void)hipSetDevice(device_);
     for (;;) {
         std::shared_ptr<ServerJob> j;
@@ -514,11 +523,11 @@ void Server::prepare_loop() {
             prep_q_.pop_front();
         }
         const double t0 = now_s();
-        j->job.reset(new Job(j->params, j->seed, prep_stream_));
+        j->job.reset(new Job(j->params, j->seed, stream));
         j->job->set_host_matrix(j->x.data());  // the job's own copy, for row directions
-        int rc = j->job->setup(j->x.data(), j->rows, j->cols, j->pairs);
+        int rc = j->job->setup(j->x.data(), j->rows, j->cols, j->pairs, false);
         if (rc == EBIC_OK) {
-            const hipError_t e = hipStreamSynchronize(prep_stream_);
+            const hipError_t e = hipStreamSynchronize(stream);
             if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
         }
         std::string err;
