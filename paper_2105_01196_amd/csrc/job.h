@@ -220,6 +220,10 @@ class Job {
     void start();                     // step 1
     int stage(ebic_job *job);         // upload what is to be scored next
     int fetch();                      // queue the outputs' download
+    // After fetch()'s download has arrived: when it held no supports, the
+    // ones the top-rank list update looks at first, gathered and downloaded
+    // (waits for the stream).
+    int fetch_first();
     // Staging through buffers shared by many jobs (one upload and one
     // download for all of them): the byte sizes of this job's slices for the
     // next stage (inputs; scores and counts; supports), then the packing of
@@ -307,14 +311,20 @@ class Job {
     DeviceArray<float> d_x_;
     DeviceArray<uint16_t> d_ranks_;
     DeviceArray<uint64_t> d_pairs_;
-    DeviceArray<int32_t> d_off_, d_order_, d_cnt_, d_aoff_, d_sel_, d_roff_, d_rows_;
-    DeviceArray<uint16_t> d_cols_, d_acols_;
-    DeviceArray<double> d_fit_;
-    DeviceArray<uint64_t> d_sup_, d_asup_;
-    PinnedArray<int32_t> h_off_, h_order_, h_cnt_, h_aoff_;
-    PinnedArray<uint16_t> h_cols_, h_acols_;
-    PinnedArray<double> h_fit_;
-    PinnedArray<uint64_t> h_sup_, h_asup_;
+    DeviceArray<int32_t> d_sel_, d_roff_, d_rows_;
+    // Own staging (stage() and fetch()): every input in one block each
+    // way, and the scores, counts and then the supports in another, so a
+    // generation takes one upload and one download; when the supports are
+    // large only the ones the top-rank list update looks at come down,
+    // gathered on the device (fetch_first()).
+    PinnedArray<uint8_t> h_in_, h_out_;
+    DeviceArray<uint8_t> d_in_, d_out_;
+    PinnedArray<WordSpan> h_spans_;
+    DeviceArray<WordSpan> d_spans_;
+    PinnedArray<uint64_t> h_first_;
+    DeviceArray<uint64_t> d_first_;
+    size_t staged_down_ = 0;  // bytes fetch() downloads for this stage
+    bool all_supports_ = true;
 
     Phase phase_ = Phase::Eval;
     int stop_ = 0;
@@ -342,6 +352,10 @@ class Job {
         size_t fit, cnt, out_bytes, sup_bytes;
     };
     Slices slices() const;
+    // The layout for P individuals with len columns in all, and K members
+    // with alen columns, W support words each.
+    static Slices layout(int32_t P, size_t len, int32_t K, size_t alen, int32_t W);
+    size_t first_count() const { return 2 * (size_t)std::max(p_.archive_size, 0) + 8; }
     void pack(int32_t *off, uint16_t *cols, int32_t *order, uint64_t *asup, int32_t *aoff,
               uint16_t *acols) const;
     TabuSet tabu_;

@@ -25,7 +25,8 @@ size_t Job::footprint(int32_t rows, int32_t cols, const ebic_params &p, bool pai
     if (pairs) b += ebic_pairs_bytes(rows, cols);
     b += nmax * (4 + 4 + 2 * (size_t)p.k_max + 8 + 4 + 8 * W) + 4;
     b += (size_t)p.archive_size * (8 * W + 4 + 2 * (size_t)p.k_max) + 4;
-    return b + (1 << 20);  // slack for allocation granularity
+    b += (2 * (size_t)p.archive_size + 8) * (8 * W + sizeof(WordSpan));  // gathered supports
+    return b + (1 << 20);  // slack for alignment and allocation granularity
 }
 
 int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs, bool own_staging) {
@@ -47,24 +48,15 @@ int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs, bool ow
     }
     if (!own_staging) return EBIC_OK;  // stage_into() only
     const int32_t nmax = std::max(P, K);
-    RUN_HIP(d_off_.alloc(nmax + 1, al_, stream_));
-    RUN_HIP(d_order_.alloc(nmax, al_, stream_));
-    RUN_HIP(d_cols_.alloc((size_t)nmax * kmax, al_, stream_));
-    RUN_HIP(d_fit_.alloc(nmax, al_, stream_));
-    RUN_HIP(d_cnt_.alloc(nmax, al_, stream_));
-    RUN_HIP(d_sup_.alloc((size_t)nmax * W_, al_, stream_));
-    RUN_HIP(d_asup_.alloc((size_t)K * W_, al_, stream_));
-    RUN_HIP(d_aoff_.alloc(K + 1, al_, stream_));
-    RUN_HIP(d_acols_.alloc((size_t)K * kmax, al_, stream_));
-    RUN_HIP(h_off_.alloc(nmax + 1));
-    RUN_HIP(h_order_.alloc(nmax));
-    RUN_HIP(h_cols_.alloc((size_t)nmax * kmax));
-    RUN_HIP(h_fit_.alloc(nmax));
-    RUN_HIP(h_cnt_.alloc(nmax));
-    RUN_HIP(h_sup_.alloc((size_t)nmax * W_));
-    RUN_HIP(h_asup_.alloc((size_t)K * W_));
-    RUN_HIP(h_aoff_.alloc(K + 1));
-    RUN_HIP(h_acols_.alloc((size_t)K * kmax));
+    const Slices most = layout(nmax, (size_t)nmax * kmax, K, (size_t)K * kmax, W_);
+    RUN_HIP(d_in_.alloc(most.in_bytes, al_, stream_));
+    RUN_HIP(d_out_.alloc(most.out_bytes + most.sup_bytes, al_, stream_));
+    RUN_HIP(d_spans_.alloc(first_count(), al_, stream_));
+    RUN_HIP(d_first_.alloc(first_count() * W_, al_, stream_));
+    RUN_HIP(h_in_.alloc(most.in_bytes));
+    RUN_HIP(h_out_.alloc(most.out_bytes + most.sup_bytes));
+    RUN_HIP(h_spans_.alloc(first_count()));
+    RUN_HIP(h_first_.alloc(first_count() * W_));
     return EBIC_OK;
 }
 
@@ -93,47 +85,23 @@ void Job::pack(int32_t *off, uint16_t *cols, int32_t *order, uint64_t *asup, int
     }
 }
 
+// Supports up to this many bytes come down whole with the scores; larger
+// ones stay on the device but for the few the top-rank list update reads.
+constexpr size_t kWholeSupportBytes = 1 << 20;
+
 int Job::stage(ebic_job *job) {
-    if (!h_off_.p) return fail(EBIC_ERR_INVALID_ARG, "internal: the job has no staging buffers");
-    const int32_t P = (int32_t)pop_.size();
-    const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
-    staged_P_ = P;
-    pack(h_off_.p, h_cols_.p, h_order_.p, h_asup_.p, h_aoff_.p, h_acols_.p);
-    const int32_t len = h_off_.p[P];
-    RUN_HIP(hipMemcpyAsync(d_off_.p, h_off_.p, sizeof(int32_t) * (P + 1), hipMemcpyHostToDevice,
-                           stream_));
-    RUN_HIP(hipMemcpyAsync(d_cols_.p, h_cols_.p, sizeof(uint16_t) * std::max(len, 1),
-                           hipMemcpyHostToDevice, stream_));
-    RUN_HIP(hipMemcpyAsync(d_order_.p, h_order_.p, sizeof(int32_t) * std::max(P, 1),
-                           hipMemcpyHostToDevice, stream_));
-    if (K > 0) {
-        RUN_HIP(hipMemcpyAsync(d_asup_.p, h_asup_.p, sizeof(uint64_t) * K * W_,
-                               hipMemcpyHostToDevice, stream_));
-        RUN_HIP(hipMemcpyAsync(d_aoff_.p, h_aoff_.p, sizeof(int32_t) * (K + 1),
-                               hipMemcpyHostToDevice, stream_));
-        RUN_HIP(hipMemcpyAsync(d_acols_.p, h_acols_.p, sizeof(uint16_t) * h_aoff_.p[K],
-                               hipMemcpyHostToDevice, stream_));
-    }
-    *job = ebic_job{};
-    job->matrix = m_;
-    job->population = ebic_population{P, (int32_t)d_cols_.n, d_off_.p, d_cols_.p, d_order_.p};
-    job->archive = ebic_archive{K, (int32_t)d_acols_.n, d_asup_.p, d_aoff_.p, d_acols_.p};
-    job->params = p_;
-    job->out = ebic_eval_out{d_fit_.p, d_cnt_.p, d_sup_.p, nullptr};
-    got_fit_ = h_fit_.p;
-    got_cnt_ = h_cnt_.p;
-    got_sup_ = h_sup_.p;
-    got_dsup_ = d_sup_.p;
-    first_sup_ = nullptr;
+    if (!h_in_.p) return fail(EBIC_ERR_INVALID_ARG, "internal: the job has no staging buffers");
+    const Slices l = slices();
+    const size_t sup = sizeof(uint64_t) * pop_.size() * W_;
+    stage_into(job, h_in_.p, d_in_.p, h_out_.p, d_out_.p, d_out_.p + l.out_bytes);
+    all_supports_ = sup <= kWholeSupportBytes;
+    staged_down_ = l.out_bytes + (all_supports_ ? sup : 0);
+    if (all_supports_) got_sup_ = reinterpret_cast<const uint64_t *>(h_out_.p + l.out_bytes);
+    RUN_HIP(hipMemcpyAsync(d_in_.p, h_in_.p, l.in_bytes, hipMemcpyHostToDevice, stream_));
     return EBIC_OK;
 }
 
-Job::Slices Job::slices() const {
-    const int32_t P = (int32_t)pop_.size();
-    const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
-    size_t len = 0, alen = 0;
-    for (const Series &q : pop_) len += q.size();
-    for (int32_t j = 0; j < K; j++) alen += archive_[j].s.size();
+Job::Slices Job::layout(int32_t P, size_t len, int32_t K, size_t alen, int32_t W) {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     Slices l{};
     size_t at = 0;
@@ -145,7 +113,7 @@ Job::Slices Job::slices() const {
     l.off = take(sizeof(int32_t) * (P + 1));
     l.cols = take(sizeof(uint16_t) * std::max<size_t>(len, 1));
     l.order = take(sizeof(int32_t) * std::max(P, 1));
-    l.asup = take(sizeof(uint64_t) * K * W_);
+    l.asup = take(sizeof(uint64_t) * K * W);
     l.aoff = take(sizeof(int32_t) * (K + 1));
     l.acols = take(sizeof(uint16_t) * std::max<size_t>(alen, 1));
     l.in_bytes = at;
@@ -153,8 +121,16 @@ Job::Slices Job::slices() const {
     l.fit = take(sizeof(double) * std::max(P, 1));
     l.cnt = take(sizeof(int32_t) * std::max(P, 1));
     l.out_bytes = at;
-    l.sup_bytes = up(sizeof(uint64_t) * std::max(P, 1) * W_);
+    l.sup_bytes = up(sizeof(uint64_t) * std::max(P, 1) * W);
     return l;
+}
+
+Job::Slices Job::slices() const {
+    const int32_t K = phase_ == Phase::Eval ? (int32_t)archive_.size() : 0;
+    size_t len = 0, alen = 0;
+    for (const Series &q : pop_) len += q.size();
+    for (int32_t j = 0; j < K; j++) alen += archive_[j].s.size();
+    return layout((int32_t)pop_.size(), len, K, alen, W_);
 }
 
 void Job::slice_bytes(size_t *in_bytes, size_t *out_bytes, size_t *sup_bytes) const {
@@ -196,14 +172,26 @@ void Job::stage_into(ebic_job *job, uint8_t *h_in, uint8_t *d_in, uint8_t *h_out
 }
 
 int Job::fetch() {
-    const int32_t P = staged_P_;
-    if (P == 0) return EBIC_OK;
-    RUN_HIP(hipMemcpyAsync(h_fit_.p, d_fit_.p, sizeof(double) * P, hipMemcpyDeviceToHost,
+    if (staged_P_ == 0) return EBIC_OK;
+    RUN_HIP(hipMemcpyAsync(h_out_.p, d_out_.p, staged_down_, hipMemcpyDeviceToHost, stream_));
+    return EBIC_OK;
+}
+
+int Job::fetch_first() {
+    if (all_supports_ || staged_P_ == 0) return EBIC_OK;
+    int rc = plan(first_count(), nullptr);
+    if (rc || first_.empty()) return rc;
+    const size_t n = first_.size();
+    for (size_t pos = 0; pos < n; pos++)
+        h_spans_.p[pos] = WordSpan{got_dsup_ + (size_t)first_[pos] * W_, (uint64_t)(pos * W_), W_};
+    RUN_HIP(hipMemcpyAsync(d_spans_.p, h_spans_.p, sizeof(WordSpan) * n, hipMemcpyHostToDevice,
                            stream_));
-    RUN_HIP(hipMemcpyAsync(h_cnt_.p, d_cnt_.p, sizeof(int32_t) * P, hipMemcpyDeviceToHost,
-                           stream_));
-    RUN_HIP(hipMemcpyAsync(h_sup_.p, d_sup_.p, sizeof(uint64_t) * P * W_, hipMemcpyDeviceToHost,
-                           stream_));
+    rc = launch_gather_spans(d_spans_.p, (int32_t)n, d_first_.p, stream_);
+    if (rc) return rc;
+    RUN_HIP(hipMemcpyAsync(h_first_.p, d_first_.p, sizeof(uint64_t) * n * W_,
+                           hipMemcpyDeviceToHost, stream_));
+    RUN_HIP(hipStreamSynchronize(stream_));
+    first_sup_ = h_first_.p;
     return EBIC_OK;
 }
 
@@ -838,6 +826,7 @@ int session_step(Session *s, int32_t steps, int32_t *done) {
             hipError_t e = hipStreamSynchronize(s->stream);
             if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
         }
+        if (rc == EBIC_OK) rc = job.fetch_first();
         if (rc == EBIC_OK) rc = job.advance();
     }
     if (done) *done = job.done() ? 1 : 0;
