@@ -364,7 +364,6 @@ class Job {
     std::vector<double> fitness_;
     std::vector<int32_t> count_;
     std::vector<int32_t> use_;
-    Series sorted_;  // scratch: the columns of the series being mutated, sorted
     std::unique_ptr<ResultImpl> res_{new ResultImpl()};
 };
 

@@ -72,9 +72,13 @@ void Job::pack(int32_t *off, uint16_t *cols, int32_t *order, uint64_t *asup, int
         std::copy(pop[i].begin(), pop[i].end(), cols + off[i]);
         off[i + 1] = off[i] + (int32_t)pop[i].size();
     }
-    std::iota(order, order + P, 0);
-    std::stable_sort(order, order + P,
-                     [&](int32_t a, int32_t b) { return pop[a].size() > pop[b].size(); });
+    // longest first, ties by index: a counting sort over the lengths
+    size_t kmax = 0;
+    for (const Series &q : pop) kmax = std::max(kmax, q.size());
+    std::vector<int32_t> start(kmax + 2, 0);
+    for (const Series &q : pop) start[kmax - q.size() + 1]++;
+    for (size_t b = 1; b <= kmax + 1; b++) start[b] += start[b - 1];
+    for (int32_t i = 0; i < P; i++) order[start[kmax - pop[i].size()]++] = i;
     if (K == 0) return;
     aoff[0] = 0;
     for (int32_t j = 0; j < K; j++) {
@@ -298,16 +302,18 @@ int Job::tournament(const std::vector<double> &key, int n) {
 }
 
 int Job::unused_column(const Series &s) {
-    // the pick-th (from 0) column outside s in ascending order: every column
-    // of s at or below the running answer pushes it one further
-    int x = rng_.below_int((int64_t)C_ - (int64_t)s.size());
-    sorted_.assign(s.begin(), s.end());
-    std::sort(sorted_.begin(), sorted_.end());
-    for (uint16_t c : sorted_) {
-        if (c > x) break;
-        x++;
+    // The pick-th (from 0) column outside s in ascending order is the least
+    // x with x = pick + #{c in s : c <= x}; iterating that map from x = pick
+    // climbs to it (the map is monotone and the answer is its least fixed
+    // point), usually in two or three passes over s.
+    const int pick = rng_.below_int((int64_t)C_ - (int64_t)s.size());
+    int x = pick;
+    for (;;) {
+        int below = 0;
+        for (uint16_t c : s) below += c <= x;
+        if (pick + below == x) return x;
+        x = pick + below;
     }
-    return x;
 }
 
 Series Job::mutate(const std::vector<Series> &pop, const std::vector<double> &key) {
