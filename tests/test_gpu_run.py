@@ -108,6 +108,17 @@ def test_batched_workload_lockstep_few_generations(E):
     _lockstep(E, case.X, kw, synth.GA_SEED + 2)
 
 
+def test_many_clashing_candidates_lockstep(E):
+    """With no overlap allowed and 12 columns the top-rank list never fills,
+    so every generation's update walks all its candidates: far past the
+    first ones whose supports are gathered (the supports, 1.5 MB, are too
+    large to download whole), the rest fetched one at a time."""
+    X = synth.random_matrix(20000, 12, seed=11)
+    kw = _params(negative_trends=1, k_min=3, k_max=6, population=600, generations=3,
+                 overlap_permille=0, n_out=20)
+    _lockstep(E, X, kw, 13)
+
+
 def test_stops(E):
     X = synth.random_matrix(8, 4, seed=2)
     got = _lockstep(E, X, _params(k_min=2, k_max=4, population=10, generations=1000,

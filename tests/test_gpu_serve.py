@@ -77,6 +77,21 @@ def test_alone_equals_mix(E):
         np.testing.assert_array_equal(x.cols, y.cols)
 
 
+def test_many_clashing_candidates_in_the_mix(E):
+    """Top-rank list updates that walk past the candidates whose supports
+    a tick gathers (no overlap allowed, 12 columns) give the same result as
+    the job alone."""
+    X = synth.random_matrix(20000, 12, seed=11)
+    kw = _kw(20000, 12, 600, 3, k_min=3, k_max=6, overlap_permille=0, n_out=20)
+    jobs = [(X, kw, 13)] + _mix()[:2]
+    alone = [E.ebic_run(x, E.make_params(**k), sd) for x, k, sd in jobs]
+    srv = E.Server()
+    ids = [srv.submit(x, E.make_params(**k), sd) for x, k, sd in jobs]
+    for a, i in zip(alone, ids):
+        _same(a, srv.wait(i))
+    srv.close()
+
+
 def test_small_budget_queues(E):
     jobs = _mix()[:4]
     alone = [E.ebic_run(X, E.make_params(**kw), seed) for X, kw, seed in jobs]
