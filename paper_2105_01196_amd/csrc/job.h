@@ -29,16 +29,41 @@ class SplitMix64 {
     // Uniform in [0, n): draws below 2^64 mod n are rejected so that the
     // accepted range holds a whole number of periods of n.
     uint64_t below(uint64_t n) {
-        const uint64_t reject = (0 - n) % n;
+        const Divisor &d = divisor(n);
         for (;;) {
             const uint64_t x = next();
-            if (x >= reject) return x % n;
+            if (x >= d.reject) return d.mod(x);
         }
     }
     int below_int(int64_t n) { return (int)below((uint64_t)n); }
 
   private:
+    // x mod n without a division: with m = floor((2^64 - 1) / n), the
+    // quotient estimate floor(x m / 2^64) is the true quotient or one less
+    // (m n > 2^64 - 1 - n, so x / n - x m / 2^64 < x / 2^64 < 1), so the
+    // remainder needs at most one correction.
+    struct Divisor {
+        uint64_t n = 0, m = 0, reject = 0;
+        uint64_t mod(uint64_t x) const {
+            const uint64_t q = (uint64_t)(((unsigned __int128)x * m) >> 64);
+            uint64_t r = x - q * n;
+            if (r >= n) r -= n;
+            return r;
+        }
+    };
+    // The few moduli a job draws with (the population, the operator count,
+    // series lengths) repeat; each is set up once per slot of a small cache.
+    const Divisor &divisor(uint64_t n) {
+        Divisor &d = cache_[n & 7];
+        if (d.n != n) {
+            d.n = n;
+            d.m = ~0ULL / n;
+            d.reject = (0 - n) % n;
+        }
+        return d;
+    }
     uint64_t state_;
+    Divisor cache_[8];
 };
 
 using Series = std::vector<uint16_t>;
@@ -280,7 +305,8 @@ class Job {
     int finish();
     int tournament(const std::vector<double> &key, int n);
     int unused_column(const Series &s);
-    Series mutate(const std::vector<Series> &pop, const std::vector<double> &key);
+    // Writes a mutant of a tournament winner into child (its storage reused).
+    void mutate(const std::vector<Series> &pop, const std::vector<double> &key, Series &child);
     double size_score(int32_t n, int k) const {
         return (n >= p_.min_rows && k >= p_.k_score_min) ? std::ldexp((double)n, k) : 0.0;
     }
@@ -361,6 +387,7 @@ class Job {
     TabuSet tabu_;
     int64_t tabu_hits_ = 0;
     std::vector<Member> archive_;
+    std::vector<Series> spare_;  // storage of an earlier population, for children
     std::vector<double> fitness_;
     std::vector<int32_t> count_;
     std::vector<int32_t> use_;

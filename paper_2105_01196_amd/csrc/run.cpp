@@ -316,7 +316,7 @@ int Job::unused_column(const Series &s) {
     }
 }
 
-Series Job::mutate(const std::vector<Series> &pop, const std::vector<double> &key) {
+void Job::mutate(const std::vector<Series> &pop, const std::vector<double> &key, Series &child) {
     const int n = (int)pop.size();
     const Series &par = pop[tournament(key, n)];
     const int k = (int)par.size();
@@ -329,7 +329,7 @@ Series Job::mutate(const std::vector<Series> &pop, const std::vector<double> &ke
         if (op == SUBST && !(k < C_)) continue;
         break;
     }
-    Series child = par;
+    child.assign(par.begin(), par.end());
     switch (op) {
         case INSERT: {
             const int pos = rng_.below_int(k + 1);
@@ -361,7 +361,6 @@ Series Job::mutate(const std::vector<Series> &pop, const std::vector<double> &ke
                     child.push_back(other[q]);
         }
     }
-    return child;
 }
 
 void Job::start() {
@@ -461,12 +460,17 @@ void Job::next_population() {
     }
     // steps 5-6: replenish with mutants; tabu hits end the run
     while ((int32_t)next.size() < P && !stop_) {
+        Series child;  // storage from an earlier population when there is some
+        if (!spare_.empty()) {
+            child.swap(spare_.back());
+            spare_.pop_back();
+        }
         for (int attempts = 0;; attempts++) {
             if (attempts == p_.max_attempts) {
                 stop_ = EBIC_STOP_EXHAUSTED;
                 break;
             }
-            Series child = mutate(pop_, key);
+            mutate(pop_, key, child);
             if ((int)child.size() < p_.k_min || (int)child.size() > p_.k_max) continue;
             if (!tabu_.insert(child, neg_)) {
                 if (++tabu_hits_ >= p_.max_tabu_hits) {
@@ -479,7 +483,9 @@ void Job::next_population() {
             break;
         }
     }
-    if (!stop_) pop_.swap(next);  // step 6: a stop ends the run before scoring
+    if (stop_) return;  // step 6: a stop ends the run before scoring
+    pop_.swap(next);
+    for (Series &q : next) spare_.push_back(std::move(q));
 }
 
 int Job::finish() {
