@@ -179,13 +179,18 @@ int ebic_population_upload(const int32_t *h_offsets, const uint16_t *h_cols, int
 int ebic_evaluate(const ebic_matrix *m, const ebic_population *pop, const ebic_archive *arch,
                   const ebic_params *p, const ebic_eval_out *out, void *stream);
 
-/* Bytes of the pair-comparison table: C(C-1)/2 pairs x rows_pad/8. */
+/* Bytes of the pair-comparison table: C(C-1)/2 pairs x
+ * ebic_pairs_words(rows) x 8 (0 when rows < 1 or cols < 2). */
 size_t ebic_pairs_bytes(int32_t rows, int32_t cols);
+/* Words per pair in the table: rows_pad/64 rounded up to a multiple of 16,
+ * so every pair's bitmap starts on a 128-byte line (0 when rows < 1). */
+int32_t ebic_pairs_words(int32_t rows);
 
 /* Pair-comparison table (used by the batched evaluator). For every
- * unordered column pair lo < hi, the support-style bitmap (W words) of the
- * rows in which lo precedes hi, at d_pairs[pair * W + word] with
- * pair = lo*C - lo*(lo+1)/2 + (hi-lo-1). A series step c_j -> c_{j+1} keeps
+ * unordered column pair lo < hi, the support-style bitmap (W = rows_pad/64
+ * words) of the rows in which lo precedes hi, at d_pairs[pair * S + word]
+ * with S = ebic_pairs_words(rows) and pair = lo*C - lo*(lo+1)/2 + (hi-lo-1);
+ * words W..S-1 of a pair are not written. A series step c_j -> c_{j+1} keeps
  * the increasing trend (Sec. 2.3) exactly in the rows of its pair's bitmap,
  * inverted when c_j > c_{j+1}, so the trend test reduces to bitwise work.
  * d_pairs (ebic_pairs_bytes bytes) is caller-owned; sets m->d_pairs.

@@ -33,6 +33,7 @@ struct DevJob {
     const uint16_t *ranks;
     const uint64_t *pairs;
     int32_t rows, cols, rows_pad, w32, w64;
+    int32_t pstride;  // words per pair in the pair table
     int32_t mode;     // 1 = pair table, 0 = gather
     int32_t nchunks;  // 4096-row chunks per individual
     int32_t cpi;      // chunks per item (one wave walks them WPL at a time)
@@ -133,7 +134,7 @@ __device__ __forceinline__ void add_sticky(uint64_t *C, const uint64_t *S, uint6
 // once; after each group the wave stops once every row has failed both
 // trends. Writes the fit words to fit[].
 template <int P, bool NEG, int KB, int WPL>
-__device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, int64_t w64,
+__device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, int64_t pstride,
                                             int wlim, const int32_t *s_pd, int k, int t, int w,
                                             uint64_t *fit) {
     constexpr int NP = P > 0 ? P : 1;
@@ -163,7 +164,7 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
             const bool en = j0 + q < k;  // uniform
             const int idx = en ? j0 + q : k - 1;
             const int pd = __builtin_amdgcn_readfirstlane(s_pd[idx]);
-            const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * w64;
+            const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * pstride;
             inv[q] = pd < 0 ? ~0ull : 0ull;
 #pragma unroll
             for (int v = 0; v < WPL; v++)
@@ -221,7 +222,7 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
             for (int v = 0; v < WPL; v++) x[v] = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
-                const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * w64;
+                const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * pstride;
 #pragma unroll
                 for (int v = 0; v < WPL; v++) {
                     const uint64_t bits = active[v] ? vec[w + kWave * v] : 0ull;
@@ -267,25 +268,25 @@ struct PairLimit {
 };
 
 template <int PP, int MAXP, bool NEG, int KB, int WPL>
-__device__ __forceinline__ void pairs_width(int P, const uint64_t *pairs, int64_t w64, int wlim,
+__device__ __forceinline__ void pairs_width(int P, const uint64_t *pairs, int64_t pstride, int wlim,
                                             const int32_t *s_pd, int k, int t, int w,
                                             uint64_t *fit) {
     if constexpr (PP == MAXP) {
-        pairs_count<PP, NEG, KB, WPL>(pairs, w64, wlim, s_pd, k, t, w, fit);
+        pairs_count<PP, NEG, KB, WPL>(pairs, pstride, wlim, s_pd, k, t, w, fit);
     } else {
-        if (P == PP) return pairs_count<PP, NEG, KB, WPL>(pairs, w64, wlim, s_pd, k, t, w, fit);
-        pairs_width<PP + 1, MAXP, NEG, KB, WPL>(P, pairs, w64, wlim, s_pd, k, t, w, fit);
+        if (P == PP) return pairs_count<PP, NEG, KB, WPL>(pairs, pstride, wlim, s_pd, k, t, w, fit);
+        pairs_width<PP + 1, MAXP, NEG, KB, WPL>(P, pairs, pstride, wlim, s_pd, k, t, w, fit);
     }
 }
 
 // Counter width for tolerance t <= PairLimit<KB, WPL>::T: the least P with
 // 2^P >= t+1.
 template <bool NEG, int KB, int WPL>
-__device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, int64_t w64, int wlim,
+__device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, int64_t pstride, int wlim,
                                                const int32_t *s_pd, int k, int t, int w,
                                                uint64_t *fit) {
     const int P = t == 0 ? 0 : 32 - __builtin_clz((unsigned)t);
-    pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL>(P, pairs, w64, wlim, s_pd, k, t, w, fit);
+    pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL>(P, pairs, pstride, wlim, s_pd, k, t, w, fit);
 }
 
 // One workgroup per individual, one wave per item (a few 4096-row chunks of
@@ -435,9 +436,9 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                     const int wlim = J.w64 < ch1 * 64 ? J.w64 : ch1 * 64;
                     uint64_t fit[WPL];
                     if (neg)
-                        pairs_dispatch<true, KB, WPL>(J.pairs, J.w64, wlim, s_pd, k, t, w, fit);
+                        pairs_dispatch<true, KB, WPL>(J.pairs, J.pstride, wlim, s_pd, k, t, w, fit);
                     else
-                        pairs_dispatch<false, KB, WPL>(J.pairs, J.w64, wlim, s_pd, k, t, w, fit);
+                        pairs_dispatch<false, KB, WPL>(J.pairs, J.pstride, wlim, s_pd, k, t, w, fit);
 #pragma unroll
                     for (int v = 0; v < WPL; v++) {
                         const int wv = w + kWave * v, r0 = wv * 64;
@@ -680,6 +681,7 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
     d.rows_pad = j.matrix.rows_pad;
     d.w32 = j.matrix.rows_pad / 32;
     d.w64 = j.matrix.rows_pad / 64;
+    d.pstride = pair_words(j.matrix.rows_pad);
     d.mode = (j.matrix.d_pairs && !(flags & EBIC_BATCH_GATHER)) ? 1 : 0;
     d.nchunks = (j.matrix.rows_pad + kItemRows - 1) / kItemRows;
     d.pop_size = j.population.size;

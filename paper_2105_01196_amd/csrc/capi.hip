@@ -194,7 +194,12 @@ int ebic_evaluate(const ebic_matrix *m, const ebic_population *pop, const ebic_a
 
 size_t ebic_pairs_bytes(int32_t rows, int32_t cols) {
     if (rows < 1 || cols < 2) return 0;
-    return (size_t)cols * (cols - 1) / 2 * (rows_padded(rows) / 8);
+    return (size_t)cols * (cols - 1) / 2 * pair_words(rows_padded(rows)) * sizeof(uint64_t);
+}
+
+int32_t ebic_pairs_words(int32_t rows) {
+    if (rows < 1) return 0;
+    return pair_words(rows_padded(rows));
 }
 
 int ebic_pairs_prepare(ebic_matrix *m, uint64_t *d_pairs, void *stream) {

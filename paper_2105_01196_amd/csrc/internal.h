@@ -27,6 +27,9 @@ int check_hip(hipError_t e, const char *what);
     } while (0)
 
 inline int32_t rows_padded(int32_t rows) { return (rows + 63) / 64 * 64; }
+// Words per pair in the pair table: the rows' 64-bit words rounded up to 16,
+// so every pair's bitmap starts on a 128-byte line.
+inline int32_t pair_words(int32_t rows_pad) { return (rows_pad / 64 + 15) / 16 * 16; }
 
 inline int tolerance(int k, int approx_permille) {
     return (int)(((int64_t)(k - 1) * (1000 - approx_permille)) / 1000);

@@ -131,6 +131,7 @@ _SIGNATURES = {
                                      ctypes.POINTER(ebic_eval_out), _vp]),
     "ebic_support_rows": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "ebic_pairs_bytes": (ctypes.c_size_t, [_i32, _i32]),
+    "ebic_pairs_words": (_i32, [_i32]),
     "ebic_pairs_prepare": (ctypes.c_int, [ctypes.POINTER(ebic_matrix), _vp, _vp]),
     "ebic_batch_create": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _i32,
                                          ctypes.POINTER(_vp)]),
@@ -414,6 +415,10 @@ def ebic_evaluate(m: Matrix, pop: Population, archive: Optional[Archive] = None,
 
 def ebic_pairs_bytes(rows: int, cols: int) -> int:
     return int(lib().ebic_pairs_bytes(rows, cols))
+
+
+def ebic_pairs_words(rows: int) -> int:
+    return int(lib().ebic_pairs_words(rows))
 
 
 def ebic_pairs_prepare(m: Matrix, stream=None) -> Matrix:

@@ -44,6 +44,11 @@ def test_host_only_calls():
     assert ebic.ebic_version() == 100
     assert ebic.ebic_matrix_bytes(100, 20) == 20 * 128 * 2
     assert ebic.ebic_matrix_bytes(0, 20) == 0
+    # pair rows: 64-bit row words rounded up to 16 (128-byte lines)
+    assert [ebic.ebic_pairs_words(r) for r in (0, 1, 64, 1024, 1025, 10000)] == \
+        [0, 16, 16, 16, 32, 160]
+    assert ebic.ebic_pairs_bytes(10000, 500) == 500 * 499 // 2 * 160 * 8
+    assert ebic.ebic_pairs_bytes(100, 1) == 0
 
 
 def test_population_validation_rejects_on_host():

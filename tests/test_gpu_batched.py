@@ -84,12 +84,15 @@ def test_pair_table_bits(E):
         ev = oracle.evaluate(X, [list(p) for p in pairs],
                              params=oracle.make_params(approx_permille=1000, negative_trends=0,
                                                        min_rows=1, k_score_min=2))
-        table = m.pairs.cpu().numpy().view(np.uint64).reshape(len(pairs), m.words)
+        S = E.ebic_pairs_words(R)
+        assert S % 16 == 0 and m.words <= S < m.words + 16
+        table = m.pairs.cpu().numpy().view(np.uint64).reshape(len(pairs), S)[:, :m.words]
+        table = np.ascontiguousarray(table)
         np.testing.assert_array_equal(E.support_to_flags(table, R), ev.support)
         bits = np.unpackbits(table.view(np.uint8).reshape(len(pairs), -1), axis=1,
                              bitorder="little")
         assert not bits[:, R:].any()
-        assert E.ebic_pairs_bytes(R, C) == len(pairs) * m.words * 8
+        assert E.ebic_pairs_bytes(R, C) == len(pairs) * S * 8
 
 
 @pytest.mark.parametrize("gather", [False, True])
