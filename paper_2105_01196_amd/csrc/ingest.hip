@@ -14,6 +14,8 @@
 namespace ebic {
 namespace {
 
+constexpr int32_t kXcds = 8;  // accelerator complex dies, each with its own L2
+
 // Sets *flag when any of the n values is NaN or infinite.
 __global__ void __launch_bounds__(256) check_finite_kernel(const float *__restrict__ x, size_t n,
                                                            int *flag) {
@@ -24,27 +26,60 @@ __global__ void __launch_bounds__(256) check_finite_kernel(const float *__restri
     if (__ballot(bad) != 0 && (threadIdx.x % kWave) == 0) atomicOr(flag, 1);
 }
 
-// One workgroup per row: stage the row in LDS, then each thread ranks its
-// columns by counting the cells with a smaller value. Padding rows
-// (r >= rows) get rank 0; the evaluators mask them out.
+// One workgroup per row. The row's values go to LDS, padded to a power of
+// two with +inf, and are sorted there (bitonic network: every stage
+// compares n/2 disjoint pairs, one per thread step, then a barrier); a
+// cell's rank, the number of cells with a smaller value, is then the lower
+// bound of its value in the sorted row (binary search). Equal values, and
+// -0 and +0, get the same rank. Padding rows (r >= rows) get rank 0; the
+// evaluators mask them out. Non-finite input is rejected by the caller
+// after the flag check, so its ranks are never used.
 __global__ void __launch_bounds__(256) rank_rows_kernel(const float *__restrict__ x, int32_t rows,
-                                                        int32_t cols, int32_t rows_pad,
+                                                        int32_t cols, int32_t rows_pad, int32_t n,
                                                         uint16_t *__restrict__ ranks) {
-    extern __shared__ float s_row[];
-    const int32_t r = blockIdx.x;
+    extern __shared__ float s_sorted[];
+    // Workgroups are dealt to the 8 XCDs in turn and each XCD has its own
+    // L2: give XCD x the contiguous rows x * rows_pad/8 .. so that the 2-byte
+    // ranks of neighbouring rows merge into whole lines in one L2 before
+    // they are written back (rows_pad is a multiple of 64).
+    const int32_t per_xcd = rows_pad / kXcds;
+    const int32_t r = (int32_t)(blockIdx.x % kXcds) * per_xcd + (int32_t)(blockIdx.x / kXcds);
     if (r >= rows) {
         for (int32_t c = threadIdx.x; c < cols; c += blockDim.x)
             ranks[(size_t)c * rows_pad + r] = 0;
         return;
     }
     const float *xr = x + (size_t)r * cols;
-    for (int32_t c = threadIdx.x; c < cols; c += blockDim.x) s_row[c] = xr[c];
+    for (int32_t c = threadIdx.x; c < n; c += blockDim.x)
+        s_sorted[c] = c < cols ? xr[c] : __builtin_inff();
     __syncthreads();
+    for (int32_t k = 2; k <= n; k <<= 1) {
+        for (int32_t lj = __builtin_ctz((uint32_t)k) - 1; lj >= 0; lj--) {
+            const int32_t j = 1 << lj;
+            for (int32_t q = threadIdx.x; q < n / 2; q += blockDim.x) {
+                // lower index of the pair: q with a zero bit inserted at bit lj
+                const int32_t i = ((q >> lj) << (lj + 1)) | (q & (j - 1));
+                const float a = s_sorted[i], b = s_sorted[i + j];
+                const bool up = (i & k) == 0;  // this run ascends
+                if ((b < a) == up) {
+                    s_sorted[i] = b;
+                    s_sorted[i + j] = a;
+                }
+            }
+            __syncthreads();
+        }
+    }
     for (int32_t c = threadIdx.x; c < cols; c += blockDim.x) {
-        const float v = s_row[c];
-        int32_t rank = 0;
-        for (int32_t d = 0; d < cols; d++) rank += s_row[d] < v;
-        ranks[(size_t)c * rows_pad + r] = (uint16_t)rank;
+        const float v = xr[c];
+        int32_t lo = 0, hi = n;  // first index whose value is not below v
+        while (lo < hi) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (s_sorted[mid] < v)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        ranks[(size_t)c * rows_pad + r] = (uint16_t)lo;
     }
 }
 
@@ -60,8 +95,10 @@ int launch_prepare(const float *x, int32_t rows, int32_t cols, uint16_t *ranks, 
     if (blocks > 4096) blocks = 4096;
     check_finite_kernel<<<blocks, 256, 0, stream>>>(x, n, flag);
     const int32_t rows_pad = rows_padded(rows);
-    rank_rows_kernel<<<rows_pad, 256, (size_t)cols * sizeof(float), stream>>>(x, rows, cols,
-                                                                             rows_pad, ranks);
+    int32_t width = 2;  // the row padded to a power of two
+    while (width < cols) width <<= 1;  // at most EBIC_MAX_COLS = 16,384: 64 KB of LDS
+    rank_rows_kernel<<<rows_pad, 256, (size_t)width * sizeof(float), stream>>>(
+        x, rows, cols, rows_pad, width, ranks);
     EBIC_HIP(hipGetLastError());
     return EBIC_OK;
 }
