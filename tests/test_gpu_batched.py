@@ -125,6 +125,22 @@ def test_batched_workload_with_archive(E, gather):
          gather=gather, order=True)
 
 
+def test_widest_matrix_with_long_archive(E):
+    """EBIC_MAX_COLS columns (gather form; a pair table would not fit) and
+    an archive whose members hold 10,240 columns in all, past what the
+    kernel keeps in LDS."""
+    R, C = 70, 16384
+    X = synth.tie_matrix(R, C, levels=C // 4, seed=C)
+    rng = np.random.default_rng(7)
+    seqs = [list(rng.permutation(C)[:int(rng.integers(2, 40))]) for _ in range(60)] + \
+        [list(rng.permutation(C)[:512]) for _ in range(2)]
+    arch_series = [list(rng.permutation(C)[:512]) for _ in range(20)]
+    kw = _kw(approx_permille=600, negative_trends=1, min_rows=1)
+    arch_flags = oracle.evaluate(X, arch_series, params=oracle.make_params(**kw),
+                                 nthreads=NCPU).support
+    _run(E, X, seqs, kw, arch_flags=arch_flags, arch_series=arch_series, gather=True)
+
+
 def test_large_workload_sampled(E):
     case = synth.workload_matrix(3)
     seqs = synth.workload_population(3, case)

@@ -145,6 +145,26 @@ def test_ragged_shapes(E, R, C):
                                    k_score_min=2))
 
 
+@pytest.mark.parametrize("R,C", [(70, 16384), (129, 1025)])
+def test_widest_rows(E, R, C):
+    """Up to the widest matrix (EBIC_MAX_COLS columns): the ranks are the
+    min-ranks (cells of the row strictly smaller, ties and signed zeros
+    sharing one), and evaluation agrees with the oracle."""
+    X = synth.tie_matrix(R, C, levels=C // 4, seed=C)
+    x = torch.from_numpy(X).cuda()
+    m = E.ebic_matrix_prepare(x)
+    torch.cuda.synchronize()
+    ranks = m.ranks.cpu().numpy().view(np.uint16).reshape(C, -1)[:, :R].T
+    srt = np.sort(X, axis=1)
+    want = np.stack([np.searchsorted(srt[r], X[r], side="left") for r in range(R)])
+    np.testing.assert_array_equal(ranks, want)
+    assert not m.ranks.cpu().numpy().view(np.uint16).reshape(C, -1)[:, R:].any()
+    rng = np.random.default_rng(C)
+    seqs = [list(rng.permutation(C)[:int(rng.integers(2, 40))]) for _ in range(60)] + \
+        [list(rng.permutation(C)[:512]) for _ in range(2)]
+    _check(E, X, seqs, _params(approx_permille=800, negative_trends=1, min_rows=1))
+
+
 def test_longest_series(E):
     """k = 512 (the maximum), several tolerances."""
     X = synth.random_matrix(300, 600, seed=4)
