@@ -388,6 +388,7 @@ class Job {
     int64_t tabu_hits_ = 0;
     std::vector<Member> archive_;
     std::vector<Series> spare_;  // storage of an earlier population, for children
+    std::vector<uint8_t> in_;    // scratch: a mark per column, all clear between uses
     std::vector<double> fitness_;
     std::vector<int32_t> count_;
     std::vector<int32_t> use_;

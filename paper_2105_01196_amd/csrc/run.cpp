@@ -356,9 +356,13 @@ void Job::mutate(const std::vector<Series> &pop, const std::vector<double> &key,
             const int a = 1 + rng_.below_int(k - 1);
             const int b = 1 + rng_.below_int((int)other.size() - 1);
             child.assign(par.begin(), par.begin() + a);
+            // the second parent's tail, less the columns already taken from
+            // the first (marked in a per-column scratch array, then cleared)
+            if (in_.size() != (size_t)C_) in_.assign(C_, 0);
+            for (int q = 0; q < a; q++) in_[child[q]] = 1;
             for (int q = b; q < (int)other.size(); q++)
-                if (std::find(child.begin(), child.begin() + a, other[q]) == child.begin() + a)
-                    child.push_back(other[q]);
+                if (!in_[other[q]]) child.push_back(other[q]);
+            for (int q = 0; q < a; q++) in_[child[q]] = 0;
         }
     }
 }
