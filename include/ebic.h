@@ -106,6 +106,10 @@ typedef struct ebic_matrix {
                                   (equal values share it), 0..cols-1              */
     int32_t rows, cols, rows_pad;
     const uint64_t *d_pairs;   /* optional pair table (ebic_pairs_prepare) or NULL */
+    const uint64_t *d_pairs_strict; /* optional strict pair table
+                                  (ebic_pairs_strict_prepare) or NULL: with d_pairs
+                                  it lets the strict and loose tie rules take the
+                                  pair form too                                   */
 } ebic_matrix;
 
 /* A population in compressed (CSR) form, as the paper sends it to the GPU
@@ -196,6 +200,16 @@ int32_t ebic_pairs_words(int32_t rows);
  * d_pairs (ebic_pairs_bytes bytes) is caller-owned; sets m->d_pairs.
  * Asynchronous. EBIC_ERR_INVALID_ARG for a NULL or unprepared matrix. */
 int ebic_pairs_prepare(ebic_matrix *m, uint64_t *d_pairs, void *stream);
+/* Strict pair table: as ebic_pairs_prepare (same layout and size), with the
+ * rows in which lo's value is strictly smaller than hi's. A tie is then
+ * neither bit's, so the two tables tell the three outcomes of a compare
+ * apart: a step keeps the increasing trend under the strict rule (ties
+ * break both trends) exactly in the strict table's rows, under the loose
+ * rule (ties keep both) in the other's, inverted for a step against the
+ * column order as above. d_pairs_strict (ebic_pairs_bytes bytes) is
+ * caller-owned; sets m->d_pairs_strict. Asynchronous. EBIC_ERR_INVALID_ARG
+ * for a NULL or unprepared matrix. */
+int ebic_pairs_strict_prepare(ebic_matrix *m, uint64_t *d_pairs_strict, void *stream);
 
 /* One evaluation job of a batch: a matrix, a population, the archive it is
  * penalised against, the parameters and the outputs (as for ebic_evaluate;

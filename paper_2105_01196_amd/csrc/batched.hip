@@ -32,6 +32,7 @@ namespace ebic {
 struct DevJob {
     const uint16_t *ranks;
     const uint64_t *pairs;
+    const uint64_t *pairs_strict;  // strict pair table or NULL
     int32_t rows, cols, rows_pad, w32, w64;
     int32_t pstride;  // words per pair in the pair table
     int32_t mode;     // 1 = pair table, 0 = gather
@@ -133,10 +134,11 @@ __device__ __forceinline__ void add_sticky(uint64_t *C, const uint64_t *S, uint6
 // together, summed into a small partial count and added to the counters
 // once; after each group the wave stops once every row has failed both
 // trends. Writes the fit words to fit[].
-template <int P, bool NEG, int KB, int WPL>
-__device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, int64_t pstride,
-                                            int wlim, const int32_t *s_pd, int k, int t, int w,
-                                            uint64_t *fit) {
+template <int P, bool NEG, int KB, int WPL, bool TWO>
+__device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs,
+                                            const uint64_t *__restrict__ strict, bool loose,
+                                            int64_t pstride, int wlim, const int32_t *s_pd, int k,
+                                            int t, int w, uint64_t *fit) {
     constexpr int NP = P > 0 ? P : 1;
     constexpr int B = PartialSum<KB>::B;
     uint32_t start = __builtin_amdgcn_readfirstlane((1u << P) - (uint32_t)(t + 1));
@@ -153,6 +155,7 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
         dov[v] = uov[v] = 0;
     }
 #if EBIC_PIPE
+    static_assert(!TWO, "the pipelined loop reads the one-bit table only");
     // Software-pipelined: the next group's loads are issued before this
     // group's bits are used, so two groups are in flight while the exit
     // check still follows every group. A loaded word is kept raw with its
@@ -217,23 +220,37 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs, 
         uint64_t up[WPL][KB], dn[WPL][KB];
 #pragma unroll
         for (int q = 0; q < KB; q++) {
-            uint64_t x[WPL];
+            // a step's rows against the decreasing trend (u) and against the
+            // increasing one (d)
+            uint64_t u[WPL], d[WPL];
 #pragma unroll
-            for (int v = 0; v < WPL; v++) x[v] = 0;
+            for (int v = 0; v < WPL; v++) u[v] = d[v] = 0;
             if (q < n) {
                 const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
-                const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * pstride;
+                const int64_t at = (int64_t)(pd & 0x7fffffff) * pstride;
+                const auto *vec = gmem(pairs) + at;
 #pragma unroll
                 for (int v = 0; v < WPL; v++) {
-                    const uint64_t bits = active[v] ? vec[w + kWave * v] : 0ull;
-                    x[v] = pd < 0 ? ~bits : bits;  // 1 = up-step in this row
+                    const uint64_t le = active[v] ? vec[w + kWave * v] : 0ull;
+                    if constexpr (TWO) {
+                        // le: lo at or below hi, lt: strictly below. Strict
+                        // rule, step lo -> hi: ups le, downs ~lt; loose: ups
+                        // lt, downs ~le; a step hi -> lo swaps the roles.
+                        const uint64_t lt = active[v] ? gmem(strict)[at + w + kWave * v] : 0ull;
+                        const uint64_t a = loose ? lt : le, b = loose ? le : lt;
+                        u[v] = pd < 0 ? ~b : a;
+                        d[v] = pd < 0 ? a : ~b;
+                    } else {
+                        u[v] = pd < 0 ? ~le : le;  // 1 = up-step in this row
+                        d[v] = ~u[v];
+                    }
                 }
             }
             const uint64_t vm = q < n ? ~0ull : 0ull;  // steps past the end count nothing
 #pragma unroll
             for (int v = 0; v < WPL; v++) {
-                up[v][q] = x[v] & vm;
-                dn[v][q] = ~x[v] & vm;
+                up[v][q] = u[v] & vm;
+                dn[v][q] = d[v] & vm;
             }
         }
         bool live = false;
@@ -267,26 +284,34 @@ struct PairLimit {
     static constexpr int T = (1 << P) - 1;
 };
 
-template <int PP, int MAXP, bool NEG, int KB, int WPL>
-__device__ __forceinline__ void pairs_width(int P, const uint64_t *pairs, int64_t pstride, int wlim,
+template <int PP, int MAXP, bool NEG, int KB, int WPL, bool TWO>
+__device__ __forceinline__ void pairs_width(int P, const uint64_t *pairs, const uint64_t *strict,
+                                            bool loose, int64_t pstride, int wlim,
                                             const int32_t *s_pd, int k, int t, int w,
                                             uint64_t *fit) {
     if constexpr (PP == MAXP) {
-        pairs_count<PP, NEG, KB, WPL>(pairs, pstride, wlim, s_pd, k, t, w, fit);
+        pairs_count<PP, NEG, KB, WPL, TWO>(pairs, strict, loose, pstride, wlim, s_pd, k, t, w,
+                                           fit);
     } else {
-        if (P == PP) return pairs_count<PP, NEG, KB, WPL>(pairs, pstride, wlim, s_pd, k, t, w, fit);
-        pairs_width<PP + 1, MAXP, NEG, KB, WPL>(P, pairs, pstride, wlim, s_pd, k, t, w, fit);
+        if (P == PP)
+            return pairs_count<PP, NEG, KB, WPL, TWO>(pairs, strict, loose, pstride, wlim, s_pd,
+                                                      k, t, w, fit);
+        pairs_width<PP + 1, MAXP, NEG, KB, WPL, TWO>(P, pairs, strict, loose, pstride, wlim, s_pd,
+                                                     k, t, w, fit);
     }
 }
 
 // Counter width for tolerance t <= PairLimit<KB, WPL>::T: the least P with
 // 2^P >= t+1.
-template <bool NEG, int KB, int WPL>
-__device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, int64_t pstride, int wlim,
+// TWO: both tables (the strict and loose tie rules; loose selects which).
+template <bool NEG, int KB, int WPL, bool TWO>
+__device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, const uint64_t *strict,
+                                               bool loose, int64_t pstride, int wlim,
                                                const int32_t *s_pd, int k, int t, int w,
                                                uint64_t *fit) {
     const int P = t == 0 ? 0 : 32 - __builtin_clz((unsigned)t);
-    pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL>(P, pairs, pstride, wlim, s_pd, k, t, w, fit);
+    pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL, TWO>(P, pairs, strict, loose, pstride, wlim,
+                                                             s_pd, k, t, w, fit);
 }
 
 // One workgroup per individual, one wave per item (a few 4096-row chunks of
@@ -311,7 +336,7 @@ __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, int64_t ps
 //    pass with all loads issued together; then count, overlap and fitness.
 // When the size score is 0 the fitness is 0 whatever the penalty, so the
 // members are only visited for the overlap output.
-template <int KB, int WPL>
+template <int KB, int WPL, bool TWO>
 __global__ void __launch_bounds__(kMaxWaves * kWave)
     batch_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
                  int32_t njobs, int64_t total_ind, int32_t sup_words, int32_t bits_words,
@@ -369,8 +394,9 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     const int t = bad0 ? 0 : tol(k, J.approx_permille);
     // pair table when the batch has one, it serves the tie rule and the
     // counters fit; else gather
-    const bool use_pairs =
-        J.mode == 1 && J.tie_rule == EBIC_TIE_INDEX && t <= PairLimit<KB, WPL>::T;
+    const bool two = TWO && J.tie_rule != EBIC_TIE_INDEX;  // both tables
+    const bool use_pairs = J.mode == 1 && t <= PairLimit<KB, WPL>::T &&
+                           (J.tie_rule == EBIC_TIE_INDEX || (TWO && J.pairs_strict));
 
     // 1. stage and validate the series
     if (threadIdx.x == 0) {
@@ -435,10 +461,21 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                     const int w = c0 * 64 + lane;
                     const int wlim = J.w64 < ch1 * 64 ? J.w64 : ch1 * 64;
                     uint64_t fit[WPL];
-                    if (neg)
-                        pairs_dispatch<true, KB, WPL>(J.pairs, J.pstride, wlim, s_pd, k, t, w, fit);
-                    else
-                        pairs_dispatch<false, KB, WPL>(J.pairs, J.pstride, wlim, s_pd, k, t, w, fit);
+                    const bool loose = J.tie_rule == EBIC_TIE_LOOSE;
+                    if (two) {
+                        if (neg)
+                            pairs_dispatch<true, KB, WPL, TWO>(J.pairs, J.pairs_strict, loose,
+                                                               J.pstride, wlim, s_pd, k, t, w, fit);
+                        else
+                            pairs_dispatch<false, KB, WPL, TWO>(J.pairs, J.pairs_strict, loose,
+                                                                J.pstride, wlim, s_pd, k, t, w, fit);
+                    } else if (neg) {
+                        pairs_dispatch<true, KB, WPL, false>(J.pairs, nullptr, false, J.pstride,
+                                                             wlim, s_pd, k, t, w, fit);
+                    } else {
+                        pairs_dispatch<false, KB, WPL, false>(J.pairs, nullptr, false, J.pstride,
+                                                              wlim, s_pd, k, t, w, fit);
+                    }
 #pragma unroll
                     for (int v = 0; v < WPL; v++) {
                         const int wv = w + kWave * v, r0 = wv * 64;
@@ -616,6 +653,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
 struct Batch {
     int device = 0;
     int32_t flags = 0;
+    bool two = false;          // some job reads both pair tables (strict or loose rule)
     std::vector<DevJob> jobs;
     DevJob *d_jobs = nullptr;  // device: DevJob[njobs] by population size, descending;
     int64_t *d_sched = nullptr;  // then the schedule (phase starts, phase rounds)
@@ -676,6 +714,7 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
     DevJob d{};
     d.ranks = j.matrix.d_ranks;
     d.pairs = j.matrix.d_pairs;
+    d.pairs_strict = j.matrix.d_pairs_strict;
     d.rows = j.matrix.rows;
     d.cols = j.matrix.cols;
     d.rows_pad = j.matrix.rows_pad;
@@ -714,6 +753,16 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
 int upload_table(Batch *b, int cpi, hipStream_t stream) {
     b->cpi = cpi;
     const int32_t n = b->njobs;
+    bool two = false;
+    for (const DevJob &d : b->jobs)
+        two |= d.mode == 1 && d.tie_rule != EBIC_TIE_INDEX && d.pairs_strict != nullptr;
+    if (two != b->two) {  // another kernel: a graph of the old one is rebuilt on the next run
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->two = two;
+    }
     int waves = 1;
     for (DevJob &d : b->jobs) {
         // whole groups per item, so that no two items share a group
@@ -777,12 +826,18 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
     return EBIC_OK;
 }
 
+template <bool TWO>
 void *kernel_fn(int kb, int wpl) {
     if (wpl == 2)
-        return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 2>)
-                       : reinterpret_cast<void *>(batch_kernel<2, 2>);
-    return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 1>)
-                   : reinterpret_cast<void *>(batch_kernel<2, 1>);
+        return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 2, TWO>)
+                       : reinterpret_cast<void *>(batch_kernel<2, 2, TWO>);
+    return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 1, TWO>)
+                   : reinterpret_cast<void *>(batch_kernel<2, 1, TWO>);
+}
+// The kernel for the batch: with the strict-table path only when some job
+// takes it, so the others keep the leaner kernel.
+void *kernel_fn(const Batch *b, int kb, int wpl) {
+    return b->two ? kernel_fn<true>(kb, wpl) : kernel_fn<false>(kb, wpl);
 }
 
 size_t lds_bytes(const Batch *b) {
@@ -796,7 +851,7 @@ size_t lds_bytes(const Batch *b) {
 int launch_batch(Batch *b, hipStream_t stream) {
     void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind, &b->sup_words,
                     &b->bits_words, &b->acol_words};
-    EBIC_HIP(hipLaunchKernel(kernel_fn(b->kb, b->wpl), dim3((unsigned)b->total_ind),
+    EBIC_HIP(hipLaunchKernel(kernel_fn(b, b->kb, b->wpl), dim3((unsigned)b->total_ind),
                              dim3(b->waves * kWave), args, lds_bytes(b), stream));
     return EBIC_OK;
 }
@@ -811,7 +866,7 @@ int build_graph(Batch *b) {
     void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind, &b->sup_words,
                     &b->bits_words, &b->acol_words};
     hipKernelNodeParams pk{};
-    pk.func = kernel_fn(b->kb, b->wpl);
+    pk.func = kernel_fn(b, b->kb, b->wpl);
     pk.gridDim = dim3((unsigned)b->total_ind);
     pk.blockDim = dim3(b->waves * kWave);
     pk.sharedMemBytes = (unsigned)lds_bytes(b);
@@ -893,7 +948,8 @@ std::string tune_key(const Batch *b) {
         mode |= 1 << d.mode;
     }
     char buf[128];
-    snprintf(buf, sizeof buf, "m%d_w%d_i%lld_j%d", mode, w, (long long)b->total_ind, b->njobs);
+    snprintf(buf, sizeof buf, "m%d_w%d_i%lld_j%d%s", mode, w, (long long)b->total_ind, b->njobs,
+             b->two ? "_s" : "");
     return buf;
 }
 

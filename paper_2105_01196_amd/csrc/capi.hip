@@ -117,6 +117,7 @@ int ebic_matrix_prepare(const float *d_x, int32_t rows, int32_t cols, uint16_t *
     m->cols = cols;
     m->rows_pad = rows_padded(rows);
     m->d_pairs = nullptr;
+    m->d_pairs_strict = nullptr;
     return EBIC_OK;
 }
 
@@ -207,10 +208,22 @@ int ebic_pairs_prepare(ebic_matrix *m, uint64_t *d_pairs, void *stream) {
     int rc = check_matrix(m);
     if (rc) return rc;
     if (!d_pairs) return fail(EBIC_ERR_INVALID_ARG, "pair table is NULL");
-    rc = launch_build_pairs(m->d_ranks, m->rows, m->cols, m->rows_pad, d_pairs,
+    rc = launch_build_pairs(m->d_ranks, m->rows, m->cols, m->rows_pad, d_pairs, false,
                             static_cast<hipStream_t>(stream));
     if (rc) return rc;
     m->d_pairs = d_pairs;
+    return EBIC_OK;
+}
+
+int ebic_pairs_strict_prepare(ebic_matrix *m, uint64_t *d_pairs_strict, void *stream) {
+    clear_error();
+    int rc = check_matrix(m);
+    if (rc) return rc;
+    if (!d_pairs_strict) return fail(EBIC_ERR_INVALID_ARG, "strict pair table is NULL");
+    rc = launch_build_pairs(m->d_ranks, m->rows, m->cols, m->rows_pad, d_pairs_strict, true,
+                            static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    m->d_pairs_strict = d_pairs_strict;
     return EBIC_OK;
 }
 

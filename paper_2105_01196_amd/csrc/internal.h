@@ -74,8 +74,10 @@ int launch_support_rows(const uint64_t *support, int32_t size, int32_t words, co
                         int32_t n_sel, const int32_t *row_off, int32_t *rows, hipStream_t stream);
 int launch_prepare(const float *x, int32_t rows, int32_t cols, uint16_t *ranks, int *flag,
                    hipStream_t stream);
+// The pair table ("lo precedes hi": rank[lo] <= rank[hi]) or, with strict,
+// the strict one (rank[lo] < rank[hi]).
 int launch_build_pairs(const uint16_t *ranks, int32_t rows, int32_t cols, int32_t rows_pad,
-                       uint64_t *table, hipStream_t stream);
+                       uint64_t *table, bool strict, hipStream_t stream);
 
 int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
                const ebic_allocator *al, hipStream_t stream, ebic_result **out);

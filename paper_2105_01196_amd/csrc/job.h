@@ -238,6 +238,12 @@ class Job {
     // Device bytes a job of this shape holds (matrix, ranks, pair table when
     // used, population, outputs, archive).
     static size_t footprint(int32_t rows, int32_t cols, const ebic_params &p, bool pairs);
+    // Bytes of the pair tables a job with these parameters builds when it
+    // uses the pair form (the strict table too under the strict and loose
+    // tie rules).
+    static size_t pair_table_bytes(int32_t rows, int32_t cols, const ebic_params &p) {
+        return ebic_pairs_bytes(rows, cols) * (p.tie_rule == EBIC_TIE_INDEX ? 1 : 2);
+    }
     // Allocate, ingest the matrix, build the pair table when `pairs`; with
     // own_staging false the job is only ever staged through stage_into()
     // and gets no staging buffers of its own.
@@ -336,7 +342,7 @@ class Job {
     ebic_matrix m_{};
     DeviceArray<float> d_x_;
     DeviceArray<uint16_t> d_ranks_;
-    DeviceArray<uint64_t> d_pairs_;
+    DeviceArray<uint64_t> d_pairs_, d_pairs_strict_;
     DeviceArray<int32_t> d_sel_, d_roff_, d_rows_;
     // Own staging (stage() and fetch()): every input in one block each
     // way, and the scores, counts and then the supports in another, so a

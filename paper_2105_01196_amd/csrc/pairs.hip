@@ -1,6 +1,7 @@
 // Pair-comparison table: for every unordered column pair lo < hi, the bitmap
 // over rows of "lo precedes hi in this row" (smaller value first; a tie puts
-// the smaller column index first). A step c_j -> c_{j+1} of a
+// the smaller column index first). The strict table holds "lo's value is
+// strictly smaller" instead, for the strict and loose tie rules. A step c_j -> c_{j+1} of a
 // series keeps the increasing trend in exactly the rows of pair
 // (min, max)'s bitmap, inverted when c_j > c_{j+1}, because the row order is
 // strict and total. With the table resident, testing a step costs one bit
@@ -27,6 +28,7 @@ constexpr int kBChunk = 32;  // columns b per wave
 // compares is the table word for (pair, block). The words are gathered
 // into lanes (q * 16 + block) so that each pair's 16 words go out as one
 // 128-byte store.
+template <bool STRICT>
 __global__ void __launch_bounds__(kBuildWaves * kWave)
     build_pairs_kernel(const uint16_t *__restrict__ ranks, int32_t rows, int32_t cols,
                        int32_t rows_pad, uint64_t *__restrict__ table, int32_t stride,
@@ -81,9 +83,10 @@ __global__ void __launch_bounds__(kBuildWaves * kWave)
             if (a0 + q >= bcol) continue;
 #pragma unroll
             for (int b = 0; b < kSpan; b++) {
-                // a < b: a tie puts a first; padding rows (rank 0 everywhere) read 0
-                const uint64_t m =
-                    __ballot((blk0 + b) * 64 + lane < rows && ra[q][b] <= rb[b]);
+                // a < b: a tie puts a first (none in the strict table);
+                // padding rows (rank 0 everywhere) read 0
+                const bool before = STRICT ? ra[q][b] < rb[b] : ra[q][b] <= rb[b];
+                const uint64_t m = __ballot((blk0 + b) * 64 + lane < rows && before);
                 lo = writelane((int)(uint32_t)m, q * kSpan + b, lo);
                 hi = writelane((int)(uint32_t)(m >> 32), q * kSpan + b, hi);
             }
@@ -98,14 +101,15 @@ __global__ void __launch_bounds__(kBuildWaves * kWave)
 }  // namespace
 
 int launch_build_pairs(const uint16_t *ranks, int32_t rows, int32_t cols, int32_t rows_pad,
-                       uint64_t *table, hipStream_t stream) {
+                       uint64_t *table, bool strict, hipStream_t stream) {
     const int32_t ngroups = (cols + kAGroup - 1) / kAGroup;
     const int32_t nspans = (rows_pad / 64 + kSpan - 1) / kSpan;
     const int32_t nchunks = (cols + kBChunk - 1) / kBChunk;
     const int64_t waves = (int64_t)ngroups * nspans * nchunks;
     const int64_t blocks = (waves + kBuildWaves - 1) / kBuildWaves;
     if (blocks > INT32_MAX) return fail(EBIC_ERR_INVALID_ARG, "pair table too large");
-    build_pairs_kernel<<<(int)blocks, kBuildWaves * kWave, 0, stream>>>(
+    auto *kernel = strict ? build_pairs_kernel<true> : build_pairs_kernel<false>;
+    kernel<<<(int)blocks, kBuildWaves * kWave, 0, stream>>>(
         ranks, rows, cols, rows_pad, table, pair_words(rows_pad), ngroups, nspans, nchunks);
     EBIC_HIP(hipGetLastError());
     return EBIC_OK;

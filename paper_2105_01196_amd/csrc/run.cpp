@@ -22,7 +22,7 @@ size_t Job::footprint(int32_t rows, int32_t cols, const ebic_params &p, bool pai
     const size_t rp = (size_t)rows_padded(rows), W = rp / 64;
     const size_t nmax = (size_t)std::max(p.population, p.archive_size);
     size_t b = sizeof(float) * rows * cols + 2 * rp * cols;
-    if (pairs) b += ebic_pairs_bytes(rows, cols);
+    if (pairs) b += pair_table_bytes(rows, cols, p);
     b += nmax * (4 + 4 + 2 * (size_t)p.k_max + 8 + 4 + 8 * W) + 4;
     b += (size_t)p.archive_size * (8 * W + 4 + 2 * (size_t)p.k_max) + 4;
     b += (2 * (size_t)p.archive_size + 8) * (8 * W + sizeof(WordSpan));  // gathered supports
@@ -45,6 +45,11 @@ int Job::setup(const float *h_x, int32_t rows, int32_t cols, bool pairs, bool ow
         RUN_HIP(d_pairs_.alloc(pair_bytes / sizeof(uint64_t), al_, stream_));
         rc = ebic_pairs_prepare(&m_, d_pairs_.p, stream_);
         if (rc) return rc;
+        if (p_.tie_rule != EBIC_TIE_INDEX) {  // both tables for the strict and loose rules
+            RUN_HIP(d_pairs_strict_.alloc(pair_bytes / sizeof(uint64_t), al_, stream_));
+            rc = ebic_pairs_strict_prepare(&m_, d_pairs_strict_.p, stream_);
+            if (rc) return rc;
+        }
     }
     if (!own_staging) return EBIC_OK;  // stage_into() only
     const int32_t nmax = std::max(P, K);
@@ -788,7 +793,7 @@ namespace {
 int session_setup(Session *s, const ebic_params &p, uint64_t seed, const ebic_allocator *al) {
     size_t free_b = 0, total_b = 0;
     EBIC_HIP(hipMemGetInfo(&free_b, &total_b));
-    const size_t pair_bytes = ebic_pairs_bytes(s->rows, s->cols);
+    const size_t pair_bytes = Job::pair_table_bytes(s->rows, s->cols, p);
     s->job.reset(new Job(p, seed, s->stream));
     s->job->set_allocator(al);
     s->job->set_host_matrix(s->x);

@@ -218,7 +218,7 @@ int Server::submit(const float *h_x, int32_t rows, int32_t cols, const ebic_para
     j->seed = seed;
     {
         std::lock_guard<std::mutex> lk(mu_);
-        const size_t pb = ebic_pairs_bytes(rows, cols);
+        const size_t pb = Job::pair_table_bytes(rows, cols, *p);
         j->pairs = pb > 0 && pb <= budget_ / 8;
         j->footprint = Job::footprint(rows, cols, *p, j->pairs);
         j->id = next_id_++;

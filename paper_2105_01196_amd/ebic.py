@@ -48,7 +48,7 @@ class ebic_params(ctypes.Structure):
 
 class ebic_matrix(ctypes.Structure):
     _fields_ = [("d_ranks", _vp), ("rows", _i32), ("cols", _i32), ("rows_pad", _i32),
-                ("d_pairs", _vp)]
+                ("d_pairs", _vp), ("d_pairs_strict", _vp)]
 
 
 class ebic_population(ctypes.Structure):
@@ -132,6 +132,7 @@ _SIGNATURES = {
     "ebic_support_rows": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i32, _vp, _vp, _vp]),
     "ebic_pairs_bytes": (ctypes.c_size_t, [_i32, _i32]),
     "ebic_pairs_words": (_i32, [_i32]),
+    "ebic_pairs_strict_prepare": (ctypes.c_int, [ctypes.POINTER(ebic_matrix), _vp, _vp]),
     "ebic_pairs_prepare": (ctypes.c_int, [ctypes.POINTER(ebic_matrix), _vp, _vp]),
     "ebic_batch_create": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _i32,
                                          ctypes.POINTER(_vp)]),
@@ -244,6 +245,7 @@ class Matrix:
     ranks: torch.Tensor
     view: ebic_matrix
     pairs: Optional[torch.Tensor] = None
+    pairs_strict: Optional[torch.Tensor] = None
 
     @property
     def rows(self) -> int:
@@ -428,6 +430,17 @@ def ebic_pairs_prepare(m: Matrix, stream=None) -> Matrix:
     table = torch.empty(max(nbytes // 8, 1), dtype=torch.int64, device=m.ranks.device)
     _check(lib().ebic_pairs_prepare(ctypes.byref(m.view), table.data_ptr(), _stream(stream)))
     m.pairs = table
+    return m
+
+
+def ebic_pairs_strict_prepare(m: Matrix, stream=None) -> Matrix:
+    """Build the strict pair table (the strict and loose tie rules take the
+    pair form with both tables) and attach it to the matrix view."""
+    nbytes = ebic_pairs_bytes(m.rows, m.cols)
+    table = torch.empty(max(nbytes // 8, 1), dtype=torch.int64, device=m.ranks.device)
+    _check(lib().ebic_pairs_strict_prepare(ctypes.byref(m.view), table.data_ptr(),
+                                           _stream(stream)))
+    m.pairs_strict = table
     return m
 
 

@@ -29,10 +29,12 @@ def _kw(**kw):
     return d
 
 
-def _matrix(E, X, pairs=True):
+def _matrix(E, X, pairs=True, strict=False):
     m = E.ebic_matrix_prepare(torch.from_numpy(np.ascontiguousarray(X)).cuda())
     if pairs:
         E.ebic_pairs_prepare(m)
+    if strict:
+        E.ebic_pairs_strict_prepare(m)
     return m
 
 
@@ -55,8 +57,8 @@ def _check_job(E, job, X, seqs, kw, arch=None, sample=None):
 
 
 def _run(E, X, seqs, kw, arch_flags=None, arch_series=None, gather=False, graph=False,
-         order=False, sample=None):
-    m = _matrix(E, X, pairs=not gather)
+         order=False, sample=None, strict=False):
+    m = _matrix(E, X, pairs=not gather, strict=strict and not gather)
     pop = E.ebic_population_upload(seqs, X.shape[1])
     if order:
         E.set_order(pop, E.longest_first(seqs))
@@ -93,6 +95,19 @@ def test_pair_table_bits(E):
                              bitorder="little")
         assert not bits[:, R:].any()
         assert E.ebic_pairs_bytes(R, C) == len(pairs) * S * 8
+        # the strict table: the rows where lo's value is strictly smaller
+        E.ebic_pairs_strict_prepare(m)
+        torch.cuda.synchronize()
+        ev = oracle.evaluate(X, [list(p) for p in pairs],
+                             params=oracle.make_params(approx_permille=1000, negative_trends=0,
+                                                       min_rows=1, k_score_min=2,
+                                                       tie_rule=E.EBIC_TIE_STRICT))
+        table = m.pairs_strict.cpu().numpy().view(np.uint64).reshape(len(pairs), S)[:, :m.words]
+        table = np.ascontiguousarray(table)
+        np.testing.assert_array_equal(E.support_to_flags(table, R), ev.support)
+        bits = np.unpackbits(table.view(np.uint8).reshape(len(pairs), -1), axis=1,
+                             bitorder="little")
+        assert not bits[:, R:].any()
 
 
 @pytest.mark.parametrize("gather", [False, True])
@@ -223,9 +238,10 @@ def test_set_tuning_rejects_other_shapes(E):
 
 @pytest.mark.parametrize("rule", [0, 1, 2])
 def test_tie_rules(E, rule):
-    """Tie-heavy rows and constant-row biclusters under each tie rule: the
-    column-index rule on the pair table, the others in the gather form (the
-    matrix has a table either way), both forms of the batch equal."""
+    """Tie-heavy rows and constant-row biclusters under each tie rule, in
+    three forms: the pair table alone (the strict and loose rules then take
+    the gather form), both pair tables (every rule in the pair form), and
+    the gather form."""
     X = synth.tie_matrix(777, 64, levels=3, seed=31)
     case = synth.planted_matrix(500, 40, background="normal", n_planted=3,
                                 rows_range=(40, 60), cols_range=(4, 12), sigma=0.0,
@@ -240,7 +256,30 @@ def test_tie_rules(E, rule):
                 kw = _kw(approx_permille=approx, negative_trends=neg, min_rows=1,
                          tie_rule=rule)
                 _run(E, M, seqs, kw)
+                _run(E, M, seqs, kw, strict=True)
                 _run(E, M, seqs, kw, gather=True)
+
+
+def test_mixed_tie_rules_in_one_batch(E):
+    """Jobs under all three tie rules in one launch over a matrix with both
+    pair tables: each job equals the oracle under its own rule."""
+    X = synth.tie_matrix(700, 48, levels=4, seed=41)
+    m = _matrix(E, X, strict=True)
+    rng = np.random.default_rng(42)
+    jobs, cases = [], []
+    for rule in (E.EBIC_TIE_INDEX, E.EBIC_TIE_STRICT, E.EBIC_TIE_LOOSE, E.EBIC_TIE_STRICT):
+        seqs = [list(rng.permutation(48)[:int(k)]) for k in rng.integers(2, 33, 120)]
+        kw = _kw(approx_permille=800, negative_trends=int(rule != E.EBIC_TIE_LOOSE), min_rows=1,
+                 tie_rule=rule)
+        pop = E.ebic_population_upload(seqs, 48)
+        jobs.append(E.make_job(m, pop, None, E.make_params(**kw)))
+        cases.append((seqs, kw))
+    b = E.Batch(jobs)
+    b.run()
+    torch.cuda.synchronize()
+    for job, (seqs, kw) in zip(jobs, cases):
+        _check_job(E, job, X, seqs, kw)
+    b.close()
 
 
 def test_pattern_biclusters(E):
