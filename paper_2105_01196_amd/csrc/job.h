@@ -207,6 +207,9 @@ template <typename T>
 struct PinnedArray {
     T *p = nullptr;
     size_t n = 0;
+    PinnedArray() = default;
+    PinnedArray(const PinnedArray &) = delete;
+    PinnedArray &operator=(const PinnedArray &) = delete;
     ~PinnedArray() {
         if (p) (void)hipHostFree(p);
     }
