@@ -165,8 +165,8 @@ int ebic_matrix_prepare(const float *d_x, int32_t rows, int32_t cols, uint16_t *
 /* Population upload: validates a host CSR population (every series has
  * 2..EBIC_MAX_K distinct columns below `cols`) and copies it into the
  * caller's device arrays d_offsets (P+1 int32) and d_cols (offsets[P]
- * uint16). Sec. 2.4, step 2 ("compressing the whole population and sending
- * it on GPU"). Synchronous. EBIC_ERR_INVALID_ARG on an invalid series (nothing
+ * uint16). Sec. 2.4, step 2 (the population is packed into one compact
+ * array before it goes to the GPU). Synchronous. EBIC_ERR_INVALID_ARG on an invalid series (nothing
  * is copied). */
 int ebic_population_upload(const int32_t *h_offsets, const uint16_t *h_cols, int32_t size,
                            int32_t cols, int32_t *d_offsets, uint16_t *d_cols, void *stream);
@@ -338,8 +338,8 @@ void ebic_result_free(ebic_result *r);
  * ground truth on a rows x cols matrix, for scoring recovery: the confusion
  * matrix counts the cells each detected bicluster shares with each true one
  * (rows x columns, so |rows ∩ rows'| * |cols ∩ cols'|), D_max is the largest
- * total of a one-to-one assignment between the two sets (Munkres), and U is
- * the union of the cells of all biclusters of both sets. *score = D_max/|U|
+ * total of a one-to-one assignment between the two sets (Munkres), and U
+ * collects every cell covered by any bicluster of either set. *score = D_max/|U|
  * (1 = perfect match, 0 = nothing shared: the paper's text reads CE this
  * way); *ce = (|U| - D_max)/|U|, Eq. 1 as printed. Both sets empty (or all
  * biclusters empty): score 1, ce 0. Only n_rows/rows/n_cols/cols of each

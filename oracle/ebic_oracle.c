@@ -7,9 +7,9 @@
  *
  * Paper: "EBIC.JL - an Efficient Implementation of Evolutionary Biclustering
  * Algorithm in Julia" (GECCO'21 Companion, arXiv 2105.01196).
- *   Sec. 2.3 (EBIC paragraph): individuals are series of columns; the series
- *     defines an increasing order for the values of every row that belongs to
- *     the bicluster; operators insertion/deletion/substitution/swap/crossover;
+ *   Sec. 2.3 (EBIC paragraph): an individual is a series of columns, and a
+ *     row belongs to its bicluster when the row's values rise along that
+ *     series; operators insertion/deletion/substitution/swap/crossover;
  *     elitism, tournament selection with an exponential penalty for overused
  *     columns (crowding), tabu list of individuals, stop on tabu hits.
  *   Sec. 2.4 (EBIC.jl): the nine-step generational loop, and the parameters

@@ -5,8 +5,8 @@
 // biclusters share number |rows ∩ rows'| * |cols ∩ cols'|: that is the
 // confusion matrix. D_max is the largest total of a one-to-one assignment
 // between the two sets (Munkres' algorithm, here the shortest augmenting
-// path form with potentials, O(n^3)), and U is the union of the cells of all
-// biclusters of both sets.
+// path form with potentials, O(n^3)); U collects every cell covered by any
+// bicluster of either set.
 #include <algorithm>
 #include <cstdint>
 #include <limits>
