@@ -274,9 +274,13 @@ int Job::update_archive() {
         std::vector<size_t> clash;
         bool beats = true;
         for (size_t j = 0; j < archive_.size(); j++) {
-            const int64_t h = shared_rows(sup, archive_[j].support.data());
+            // h <= min(n, n_j): when even that cannot clash (g = 0 among
+            // others), the rows need no counting
             const int64_t g = shared_cols(s, archive_[j].s);
-            if (1000 * h * g > (int64_t)p_.overlap_permille * n * k) {
+            const int64_t bound = (int64_t)p_.overlap_permille * n * k;
+            if (1000 * std::min<int64_t>(n, archive_[j].n) * g <= bound) continue;
+            const int64_t h = shared_rows(sup, archive_[j].support.data());
+            if (1000 * h * g > bound) {
                 clash.push_back(j);
                 if (!ranks_above(score_[i], s, archive_[j].score, archive_[j].s)) beats = false;
             }
