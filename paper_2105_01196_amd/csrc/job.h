@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <memory>
 #include <numeric>
 #include <iterator>
@@ -88,7 +89,10 @@ inline bool same_canonical(const Series &s, const Series &c, bool neg) {
 
 // The tabu list (Sec. 2.4, step 6): a set of canonical series, open
 // addressing over one flat arena of columns, so an insert allocates only
-// when a buffer doubles.
+// when a buffer doubles. Each slot keeps a 32-bit tag (part of the hash,
+// never 0) in one compact array and the series' place in the arena in
+// another, so a probe for a new series usually reads the tags alone. The
+// hash only places series; membership is decided by comparing columns.
 class TabuSet {
   public:
     // Inserts canonical(s, neg); false if it was present.
@@ -99,58 +103,77 @@ class TabuSet {
                             std::reverse_iterator<const uint16_t *>(s));
             c = scratch_.data();
         }
-        uint64_t h = 0x84222325CBF29CE4ULL ^ k;
-        for (size_t i = 0; i < k; i++) h = (h ^ c[i]) * 0x100000001B3ULL;
-        h ^= h >> 31;
-        h *= 0x94D049BB133111EBULL;
-        h ^= h >> 29;
-        if (2 * (n_ + 1) > slots_.size()) grow();
-        const size_t mask = slots_.size() - 1;
+        if (2 * (n_ + 1) > tag_.size()) grow();
+        const uint64_t h = hash(c, k);
+        const uint32_t tg = tag_of(h);
+        const size_t mask = tag_.size() - 1;
         for (size_t i = (size_t)h & mask;; i = (i + 1) & mask) {
-            Slot &e = slots_[i];
-            if (e.len1 == 0) {
-                e.hash = h;
-                e.off = arena_.size();
-                e.len1 = (uint32_t)k + 1;
+            const uint32_t t = tag_[i];
+            if (t == 0) {
+                tag_[i] = tg;
+                at_[i] = (uint64_t)arena_.size() << 16 | (uint64_t)k;
                 arena_.insert(arena_.end(), c, c + k);
                 n_++;
                 return true;
             }
-            if (e.hash == h && e.len1 == k + 1 && std::equal(c, c + k, arena_.data() + e.off))
+            if (t == tg && (at_[i] & 0xffff) == k &&
+                std::equal(c, c + k, arena_.data() + (at_[i] >> 16)))
                 return false;
         }
     }
     bool insert(const Series &s, bool neg) { return insert(s.data(), s.size(), neg); }
     size_t size() const { return n_; }
     void clear() {
-        slots_.clear();
+        tag_.clear();
+        at_.clear();
         arena_.clear();
         n_ = 0;
     }
     // f(columns, length) for every member, in no particular order.
     template <class F>
     void for_each(F &&f) const {
-        for (const Slot &e : slots_)
-            if (e.len1) f(arena_.data() + e.off, (size_t)e.len1 - 1);
+        for (size_t i = 0; i < tag_.size(); i++)
+            if (tag_[i]) f(arena_.data() + (at_[i] >> 16), (size_t)(at_[i] & 0xffff));
     }
 
   private:
-    struct Slot {
-        uint64_t hash = 0, off = 0;
-        uint32_t len1 = 0;  // length + 1; 0 marks a free slot
-    };
-    void grow() {
-        std::vector<Slot> old(std::max<size_t>(1024, 2 * slots_.size()));
-        old.swap(slots_);
-        const size_t mask = slots_.size() - 1;
-        for (const Slot &e : old) {
-            if (!e.len1) continue;
-            size_t i = (size_t)e.hash & mask;
-            while (slots_[i].len1) i = (i + 1) & mask;
-            slots_[i] = e;
+    // Four columns per multiply, then a final mix (series are at most
+    // EBIC_MAX_K = 512 columns, which fits the 16-bit length field).
+    static uint64_t hash(const uint16_t *c, size_t k) {
+        uint64_t h = 0x9E3779B97F4A7C15ULL ^ k;
+        size_t i = 0;
+        for (; i + 4 <= k; i += 4) {
+            uint64_t w;
+            std::memcpy(&w, c + i, sizeof w);
+            h = (h ^ w) * 0xBF58476D1CE4E5B9ULL;
+            h ^= h >> 29;
         }
+        uint64_t w = 0;
+        for (size_t q = 0; i + q < k; q++) w |= (uint64_t)c[i + q] << (16 * q);
+        h = (h ^ w) * 0x94D049BB133111EBULL;
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ULL;
+        return h ^ (h >> 32);
     }
-    std::vector<Slot> slots_;
+    static uint32_t tag_of(uint64_t h) { return (uint32_t)(h >> 32) | 1u; }
+    void grow() {
+        const size_t cap = std::max<size_t>(1024, 2 * tag_.size());
+        std::vector<uint32_t> tag(cap, 0);
+        std::vector<uint64_t> at(cap, 0);
+        const size_t mask = cap - 1;
+        for (size_t j = 0; j < tag_.size(); j++) {
+            if (!tag_[j]) continue;
+            const uint64_t h = hash(arena_.data() + (at_[j] >> 16), (size_t)(at_[j] & 0xffff));
+            size_t i = (size_t)h & mask;
+            while (tag[i]) i = (i + 1) & mask;
+            tag[i] = tag_[j];
+            at[i] = at_[j];
+        }
+        tag_.swap(tag);
+        at_.swap(at);
+    }
+    std::vector<uint32_t> tag_;  // per slot: 0 free, else part of the series' hash
+    std::vector<uint64_t> at_;   // per slot: arena offset << 16 | length
     std::vector<uint16_t> arena_, scratch_;
     size_t n_ = 0;
 };
