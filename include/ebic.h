@@ -385,8 +385,9 @@ void ebic_session_free(ebic_session *s);
  * resident on the device. Preparer threads set admitted jobs up (upload,
  * ranks, pair table, first population) on streams of their own while the
  * scheduler keeps ticking; a prepared job joins at the next tick. Each tick
- * scores the current populations of all active jobs in one batched launch,
- * then runs their host steps. A finished job frees its memory and slot, and
+ * scores the current populations of the jobs that want scores in one
+ * batched launch; each job's host steps then run as a task of their own, and
+ * the job joins the next tick once they are done. A finished job frees its memory and slot, and
  * queued jobs are admitted at the next tick. Each job's result is identical to ebic_run with the same
  * matrix, parameters and seed. */
 typedef struct ebic_server ebic_server;
@@ -407,7 +408,7 @@ typedef struct ebic_server_metrics {
     size_t hbm_in_use, hbm_budget;
     double stage_s;             /* ticks' host packing                         */
     double device_s;            /* ticks' upload, launch, download and wait    */
-    double host_s;              /* ticks' host steps of the jobs               */
+    double host_s;              /* jobs' host steps (summed over worker tasks) */
     double setup_s;             /* admitted jobs' setup, beside the ticks      */
     double release_s;           /* ended jobs' frees                           */
 } ebic_server_metrics;

@@ -1,15 +1,19 @@
 // Job server: continuous batching of many runs of the method on one GPU.
 //
-// A scheduler thread owns a stream and the batch. Before each tick it admits
-// queued jobs whose device footprint fits the remaining HBM budget (arrival
-// order, so a large job is never starved by smaller ones behind it) and
-// hands them to preparer threads, which set them up on streams of their own
-// (allocation, upload, ranks, pair table, first population) while the ticks
-// go on; prepared jobs join the active set at the next tick. A tick packs
-// the population and top-rank list of every active job into one shared
-// staging buffer, uploads it with one copy, scores all jobs in one batched
-// launch, downloads every output with one copy, and runs each job's host
-// steps. Finished jobs release their device memory and slot.
+// A scheduler thread owns a stream. It admits queued jobs whose device
+// footprint fits the remaining HBM budget (arrival order, so a large job is
+// never starved by smaller ones behind it) and hands them to preparer
+// threads, which set them up on streams of their own (allocation, upload,
+// ranks, pair tables, first population) while the ticks go on. A tick takes
+// every job that wants scores (just prepared, or its last host step done):
+// it packs their populations and top-rank lists into one staging buffer,
+// uploads it with one copy, scores them all in one batched launch,
+// downloads scores and counts with one copy, orders each job's candidates
+// and gathers the supports their top-rank list updates look at first. Each
+// job's host step then runs as a task of its own on the worker pool, so no
+// job waits for the slowest one; the tick's buffers (one of a few slots)
+// stay reserved until those steps have read them. Finished jobs release
+// their device memory and slot.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -33,8 +37,9 @@ double now_s() {
     return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-// Fixed pool of host threads for the jobs' host steps (they are independent
-// across jobs); run(n, fn) calls fn(0..n-1) and returns when all are done.
+// Fixed pool of host threads. Jobs' host steps are queued as tasks (each job
+// runs its own as soon as its scores are in); parallel(n, fn) runs fn(0..n-1)
+// ahead of the queued tasks and returns when all n are done.
 class WorkerPool {
   public:
     explicit WorkerPool(int n) {
@@ -48,37 +53,50 @@ class WorkerPool {
         cv_.notify_all();
         for (auto &t : threads_) t.join();
     }
-    void run(size_t n, const std::function<void(size_t)> &fn) {
+    void submit(std::function<void()> task) {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            tasks_.push_back(std::move(task));
+        }
+        cv_.notify_one();
+    }
+    void parallel(size_t n, const std::function<void(size_t)> &fn) {
         if (n == 0) return;
-        std::unique_lock<std::mutex> lk(mu_);
-        fn_ = &fn;
-        next_ = 0;
-        total_ = n;
-        left_ = n;
+        std::mutex m;
+        std::condition_variable done;
+        size_t left = n;
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            for (size_t i = n; i-- > 0;)  // front of the queue, fn(0) first
+                tasks_.push_front([&, i] {
+                    fn(i);
+                    std::lock_guard<std::mutex> l(m);
+                    if (--left == 0) done.notify_all();
+                });
+        }
         cv_.notify_all();
-        done_.wait(lk, [&] { return left_ == 0; });
-        fn_ = nullptr;
+        std::unique_lock<std::mutex> l(m);
+        done.wait(l, [&] { return left == 0; });
     }
 
   private:
     void work() {
-        std::unique_lock<std::mutex> lk(mu_);
         for (;;) {
-            cv_.wait(lk, [&] { return quit_ || (fn_ && next_ < total_); });
-            if (quit_) return;
-            const size_t i = next_++;
-            const std::function<void(size_t)> *fn = fn_;
-            lk.unlock();
-            (*fn)(i);
-            lk.lock();
-            if (--left_ == 0) done_.notify_all();
+            std::function<void()> task;
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return quit_ || !tasks_.empty(); });
+                if (tasks_.empty()) return;  // quitting with nothing queued
+                task = std::move(tasks_.front());
+                tasks_.pop_front();
+            }
+            task();
         }
     }
     std::vector<std::thread> threads_;
     std::mutex mu_;
-    std::condition_variable cv_, done_;
-    const std::function<void(size_t)> *fn_ = nullptr;
-    size_t next_ = 0, total_ = 0, left_ = 0;
+    std::condition_variable cv_;
+    std::deque<std::function<void()>> tasks_;
     bool quit_ = false;
 };
 
@@ -111,14 +129,29 @@ class Server {
     void stats(ebic_server_metrics *st);
 
   private:
+    // Staging buffers of one tick (inputs, scores and counts, supports, the
+    // gathered first supports), reserved until the host steps of its jobs
+    // have read them: pending counts the steps not yet finished.
+    struct Slot {
+        PinnedArray<uint8_t> h_in, h_out;
+        DeviceArray<uint8_t> d_in, d_out, d_sup;
+        PinnedArray<WordSpan> h_spans;
+        DeviceArray<WordSpan> d_spans;
+        PinnedArray<uint64_t> h_first;
+        DeviceArray<uint64_t> d_first;
+        Batch *batch = nullptr;
+        int pending = 0;  // under mu_
+    };
+    static constexpr int kSlots = 4;
+
     void loop();
     void prepare_loop(hipStream_t stream);
-    void tick(std::vector<std::shared_ptr<ServerJob>> &active);
+    void tick(std::vector<std::shared_ptr<ServerJob>> &jobs, Slot &sl);
     void finish_job(const std::shared_ptr<ServerJob> &j, int status, const char *err);
     void release_loop();
     void end_jobs(const std::vector<std::shared_ptr<ServerJob>> &ended);
     bool admissible() const;
-    int fetch_first_supports(const std::vector<std::shared_ptr<ServerJob>> &active,
+    int fetch_first_supports(Slot &sl, const std::vector<std::shared_ptr<ServerJob>> &jobs,
                              const std::vector<std::vector<int32_t>> &first,
                              std::vector<size_t> *at);
 
@@ -128,6 +161,7 @@ class Server {
     // admitted, waiting for the preparer; prepared, waiting for a tick;
     // ended, waiting for their memory to be freed
     std::deque<std::shared_ptr<ServerJob>> prep_q_, ready_, rel_q_;
+    std::deque<std::shared_ptr<ServerJob>> host_done_;  // host step finished
     std::unordered_map<int64_t, std::shared_ptr<ServerJob>> jobs_;
     std::vector<double> latencies_;
     int64_t next_id_ = 1, submitted_ = 0, completed_ = 0, failed_ = 0, evaluations_ = 0;
@@ -142,17 +176,7 @@ class Server {
     int device_ = 0;
     hipStream_t stream_ = nullptr;
     std::vector<hipStream_t> prep_streams_;  // one per preparer thread
-    Batch *batch_ = nullptr;
-    // One tick's inputs of all jobs (uploaded by one copy), scores and
-    // counts (downloaded by one copy) and supports (left on the device); the
-    // spans that gather the supports the top-rank list updates look at, and
-    // those supports (one copy each way). All grow to the largest tick seen.
-    PinnedArray<uint8_t> h_in_, h_out_;
-    DeviceArray<uint8_t> d_in_, d_out_, d_sup_;
-    PinnedArray<WordSpan> h_spans_;
-    DeviceArray<WordSpan> d_spans_;
-    PinnedArray<uint64_t> h_first_;
-    DeviceArray<uint64_t> d_first_;
+    Slot slots_[kSlots];
     std::unique_ptr<WorkerPool> pool_;
     std::thread thread_, rel_thread_;
     std::vector<std::thread> prep_threads_;
@@ -196,7 +220,8 @@ Server::~Server() {
     cv_rel_.notify_all();
     if (rel_thread_.joinable()) rel_thread_.join();
     pool_.reset();
-    if (batch_) batch_destroy(batch_);
+    for (Slot &sl : slots_)
+        if (sl.batch) batch_destroy(sl.batch);
     if (stream_) (void)hipStreamDestroy(stream_);
     for (hipStream_t st : prep_streams_) (void)hipStreamDestroy(st);
     for (auto &kv : jobs_) delete kv.second->result;
@@ -311,82 +336,82 @@ int grow(DeviceArray<T> &d, size_t count) {
 }
 }  // namespace
 
-// Downloads, for every job, the supports of the candidates its top-rank list
-// update looks at first (gathered on the device into one buffer); job i's
-// land at h_first_.p + (*at)[i].
-int Server::fetch_first_supports(const std::vector<std::shared_ptr<ServerJob>> &active,
+// Downloads, for every job of the tick, the supports of the candidates its
+// top-rank list update looks at first (gathered on the device into one
+// buffer); job i's land at sl.h_first.p + (*at)[i].
+int Server::fetch_first_supports(Slot &sl, const std::vector<std::shared_ptr<ServerJob>> &jobs,
                                  const std::vector<std::vector<int32_t>> &first,
                                  std::vector<size_t> *at) {
-    const size_t n = active.size();
+    const size_t n = jobs.size();
     at->assign(n + 1, 0);
     size_t spans = 0;
     for (size_t i = 0; i < n; i++) {
-        (*at)[i + 1] = (*at)[i] + first[i].size() * (size_t)active[i]->job->words();
+        (*at)[i + 1] = (*at)[i] + first[i].size() * (size_t)jobs[i]->job->words();
         spans += first[i].size();
     }
     if (spans == 0) return EBIC_OK;
-    int rc = grow(h_spans_, d_spans_, spans);
-    if (rc == EBIC_OK) rc = grow(h_first_, d_first_, (*at)[n]);
+    int rc = grow(sl.h_spans, sl.d_spans, spans);
+    if (rc == EBIC_OK) rc = grow(sl.h_first, sl.d_first, (*at)[n]);
     if (rc) return rc;
     size_t q = 0;
     for (size_t i = 0; i < n; i++) {
-        const Job &jb = *active[i]->job;
+        const Job &jb = *jobs[i]->job;
         const int64_t W = jb.words();
         for (size_t pos = 0; pos < first[i].size(); pos++)
-            h_spans_.p[q++] = WordSpan{jb.device_supports() + (size_t)first[i][pos] * W,
-                                       (uint64_t)((*at)[i] + pos * W), W};
+            sl.h_spans.p[q++] = WordSpan{jb.device_supports() + (size_t)first[i][pos] * W,
+                                         (uint64_t)((*at)[i] + pos * W), W};
     }
-    EBIC_HIP(hipMemcpyAsync(d_spans_.p, h_spans_.p, sizeof(WordSpan) * spans,
+    EBIC_HIP(hipMemcpyAsync(sl.d_spans.p, sl.h_spans.p, sizeof(WordSpan) * spans,
                             hipMemcpyHostToDevice, stream_));
-    rc = launch_gather_spans(d_spans_.p, (int32_t)spans, d_first_.p, stream_);
+    rc = launch_gather_spans(sl.d_spans.p, (int32_t)spans, sl.d_first.p, stream_);
     if (rc) return rc;
-    EBIC_HIP(hipMemcpyAsync(h_first_.p, d_first_.p, sizeof(uint64_t) * (*at)[n],
+    EBIC_HIP(hipMemcpyAsync(sl.h_first.p, sl.d_first.p, sizeof(uint64_t) * (*at)[n],
                             hipMemcpyDeviceToHost, stream_));
     EBIC_HIP(hipStreamSynchronize(stream_));
     return EBIC_OK;
 }
 
-void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
-    const size_t n = active.size();
+// One tick over the jobs whose previous host step is done: pack (worker
+// pool, largest populations first), one upload, one launch, one download of
+// scores and counts, candidate order, the first candidates' supports; then
+// every job's host step is queued as its own task, reading the slot's
+// buffers, which stay reserved until the last of those steps has finished.
+void Server::tick(std::vector<std::shared_ptr<ServerJob>> &jobs, Slot &sl) {
+    const size_t n = jobs.size();
     std::vector<ebic_job> views(n);
-    // the pool takes the largest populations first, so the slowest job's
-    // host work does not start last
-    std::vector<size_t> lpt(n);
-    std::iota(lpt.begin(), lpt.end(), 0);
-    std::stable_sort(lpt.begin(), lpt.end(), [&](size_t a, size_t b) {
-        return active[a]->params.population > active[b]->params.population;
+    std::stable_sort(jobs.begin(), jobs.end(), [](const std::shared_ptr<ServerJob> &a,
+                                                   const std::shared_ptr<ServerJob> &b) {
+        return a->params.population > b->params.population;
     });
     const double t0 = now_s();
-    // every job's slices of the shared staging buffers
     std::vector<size_t> in_at(n + 1, 0), out_at(n + 1, 0), sup_at(n + 1, 0);
     for (size_t i = 0; i < n; i++) {
         size_t ib = 0, ob = 0, sb = 0;
-        active[i]->job->slice_bytes(&ib, &ob, &sb);
+        jobs[i]->job->slice_bytes(&ib, &ob, &sb);
         in_at[i + 1] = in_at[i] + ib;
         out_at[i + 1] = out_at[i] + ob;
         sup_at[i + 1] = sup_at[i] + sb;
     }
-    int rc = grow(h_in_, d_in_, in_at[n]);
-    if (rc == EBIC_OK) rc = grow(h_out_, d_out_, out_at[n]);
-    if (rc == EBIC_OK) rc = grow(d_sup_, sup_at[n]);
-    // host packing of every job in parallel, then one upload
+    int rc = grow(sl.h_in, sl.d_in, in_at[n]);
+    if (rc == EBIC_OK) rc = grow(sl.h_out, sl.d_out, out_at[n]);
+    if (rc == EBIC_OK) rc = grow(sl.d_sup, sup_at[n]);
     if (rc == EBIC_OK)
-        pool_->run(n, [&](size_t q) {
-            const size_t i = lpt[q];
-            active[i]->job->stage_into(&views[i], h_in_.p + in_at[i], d_in_.p + in_at[i],
-                                       h_out_.p + out_at[i], d_out_.p + out_at[i],
-                                       d_sup_.p + sup_at[i]);
+        pool_->parallel(n, [&](size_t i) {
+            jobs[i]->job->stage_into(&views[i], sl.h_in.p + in_at[i], sl.d_in.p + in_at[i],
+                                     sl.h_out.p + out_at[i], sl.d_out.p + out_at[i],
+                                     sl.d_sup.p + sup_at[i]);
         });
     const double t1 = now_s();
     if (rc == EBIC_OK) {
         const hipError_t e =
-            hipMemcpyAsync(d_in_.p, h_in_.p, in_at[n], hipMemcpyHostToDevice, stream_);
+            hipMemcpyAsync(sl.d_in.p, sl.h_in.p, in_at[n], hipMemcpyHostToDevice, stream_);
         if (e != hipSuccess) rc = check_hip(e, "hipMemcpyAsync");
     }
-    if (rc == EBIC_OK) rc = batch_set(&batch_, views.data(), (int32_t)n, stream_);
-    if (rc == EBIC_OK) rc = batch_run(batch_, stream_);
+    if (rc == EBIC_OK) rc = batch_set(&sl.batch, views.data(), (int32_t)n, stream_);
+    if (rc == EBIC_OK) rc = batch_run(sl.batch, stream_);
     if (rc == EBIC_OK) {
-        hipError_t e = hipMemcpyAsync(h_out_.p, d_out_.p, out_at[n], hipMemcpyDeviceToHost, stream_);
+        hipError_t e =
+            hipMemcpyAsync(sl.h_out.p, sl.d_out.p, out_at[n], hipMemcpyDeviceToHost, stream_);
         if (e == hipSuccess) e = hipStreamSynchronize(stream_);
         if (e != hipSuccess) rc = check_hip(e, "download");
     }
@@ -396,10 +421,9 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
     std::vector<std::vector<int32_t>> first(n);
     const double t2a = now_s();
     if (rc == EBIC_OK)
-        pool_->run(n, [&](size_t q) {
-            const size_t i = lpt[q];
-            const size_t m = 2 * (size_t)std::max(active[i]->params.archive_size, 0) + 8;
-            st[i] = active[i]->job->plan(m, &first[i]);
+        pool_->parallel(n, [&](size_t i) {
+            const size_t m = 2 * (size_t)std::max(jobs[i]->params.archive_size, 0) + 8;
+            st[i] = jobs[i]->job->plan(m, &first[i]);
             if (st[i]) {
                 msg[i] = ebic_last_error();
                 first[i].clear();
@@ -408,7 +432,7 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
     const double t2b = now_s();
     std::vector<size_t> first_at;
     if (rc == EBIC_OK) {
-        rc = fetch_first_supports(active, first, &first_at);
+        rc = fetch_first_supports(sl, jobs, first, &first_at);
         if (rc) {
             const std::string e = ebic_last_error();
             for (size_t i = 0; i < n; i++)
@@ -418,40 +442,45 @@ void Server::tick(std::vector<std::shared_ptr<ServerJob>> &active) {
                 }
         }
     }
-    const double t2 = now_s();
-    if (rc == EBIC_OK)
-        pool_->run(n, [&](size_t q) {
-            const size_t i = lpt[q];
-            if (st[i]) return;
-            (void)hipSetDevice(device_);
-            if (!first[i].empty()) active[i]->job->set_first_supports(h_first_.p + first_at[i]);
-            st[i] = active[i]->job->advance();
-            if (st[i]) msg[i] = ebic_last_error();
-        });
     const double t3 = now_s();
-    std::vector<std::shared_ptr<ServerJob>> keep, ended;
-    for (size_t i = 0; i < active.size(); i++) {
-        auto &j = active[i];
-        if (st[i] == EBIC_OK && !j->job->done()) {
-            keep.push_back(j);
-            continue;
-        }
-        j->end_status = st[i];
-        if (st[i] == EBIC_OK)
-            j->result = j->job->take_result();
-        else
-            j->end_error = msg[i];
-        ended.push_back(j);
-    }
+    std::vector<std::shared_ptr<ServerJob>> failed;
     {
         std::lock_guard<std::mutex> lk(mu_);
         ticks_++;
         stage_s_ += t1 - t0;
-        device_s_ += (t2a - t1) + (t2 - t2b);
-        host_s_ += (t2b - t2a) + (t3 - t2);
+        device_s_ += (t2a - t1) + (t3 - t2b);
+        host_s_ += t2b - t2a;
+        for (size_t i = 0; i < n; i++)
+            if (st[i] == EBIC_OK) sl.pending++;
     }
-    active.swap(keep);
-    end_jobs(ended);
+    for (size_t i = 0; i < n; i++) {
+        auto j = jobs[i];
+        if (st[i] != EBIC_OK) {
+            j->end_status = st[i];
+            j->end_error = msg[i];
+            failed.push_back(j);
+            continue;
+        }
+        if (!first[i].empty()) j->job->set_first_supports(sl.h_first.p + first_at[i]);
+        Slot *slot = &sl;
+        pool_->submit([this, j, slot] {
+            (void)hipSetDevice(device_);
+            const double a = now_s();
+            const int s = j->job->advance();
+            std::string e = s ? ebic_last_error() : "";
+            const double b = now_s();
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                host_s_ += b - a;
+                j->end_status = s;
+                j->end_error = std::move(e);
+                host_done_.push_back(j);
+                slot->pending--;
+            }
+            cv_work_.notify_all();
+        });
+    }
+    end_jobs(failed);
 }
 
 // Publishes the ended jobs' results (status in ServerJob::end_status)
@@ -554,12 +583,20 @@ void Server::prepare_loop(hipStream_t stream) {
 
 void Server::loop() {
     (void)hipSetDevice(device_);
-    std::vector<std::shared_ptr<ServerJob>> active;
+    std::vector<std::shared_ptr<ServerJob>> idle;  // scores wanted: prepared or stepped
     for (;;) {
+        std::vector<std::shared_ptr<ServerJob>> ended;
+        Slot *free_slot = nullptr;
         {
             std::unique_lock<std::mutex> lk(mu_);
+            auto slot_free = [&] {
+                for (Slot &s : slots_)
+                    if (s.pending == 0) return &s;
+                return static_cast<Slot *>(nullptr);
+            };
             cv_work_.wait(lk, [&] {
-                return stop_ || !active.empty() || !ready_.empty() || admissible();
+                return stop_ || !ready_.empty() || !host_done_.empty() || admissible() ||
+                       (!idle.empty() && slot_free());
             });
             if (stop_ && !queue_.empty()) {  // queued jobs are dropped; admitted ones finish
                 while (!queue_.empty()) {
@@ -586,18 +623,26 @@ void Server::loop() {
             }
             if (admitted) cv_prep_.notify_all();
             while (!ready_.empty()) {
-                active.push_back(ready_.front());
+                idle.push_back(ready_.front());
                 ready_.pop_front();
             }
+            while (!host_done_.empty()) {
+                auto j = host_done_.front();
+                host_done_.pop_front();
+                if (j->end_status != EBIC_OK || j->job->done())
+                    ended.push_back(j);
+                else
+                    idle.push_back(j);
+            }
+            free_slot = slot_free();
         }
-        if (active.empty()) {
-            // nothing to tick: wait for the preparer or a release
-            std::unique_lock<std::mutex> lk(mu_);
-            cv_work_.wait(lk, [&] { return !ready_.empty() || admissible() || (stop_ && n_active_ == 0); });
-            continue;
-        }
+        for (auto &j : ended)
+            if (j->end_status == EBIC_OK) j->result = j->job->take_result();
+        end_jobs(ended);
+        if (idle.empty() || !free_slot) continue;
         const double t0 = now_s();
-        tick(active);
+        tick(idle, *free_slot);
+        idle.clear();
         std::lock_guard<std::mutex> lk(mu_);
         busy_s_ += now_s() - t0;
     }
