@@ -31,6 +31,8 @@ namespace {
 
 // Threads (each with a stream) setting admitted jobs up beside the ticks.
 constexpr int kPreparers = 3;
+// Longest wait, in microseconds, for more jobs to join a tick.
+constexpr int kGather = 500;
 
 double now_s() {
     using namespace std::chrono;
@@ -639,7 +641,45 @@ void Server::loop() {
         for (auto &j : ended)
             if (j->end_status == EBIC_OK) j->result = j->job->take_result();
         end_jobs(ended);
+        ended.clear();
         if (idle.empty() || !free_slot) continue;
+        {
+            // a short window for more jobs to finish their host steps while
+            // fewer than half of the running ones want scores, so a launch
+            // carries more than a few populations
+            std::unique_lock<std::mutex> lk(mu_);
+            const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(kGather);
+            auto stepping = [&] {
+                size_t n = 0;
+                for (const Slot &sl : slots_) n += (size_t)sl.pending;
+                return n;
+            };
+            while (!stop_ && 2 * idle.size() < idle.size() + stepping() &&
+                   cv_work_.wait_until(lk, until) != std::cv_status::timeout) {
+                while (!host_done_.empty()) {
+                    auto j = host_done_.front();
+                    host_done_.pop_front();
+                    if (j->end_status != EBIC_OK || j->job->done())
+                        ended.push_back(j);
+                    else
+                        idle.push_back(j);
+                }
+            }
+            while (!host_done_.empty()) {
+                auto j = host_done_.front();
+                host_done_.pop_front();
+                if (j->end_status != EBIC_OK || j->job->done())
+                    ended.push_back(j);
+                else
+                    idle.push_back(j);
+            }
+        }
+        if (!ended.empty()) {
+            for (auto &j : ended)
+                if (j->end_status == EBIC_OK) j->result = j->job->take_result();
+            end_jobs(ended);
+            ended.clear();
+        }
         const double t0 = now_s();
         tick(idle, *free_slot);
         idle.clear();
