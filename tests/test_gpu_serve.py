@@ -92,6 +92,28 @@ def test_many_clashing_candidates_in_the_mix(E):
     srv.close()
 
 
+def test_many_small_jobs_churn(E):
+    """Forty small jobs of mixed shapes, at most eight resident: ticks take
+    whichever jobs have finished their host steps, staging slots are reused
+    many times over, and every job still equals its run alone."""
+    rng = np.random.default_rng(91)
+    jobs = []
+    for j in range(40):
+        R, C = int(rng.integers(60, 900)), int(rng.integers(8, 60))
+        X = synth.random_matrix(R, C, seed=900 + j)
+        kw = _kw(R, C, int(rng.choice([32, 64, 128, 256])), int(rng.integers(2, 7)),
+                 neg=int(j % 2), k_max=min(12, C), tie_rule=int(j % 3))
+        jobs.append((X, kw, 950 + j))
+    alone = [E.ebic_run(X, E.make_params(**kw), seed) for X, kw, seed in jobs]
+    srv = E.Server(max_active=8)
+    ids = [srv.submit(X, E.make_params(**kw), seed) for X, kw, seed in jobs]
+    for a, i in zip(alone, ids):
+        _same(a, srv.wait(i))
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["failed"] == 0
+    srv.close()
+
+
 def test_small_budget_queues(E):
     jobs = _mix()[:4]
     alone = [E.ebic_run(X, E.make_params(**kw), seed) for X, kw, seed in jobs]
