@@ -47,9 +47,9 @@ def parse():
                     help="instead of the evaluation step, run the job-server mix: JOBS jobs "
                          "with Poisson arrivals, and print its own JSON line")
     ap.add_argument("--serving-gens", type=int, default=30)
-    ap.add_argument("--recovery", type=int, default=0, metavar="WORKLOAD",
+    ap.add_argument("--recovery", type=int, default=None, metavar="WORKLOAD",
                     help="instead of the evaluation step, run the whole method on a planted "
-                         "workload (1 or 2) with its parameters and print the clustering "
+                         "workload (0, 1 or 2) with its parameters and print the clustering "
                          "error of the biclusters found against the planted ones")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
@@ -113,7 +113,7 @@ def main():
     if args.gpus == 1 and args.serving:
         serving(args)
         return
-    if args.gpus == 1 and args.recovery:
+    if args.gpus == 1 and args.recovery is not None:
         recovery(args)
         return
     if args.gpus != 1:
