@@ -23,10 +23,13 @@
  * from integers; compile with -ffp-contract=off.
  *
  * Parity status: evaluate() is pinned (brute force, Eulerian closed forms,
- * invariants, fitness identities). The size-score and overlap-penalty
- * formulas themselves are a reading, not printed in the paper. run() is pinned
- * by RNG known-answer values, determinism and planted recovery only:
- * its trajectory is parity unpinned against the paper.
+ * invariants, fitness identities, the size-score and overlap thresholds on
+ * both sides). The size-score and overlap-penalty formulas themselves are a
+ * reading, not printed in the paper: parity unpinned beyond those
+ * identities. run() is pinned by RNG known-answer values (bounded draws
+ * against a big-integer implementation included), the canonical tabu key,
+ * determinism and planted recovery only: its trajectory is parity unpinned
+ * against the paper.
  */
 #include <math.h>
 #include <stdint.h>

@@ -381,3 +381,121 @@ def test_ce_score_brute_force_assignment():
         got = oracle.ce_score(f, t)
         if u:
             assert got == (best / u, (u - best) / u), trial
+
+
+# --- boundaries of the size score, the overlap test and the bounded draw ---
+
+def _increasing_rows(R, C, n):
+    """R x C matrix whose first n rows increase along columns 0..C-1 and the
+    rest decrease: along (0..k-1), exactly n rows keep the exact trend."""
+    up = np.tile(np.arange(C, dtype=np.float32), (n, 1))
+    down = np.tile(np.arange(C, 0, -1, dtype=np.float32), (R - n, 1))
+    return np.vstack([up, down])
+
+
+def test_size_score_thresholds():
+    """s = n 2^k once n reaches min_rows and k reaches k_score_min; one
+    below either threshold scores 0 (both comparisons inclusive)."""
+    X = _increasing_rows(30, 6, 12)
+    k = 4
+    series = [list(range(k))]
+    base = dict(approx_permille=1000, negative_trends=0, overlap_permille=750)
+    for min_rows, want in ((11, 12 * 2 ** k), (12, 12 * 2 ** k), (13, 0)):
+        ev = oracle.evaluate(X, series, params=oracle.make_params(
+            min_rows=min_rows, k_score_min=2, **base))
+        assert ev.count[0] == 12
+        assert ev.score[0] == want and ev.fitness[0] == want, min_rows
+    for ksm, want in ((k - 1, 12 * 2 ** k), (k, 12 * 2 ** k), (k + 1, 0)):
+        ev = oracle.evaluate(X, series, params=oracle.make_params(
+            min_rows=1, k_score_min=ksm, **base))
+        assert ev.score[0] == want, ksm
+
+
+def test_overlap_threshold_uses_shared_columns():
+    """A member overlaps when 1000 h g > theta n k: h shared rows, g shared
+    columns. Candidate (0, 1, 2, 3) on 10 fitting rows, theta 500 per mille:
+    theta n k = 20,000. A member holding every row (h = 10) halves the score
+    only when it shares 3 of the 4 columns (30,000); at 2 shared columns the
+    product sits exactly on the bound (20,000, not above), and a member with
+    every row but no shared column never penalises."""
+    X = _increasing_rows(20, 8, 10)
+    cand = [0, 1, 2, 3]
+    p = oracle.make_params(approx_permille=1000, negative_trends=0, overlap_permille=500,
+                           min_rows=1, k_score_min=2)
+    ev = oracle.evaluate(X, [cand], params=p)
+    n, s = int(ev.count[0]), float(ev.score[0])
+    assert n == 10 and s == 10 * 2 ** 4
+    rows = ev.support[:1].copy()
+    cases = [([4, 5, 6, 7], s),        # g = 0
+             ([0, 5, 6, 7], s),        # g = 1
+             ([0, 1, 6, 7], s),        # g = 2: exactly on the bound
+             ([7, 2, 1, 0], s / 2),    # g = 3 (order does not matter)
+             ([3, 2, 1, 0, 4], s / 2)]  # g = 4
+    for member, want in cases:
+        got = oracle.evaluate(X, [cand], archive=oracle.Archive(rows, [member]), params=p)
+        assert got.overlap[0, 0] == 10
+        assert got.fitness[0] == want, member
+    # the row side of the product: 9 shared rows and all 4 columns give
+    # 36,000 > 20,000; 5 shared rows and 4 columns sit on the bound
+    for h, want in ((9, s / 2), (5, s), (4, s)):
+        part = np.zeros_like(rows)
+        part[0, :h] = 1
+        got = oracle.evaluate(X, [cand], archive=oracle.Archive(part, [cand]), params=p)
+        assert got.overlap[0, 0] == h and got.fitness[0] == want, h
+
+
+M64 = (1 << 64) - 1
+
+
+def _splitmix64_ref(seed):
+    """SplitMix64 in Python integers (the published generator: golden-ratio
+    increment, variant-13 finaliser), as an independent implementation."""
+    s = seed
+    while True:
+        s = (s + 0x9E3779B97F4A7C15) & M64
+        z = s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        yield z ^ (z >> 31)
+
+
+def _uniform_ref(gen, n):
+    """x mod n of the first draw x at or above 2^64 mod n."""
+    low = (1 << 64) % n
+    while True:
+        x = next(gen)
+        if x >= low:
+            return x % n
+
+
+@pytest.mark.parametrize("n", [(1 << 63) + 1, 3 << 62, 10 ** 18 + 7])
+def test_uniform_draw_rejection_large_bounds(n):
+    """Bounds where rejection happens often (about 1/2, 1/4 and 1/41 of the
+    draws): the oracle's stream equals a big-integer implementation, and for
+    3 * 2^62 (where dropping the rejection would put half the draws below
+    2^62) about a third of the draws fall below 2^62."""
+    for seed in (1, 2, 3):
+        ref = _splitmix64_ref(seed)
+        want = [_uniform_ref(ref, n) for _ in range(1000)]
+        assert oracle.uniform_stream(seed, [n] * 1000) == want
+    if n == 3 << 62:
+        xs = oracle.uniform_stream(77, [n] * 3000)
+        frac = sum(x < (1 << 62) for x in xs) / len(xs)
+        assert abs(frac - 1 / 3) < 0.05, frac
+
+
+def test_reversed_series_share_a_tabu_entry():
+    """Three columns, series of exactly three: six series, three up to
+    reversal. With reversed trends on, a series and its reverse are one
+    tabu entry, so once the first population holds one of each pair every
+    mutant (a swap, or a full-length crossover child) is a tabu hit and the
+    run stops after one generation; with them off three fresh series remain
+    and the run goes on."""
+    X = synth.random_matrix(12, 3, seed=4)
+    base = dict(k_min=3, k_max=3, population=3, generations=20, max_tabu_hits=40,
+                min_rows=1, n_out=3)
+    for seed in (1, 2, 3, 4):
+        on = oracle.run(X, _c0_params(negative_trends=1, k_score_min=3, **base), seed=seed)
+        assert (on.generations, on.stop_reason, on.tabu_hits) == (1, 2, 40), seed
+        off = oracle.run(X, _c0_params(negative_trends=0, k_score_min=2, **base), seed=seed)
+        assert off.generations >= 2, seed
