@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in (
         "approx_permille", "negative_trends", "overlap_permille", "min_rows", "k_score_min",
         "k_min", "k_max", "archive_size", "n_out", "population", "generations",
-        "max_tabu_hits", "tournament", "max_attempts", "tie_rule")]
+        "max_tabu_hits", "tournament", "max_attempts", "tie_rule")] + \
+        [("op_permille", ctypes.c_int32 * 5)]
 
 
 class _Result(ctypes.Structure):
@@ -65,11 +66,16 @@ DEFAULTS = dict(approx_permille=850, negative_trends=0, overlap_permille=750, mi
 
 
 def make_params(**kw) -> Params:
+    """Parameters with the defaults above; op_permille (insertion, deletion,
+    substitution, swap, crossover weights, per mille) defaults to 200 each."""
     d = dict(DEFAULTS)
     if "negative_trends" in kw and "k_score_min" not in kw:
         d["k_score_min"] = 3 if kw["negative_trends"] else 2
     d.update(kw)
-    return Params(**d)
+    ops = d.pop("op_permille", (200,) * 5)
+    p = Params(**d)
+    p.op_permille[:] = list(ops)
+    return p
 
 
 _lib = None
@@ -95,6 +101,11 @@ def lib():
         L.oracle_splitmix64_next.argtypes = [P(ctypes.c_uint64)]
         L.oracle_uniform.restype = ctypes.c_uint64
         L.oracle_uniform.argtypes = [P(ctypes.c_uint64), ctypes.c_uint64]
+        L.oracle_mutants.restype = ctypes.c_int
+        L.oracle_mutants.argtypes = [P(ctypes.c_int32), P(ctypes.c_uint16), ctypes.c_int,
+                                     P(ctypes.c_double), ctypes.c_int, P(Params),
+                                     ctypes.c_uint64, ctypes.c_int, P(ctypes.c_int32),
+                                     P(ctypes.c_uint16)]
         _lib = L
     return _lib
 
@@ -212,6 +223,25 @@ def run(X: np.ndarray, params: Params, seed: int, nthreads: int = 1) -> RunResul
            for j in range(int(count[0]))]
     g = int(stats[0])
     return RunResult(bcs, g, int(stats[1]), int(stats[2]), int(stats[3]), trace[:g].copy())
+
+
+def mutants(seqs: Sequence[Sequence[int]], C: int, params: Params, seed: int, n: int,
+            key: Optional[Sequence[float]] = None) -> List[np.ndarray]:
+    """n mutation attempts (tournament, operator, child) from the population
+    seqs with tournament keys `key` (default all equal). An attempt in which
+    no weighted operator applies gives an empty child."""
+    off, cols = _csr(seqs)
+    P = len(seqs)
+    k = np.ascontiguousarray(key if key is not None else np.zeros(P), dtype=np.float64)
+    lens = np.zeros(max(n, 1), np.int32)
+    out = np.zeros((max(n, 1), K_LIMIT), np.uint16)
+    rc = lib().oracle_mutants(_ptr(off, ctypes.c_int32), _ptr(cols, ctypes.c_uint16), P,
+                              _ptr(k, ctypes.c_double), C, ctypes.byref(params),
+                              ctypes.c_uint64(seed), n, _ptr(lens, ctypes.c_int32),
+                              _ptr(out, ctypes.c_uint16))
+    if rc != 0:
+        raise ValueError("oracle_mutants: invalid argument")
+    return [out[i, :min(lens[i], K_LIMIT)].astype(np.int64) for i in range(n)]
 
 
 def splitmix64_stream(seed: int, count: int) -> List[int]:

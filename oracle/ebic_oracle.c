@@ -54,6 +54,9 @@ typedef struct oracle_params {
     int32_t max_attempts;      /* attempts per population slot                */
     int32_t tie_rule;          /* equal values: 0 by column index, 1 strict,  */
                                /* 2 loose (see step_counts)                   */
+    int32_t op_permille[5];    /* weights of insertion, deletion,             */
+                               /* substitution, swap, crossover: per mille,   */
+                               /* summing to 1000; all 0 means 200 each       */
 } oracle_params;
 
 /* ------------------------------------------------------------------------ */
@@ -529,20 +532,39 @@ static int tournament(ga_state *G, const double *key, int P)
     return best;
 }
 
-enum { OP_INSERT, OP_DELETE, OP_SUBST, OP_SWAP, OP_CROSS };
+enum { OP_INSERT, OP_DELETE, OP_SUBST, OP_SWAP, OP_CROSS, OP_COUNT };
 
-/* One mutation attempt from the old population (step 5). */
+/* Weight of operator o (the paper names the five operators, Sec. 2.3, and
+ * no probabilities: a parameter, uniform by default). */
+static int op_weight(const oracle_params *p, int o)
+{
+    int any = 0;
+    for (int q = 0; q < OP_COUNT; q++) any |= p->op_permille[q];
+    return any ? p->op_permille[o] : 200;
+}
+
+/* One mutation attempt from the old population (step 5). The operator is
+ * drawn among those that apply to the parent (insertion needs k < k_max
+ * and k < C, deletion k > k_min, substitution k < C), in proportion to
+ * their weights; when none of them has weight the attempt fails (the child
+ * is left empty, outside every length range). */
 static void mutate(ga_state *G, const series *pop, const double *key, int P, series *child)
 {
     const oracle_params *p = G->p;
     const series *I = &pop[tournament(G, key, P)];
     int k = I->k, op;
-    for (;;) {
-        op = (int)oracle_uniform(&G->rng, 5);
-        if (op == OP_INSERT && !(k < p->k_max && k < G->C)) continue;
-        if (op == OP_DELETE && !(k > p->k_min)) continue;
-        if (op == OP_SUBST && !(k < G->C)) continue;
-        break;
+    int applies[OP_COUNT] = {k < p->k_max && k < G->C, k > p->k_min, k < G->C, 1, 1};
+    int total = 0;
+    for (int o = 0; o < OP_COUNT; o++) total += applies[o] * op_weight(p, o);
+    if (total == 0) {
+        child->k = 0;
+        return;
+    }
+    int x = (int)oracle_uniform(&G->rng, (uint64_t)total);
+    for (op = 0;; op++) {
+        int w = applies[op] * op_weight(p, op);
+        if (x < w) break;
+        x -= w;
     }
     *child = *I;
     if (op == OP_INSERT) {
@@ -585,6 +607,50 @@ static void mutate(ga_state *G, const series *pop, const double *key, int P, ser
     }
 }
 
+/* Operator weights: each 0..1000 and summing to 1000, or all 0. */
+static int ops_valid(const oracle_params *p)
+{
+    int sum = 0;
+    for (int o = 0; o < OP_COUNT; o++) {
+        if (p->op_permille[o] < 0 || p->op_permille[o] > 1000) return 0;
+        sum += p->op_permille[o];
+    }
+    return sum == 0 || sum == 1000;
+}
+
+/* n mutation attempts (step 5) from a population given in CSR form, with
+ * tournament keys `key` and the generator seeded with `seed`: child i goes
+ * to child_cols[i * ORACLE_K_LIMIT ..], its length to child_len[i] (0 when
+ * no weighted operator applied; a crossover child longer than the storage
+ * keeps only its first ORACLE_K_LIMIT columns). Exposes the operators for
+ * testing. Returns 0, or -1 for an invalid argument. */
+int oracle_mutants(const int32_t *offsets, const uint16_t *cols, int P, const double *key,
+                   int C, const oracle_params *p, uint64_t seed, int n, int32_t *child_len,
+                   uint16_t *child_cols)
+{
+    if (P < 1 || C < 2 || n < 0 || !p || !ops_valid(p) || p->tournament < 1) return -1;
+    series *pop = malloc(sizeof(series) * P);
+    if (!pop) return -1;
+    for (int i = 0; i < P; i++) {
+        int k = offsets[i + 1] - offsets[i];
+        if (k < 2 || k > ORACLE_K_LIMIT) { free(pop); return -1; }
+        pop[i].k = k;
+        memcpy(pop[i].c, cols + offsets[i], sizeof(uint16_t) * k);
+    }
+    ga_state G;
+    memset(&G, 0, sizeof G);
+    G.C = C; G.p = p; G.rng = seed;
+    for (int i = 0; i < n; i++) {
+        series child;
+        mutate(&G, pop, key, P, &child);
+        child_len[i] = child.k;
+        int stored = child.k < ORACLE_K_LIMIT ? child.k : ORACLE_K_LIMIT;
+        memcpy(child_cols + (size_t)i * ORACLE_K_LIMIT, child.c, sizeof(uint16_t) * stored);
+    }
+    free(pop);
+    return 0;
+}
+
 /* Result of run(); caller-allocated arrays sized by n_out, R and G. */
 typedef struct {
     int32_t *count;         /* biclusters written                      */
@@ -607,7 +673,7 @@ int oracle_run(const float *X, int R, int C, const oracle_params *p, uint64_t se
         p->k_max > ORACLE_K_LIMIT || p->k_max > C || p->population < 1 ||
         p->generations < 1 || p->archive_size < 1 || p->archive_size > 64 ||
         p->n_out < 0 || p->tournament < 1 || p->max_attempts < 1 || p->max_tabu_hits < 1 ||
-        p->approx_permille < 0 || p->approx_permille > 1000)
+        p->approx_permille < 0 || p->approx_permille > 1000 || !ops_valid(p))
         return -1;
     ga_state G;
     memset(&G, 0, sizeof G);

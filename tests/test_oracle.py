@@ -499,3 +499,171 @@ def test_reversed_series_share_a_tabu_entry():
         assert (on.generations, on.stop_reason, on.tabu_hits) == (1, 2, 40), seed
         off = oracle.run(X, _c0_params(negative_trends=0, k_score_min=2, **base), seed=seed)
         assert off.generations >= 2, seed
+
+
+# --- the five operators (Sec. 2.3) and their weights ---
+
+def _member_pop(rng, C, per, lens):
+    """`per` random series of each length in `lens`."""
+    return [list(map(int, rng.permutation(C)[:k])) for k in lens for _ in range(per)]
+
+
+def _insertion_of(c, m):
+    """Position where c inserts one new column into m, or None."""
+    if len(c) != len(m) + 1:
+        return None
+    for pos in range(len(c)):
+        if c[:pos] + c[pos + 1:] == m and c[pos] not in m:
+            return pos
+    return None
+
+
+def _deletion_of(c, m):
+    if len(c) != len(m) - 1:
+        return None
+    for pos in range(len(m)):
+        if m[:pos] + m[pos + 1:] == c:
+            return pos
+    return None
+
+
+def _substitution_of(c, m):
+    if len(c) != len(m):
+        return None
+    diff = [i for i in range(len(m)) if c[i] != m[i]]
+    return diff[0] if len(diff) == 1 and c[diff[0]] not in m else None
+
+
+def _swap_of(c, m):
+    if len(c) != len(m):
+        return None
+    diff = [i for i in range(len(m)) if c[i] != m[i]]
+    if len(diff) == 2 and c[diff[0]] == m[diff[1]] and c[diff[1]] == m[diff[0]]:
+        return tuple(diff)
+    return None
+
+
+def _crossover_cuts(c, I, J):
+    """(a, b) with c = I[:a] followed by the columns of J[b:] not in I[:a]."""
+    cuts = []
+    for a in range(1, len(I)):
+        for b in range(1, len(J)):
+            head = I[:a]
+            if head + [x for x in J[b:] if x not in head] == c:
+                cuts.append((a, b))
+    return cuts
+
+
+OPS = ("insertion", "deletion", "substitution", "swap", "crossover")
+
+
+@pytest.mark.parametrize("op", range(5))
+def test_each_operator_alone(op):
+    """With all the weight on one operator every child is that operator's
+    result from some member of the population, and the drawn positions
+    cover their whole ranges: insertion at 0..k (k = at the end), deletion,
+    substitution and swap positions 0..k-1, crossover cuts 1..k-1."""
+    rng = np.random.default_rng(31 + op)
+    C = 30
+    pop = _member_pop(rng, C, 3, [3, 4, 5, 6])
+    w = [0] * 5
+    w[op] = 1000
+    p = oracle.make_params(k_min=2, k_max=8, tournament=1, op_permille=w)
+    kids = [list(map(int, c)) for c in oracle.mutants(pop, C, p, seed=5 + op, n=3000)]
+    seen = set()
+    for c in kids:
+        found = False
+        for m in pop:
+            if op == 0:
+                pos = _insertion_of(c, m)
+                ok = pos is not None
+                if ok:
+                    seen.add((len(m), pos))
+            elif op == 1:
+                pos = _deletion_of(c, m)
+                ok = pos is not None
+                if ok:
+                    seen.add((len(m), pos))
+            elif op == 2:
+                pos = _substitution_of(c, m)
+                ok = pos is not None
+                if ok:
+                    seen.add((len(m), pos))
+            elif op == 3:
+                ij = _swap_of(c, m)
+                ok = ij is not None
+                if ok:
+                    seen.update((len(m), q) for q in ij)
+            else:
+                cuts = [ab for J in pop for ab in _crossover_cuts(c, m, J)]
+                ok = bool(cuts)
+                if ok:
+                    seen.update((len(m), a) for a, _ in cuts)
+            if ok:
+                found = True
+                break
+        assert found, (OPS[op], c)
+    for k in (3, 4, 5, 6):
+        if op == 0:
+            want = set(range(k + 1))
+        elif op == 4:
+            want = set(range(1, k))
+        else:
+            want = set(range(k))
+        assert {pos for kk, pos in seen if kk == k} >= want, (OPS[op], k)
+
+
+def test_operator_weights_distribution():
+    """Members with disjoint columns, so a child's operator is read off its
+    shape: one longer (insertion), one shorter (deletion), the same columns
+    in another order (swap), one column replaced (substitution). Weights
+    100/200/300/400/0 per mille give those shares of 20,000 children
+    (chi-square, 3 degrees of freedom)."""
+    C = 60
+    pop = [list(range(4 * i, 4 * i + 4)) for i in range(15)]
+    sets = [set(m) for m in pop]
+    p = oracle.make_params(k_min=2, k_max=8, op_permille=[100, 200, 300, 400, 0])
+    kids = oracle.mutants(pop, C, p, seed=9, n=20000)
+    counts = np.zeros(4)
+    for c in kids:
+        c = list(map(int, c))
+        if len(c) == 5:
+            counts[0] += 1
+        elif len(c) == 3:
+            counts[1] += 1
+        elif set(c) in sets:
+            counts[3] += 1
+        else:
+            counts[2] += 1
+    want = np.array([0.1, 0.2, 0.3, 0.4]) * len(kids)
+    chi2 = (((counts - want) ** 2) / want).sum()
+    assert chi2 < 16.3, counts  # p = 0.001
+
+
+def test_operator_applicability():
+    """At k = k_max insertion does not apply: with weights on insertion and
+    deletion only, every child is a deletion; with all the weight on
+    insertion no operator applies and every attempt gives no child."""
+    C = 30
+    pop = [list(range(3 * i, 3 * i + 6)) for i in range(4)]  # k = 6 = k_max
+    p = oracle.make_params(k_min=2, k_max=6, op_permille=[500, 500, 0, 0, 0])
+    for c in oracle.mutants(pop, C, p, seed=3, n=500):
+        assert len(c) == 5
+    p = oracle.make_params(k_min=2, k_max=6, op_permille=[1000, 0, 0, 0, 0])
+    assert all(len(c) == 0 for c in oracle.mutants(pop, C, p, seed=3, n=50))
+    # k = C: neither insertion nor substitution applies
+    full = [[0, 1, 2], [2, 0, 1]]
+    p = oracle.make_params(k_min=3, k_max=3, op_permille=[300, 0, 300, 400, 0])
+    for c in oracle.mutants(full, 3, p, seed=4, n=300):
+        assert sorted(c) == [0, 1, 2] and len(c) == 3
+
+
+def test_operator_weights_validated_and_default():
+    X = synth.random_matrix(20, 6, seed=1)
+    for bad in ([200, 200, 200, 200, 199], [-1, 201, 200, 200, 400], [1001, 0, 0, 0, -1]):
+        with pytest.raises(ValueError):
+            oracle.run(X, _c0_params(k_max=4, generations=2, op_permille=bad), seed=1)
+    a = oracle.run(X, _c0_params(k_max=4, generations=5, op_permille=[0] * 5), seed=2)
+    b = oracle.run(X, _c0_params(k_max=4, generations=5), seed=2)
+    np.testing.assert_array_equal(a.trace, b.trace)
+    assert a.tabu_hits == b.tabu_hits
