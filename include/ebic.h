@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define EBIC_VERSION 100 /* 0.1.0 */
+#define EBIC_VERSION 200 /* 0.2.0: ebic_params gained op_permille */
 
 #define EBIC_OK 0
 #define EBIC_PENDING 1
@@ -83,6 +83,16 @@ typedef struct ebic_params {
     int32_t tournament;        /* tournament size (ebic_run)                           */
     int32_t max_attempts;      /* mutation attempts per population slot (ebic_run)     */
     int32_t tie_rule;          /* equal values in a row (EBIC_TIE_*)                    */
+    int32_t op_permille[5];    /* weights of the mutation operators (ebic_run), per
+                                  mille, in the order insertion, deletion,
+                                  substitution, swap, crossover (Sec. 2.3 names the
+                                  five): each 0..1000 and summing to 1000, or all 0
+                                  for 200 each. Each attempt draws one operator among
+                                  those that apply to the parent (insertion needs
+                                  k < k_max and k < cols, deletion k > k_min,
+                                  substitution k < cols) in proportion to its weight;
+                                  with no weighted operator applicable the attempt
+                                  fails                                                   */
 } ebic_params;
 
 /* Equal values in a row (the paper does not say how ties count; a step of a
@@ -93,8 +103,9 @@ typedef struct ebic_params {
  * EBIC_TIE_STRICT   a tie is neither: it breaks the increasing and the
  *                   decreasing trend alike;
  * EBIC_TIE_LOOSE    a tie is both: it fits either trend.
- * The pair table serves EBIC_TIE_INDEX; the batched evaluator scores the
- * other rules in the gather form. */
+ * The pair table serves EBIC_TIE_INDEX; with the strict table as well
+ * (ebic_pairs_strict_prepare) the batched evaluator scores the other two
+ * rules in the pair form too, else in the gather form. */
 #define EBIC_TIE_INDEX 0
 #define EBIC_TIE_STRICT 1
 #define EBIC_TIE_LOOSE 2
@@ -328,7 +339,7 @@ typedef struct ebic_allocator {
  * directions. Synchronous on `stream`. Errors: EBIC_ERR_INVALID_ARG (parameters:
  * 2 <= k_min <= k_max <= min(cols, 512), population >= 1, generations >= 1,
  * 1 <= archive_size <= 64, tournament >= 1, max_attempts >= 1,
- * max_tabu_hits >= 1, n_out >= 0), EBIC_ERR_NONFINITE, EBIC_ERR_OOM,
+ * max_tabu_hits >= 1, n_out >= 0, op_permille as above), EBIC_ERR_NONFINITE, EBIC_ERR_OOM,
  * EBIC_ERR_DEVICE. On success *out is set. */
 int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
              const ebic_allocator *alloc, void *stream, ebic_result **out);

@@ -65,9 +65,6 @@ constexpr int kGGroup = 8;        // archive members whose columns one pass load
 constexpr int kHGroup = 4;        // archive members whose shared rows one pass counts
 constexpr int kHWords = 3;        // support words per lane and pass when counting them
 constexpr int kArchLdsCols = 8192;  // largest archive whose columns are copied to LDS (16 KB)
-#ifndef EBIC_PIPE
-#define EBIC_PIPE 0
-#endif
 constexpr int kSchedBatch = 4;   // schedule phases loaded together
 constexpr int kSupLdsWords = 2048;  // longest support kept in LDS for the reduction (16 KB)
 
@@ -154,66 +151,6 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs,
         for (int p = 0; p < P; p++) D[v][p] = U[v][p] = ((start >> p) & 1u) ? ~0ull : 0ull;
         dov[v] = uov[v] = 0;
     }
-#if EBIC_PIPE
-    static_assert(!TWO, "the pipelined loop reads the one-bit table only");
-    // Software-pipelined: the next group's loads are issued before this
-    // group's bits are used, so two groups are in flight while the exit
-    // check still follows every group. A loaded word is kept raw with its
-    // step's inversion mask, so nothing consumes it before its turn.
-    uint64_t bc[KB][WPL], bn[KB][WPL], ic[KB], in_[KB];
-    auto issue = [&](int j0, uint64_t (&bits)[KB][WPL], uint64_t (&inv)[KB]) {
-#pragma unroll
-        for (int q = 0; q < KB; q++) {
-            const bool en = j0 + q < k;  // uniform
-            const int idx = en ? j0 + q : k - 1;
-            const int pd = __builtin_amdgcn_readfirstlane(s_pd[idx]);
-            const auto *vec = gmem(pairs) + (int64_t)(pd & 0x7fffffff) * pstride;
-            inv[q] = pd < 0 ? ~0ull : 0ull;
-#pragma unroll
-            for (int v = 0; v < WPL; v++)
-                bits[q][v] = (en && active[v]) ? vec[w + kWave * v] : 0ull;
-        }
-    };
-    int j = 1;
-    if (j < k) issue(j, bc, ic);
-    while (j < k) {
-        const int n = (k - j) < KB ? (k - j) : KB;
-        const int jn = j + n;
-        issue(jn, bn, in_);  // steps at or past k load nothing
-        uint64_t up[WPL][KB], dn[WPL][KB];
-#pragma unroll
-        for (int q = 0; q < KB; q++) {
-            const uint64_t vm = q < n ? ~0ull : 0ull;  // steps past the end count nothing
-#pragma unroll
-            for (int v = 0; v < WPL; v++) {
-                const uint64_t x = bc[q][v] ^ ic[q];  // 1 = up-step in this row
-                up[v][q] = x & vm;
-                dn[v][q] = ~x & vm;
-            }
-        }
-        bool live = false;
-#pragma unroll
-        for (int v = 0; v < WPL; v++) {
-            uint64_t S[B];
-            PartialSum<KB>::sum(dn[v], S);
-            add_sticky<P, B>(D[v], S, dov[v]);
-            if (NEG) {
-                PartialSum<KB>::sum(up[v], S);
-                add_sticky<P, B>(U[v], S, uov[v]);
-            }
-            const uint64_t dead = dov[v] & (NEG ? uov[v] : ~0ull);
-            live |= active[v] && dead != ~0ull;
-        }
-        j = jn;
-        if (__ballot(live) == 0) break;
-#pragma unroll
-        for (int q = 0; q < KB; q++) {
-            ic[q] = in_[q];
-#pragma unroll
-            for (int v = 0; v < WPL; v++) bc[q][v] = bn[q][v];
-        }
-    }
-#else
     int j = 1;
     while (j < k) {
         const int n = (k - j) < KB ? (k - j) : KB;
@@ -269,7 +206,6 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs,
         j += n;
         if (__ballot(live) == 0) break;
     }
-#endif
 #pragma unroll
     for (int v = 0; v < WPL; v++) fit[v] = ~dov[v] | (NEG ? ~uov[v] : 0ull);
 }
@@ -681,14 +617,9 @@ struct Batch {
 
 namespace {
 
-// Default chunks per item; EBIC_CHUNKS_PER_ITEM overrides it.
-int default_cpi() {
-    static const int forced = [] {
-        const char *v = getenv("EBIC_CHUNKS_PER_ITEM");
-        return v ? atoi(v) : 0;
-    }();
-    return forced > 0 ? forced : 1;
-}
+// Chunk groups per item before any tuning (ebic_batch_set_tuning or
+// EBIC_BATCH_TUNE change it).
+constexpr int kDefaultCpi = 1;
 
 int check_job(const ebic_job *j, int idx) {
     const ebic_matrix *m = &j->matrix;
@@ -1046,7 +977,7 @@ int batch_set(Batch **bp, const ebic_job *jobs, int32_t njobs, hipStream_t strea
         b->al = al;
         b->al_stream = stream;
         EBIC_HIP(hipGetDevice(&b->device));
-        b->cpi = default_cpi();
+        b->cpi = kDefaultCpi;
         *bp = b;
     }
     b->jobs.clear();
@@ -1063,7 +994,7 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
     }
     Batch *b = new Batch();
     b->flags = flags;
-    b->cpi = default_cpi();
+    b->cpi = kDefaultCpi;
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) {
         delete b;

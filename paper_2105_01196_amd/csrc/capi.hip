@@ -45,20 +45,32 @@ int check_eval_params(const ebic_params *p) {
     return EBIC_OK;
 }
 
-int device_flag(int **flag) {
-    static std::mutex mu;
-    static std::vector<int *> flags;
+namespace {
+std::mutex g_flag_mu;
+std::vector<std::vector<int *>> g_free_flags;  // per device
+constexpr int kFlagBlock = 64;                 // words per allocation
+}  // namespace
+
+int acquire_flag(int **flag, int *device) {
     int dev = 0;
     EBIC_HIP(hipGetDevice(&dev));
-    std::lock_guard<std::mutex> lock(mu);
-    if ((int)flags.size() <= dev) flags.resize(dev + 1, nullptr);
-    if (!flags[dev]) {
+    std::lock_guard<std::mutex> lock(g_flag_mu);
+    if ((int)g_free_flags.size() <= dev) g_free_flags.resize(dev + 1);
+    std::vector<int *> &free_list = g_free_flags[dev];
+    if (free_list.empty()) {
         void *p = nullptr;
-        EBIC_HIP(hipMalloc(&p, 256));
-        flags[dev] = static_cast<int *>(p);
+        EBIC_HIP(hipMalloc(&p, kFlagBlock * sizeof(int)));
+        for (int i = kFlagBlock; i-- > 0;) free_list.push_back(static_cast<int *>(p) + i);
     }
-    *flag = flags[dev];
+    *flag = free_list.back();
+    free_list.pop_back();
+    *device = dev;
     return EBIC_OK;
+}
+
+void release_flag(int *flag, int device) {
+    std::lock_guard<std::mutex> lock(g_flag_mu);
+    g_free_flags[device].push_back(flag);
 }
 
 static int check_matrix(const ebic_matrix *m) {
@@ -103,14 +115,22 @@ int ebic_matrix_prepare(const float *d_x, int32_t rows, int32_t cols, uint16_t *
         (int64_t)cols * rows_padded(rows) > INT32_MAX)
         return fail(EBIC_ERR_INVALID_ARG, "matrix shape %d x %d not supported", rows, cols);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int *flag = nullptr;
-    int rc = device_flag(&flag);
+    int *flag = nullptr, dev = 0;
+    int rc = acquire_flag(&flag, &dev);
     if (rc) return rc;
-    rc = launch_prepare(d_x, rows, cols, d_ranks, flag, s);
-    if (rc) return rc;
+    // this call's own status word, zeroed, set by the check and read back
+    // on this stream; returned to the pool once the read has landed
     int bad = 0;
-    EBIC_HIP(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s));
-    EBIC_HIP(hipStreamSynchronize(s));
+    rc = launch_prepare(d_x, rows, cols, d_ranks, flag, s);
+    if (rc == EBIC_OK) {
+        hipError_t e = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) rc = check_hip(e, "matrix status word");
+    }
+    // the word goes back to the pool only once nothing of this call can still
+    // write it; after a device error it stays out of the pool (4 bytes)
+    if (rc == EBIC_OK) release_flag(flag, dev);
+    if (rc) return rc;
     if (bad) return fail(EBIC_ERR_NONFINITE, "matrix holds NaN or infinite values");
     m->d_ranks = d_ranks;
     m->rows = rows;

@@ -43,7 +43,9 @@ __device__ inline int load_rank(__amdgpu_buffer_rsrc_t rs, int lane_off, int col
 // increasing trend when rank[a] < rank[b] + fu and the decreasing one when
 // rank[b] < rank[a] + fd, with, by tie rule: column index fu = [a < b],
 // fd = [a > b] (then exactly one of the two holds); strict fu = fd = 0;
-// loose fu = fd = 1 (offsets are in column order, so a < b is off_a < off_b).
+// loose fu = fd = 1. A column's byte offset c * rows_pad * 2 stays below 2^32
+// (cols * rows_pad < 2^31), so compared as unsigned it keeps column order:
+// a < b is off_a < off_b.
 // A row fits when at most t steps break the increasing trend, or (neg) at
 // most t break the decreasing one. The wave stops once every row is out.
 template <int RULE>
@@ -54,8 +56,9 @@ __device__ inline uint64_t block_support_rule(__amdgpu_buffer_rsrc_t rs, const i
     int prev = load_rank(rs, lane_off, off_prev);
     int inc_bad = 0, dec_bad = 0;  // steps against each trend
     auto step = [&](int off, int cur) {
-        const int fu = RULE == EBIC_TIE_INDEX ? (off_prev < off) : (RULE == EBIC_TIE_LOOSE);
-        const int fd = RULE == EBIC_TIE_INDEX ? (off_prev > off) : (RULE == EBIC_TIE_LOOSE);
+        const uint32_t ua = (uint32_t)off_prev, ub = (uint32_t)off;
+        const int fu = RULE == EBIC_TIE_INDEX ? (ua < ub) : (RULE == EBIC_TIE_LOOSE);
+        const int fd = RULE == EBIC_TIE_INDEX ? (ua > ub) : (RULE == EBIC_TIE_LOOSE);
         inc_bad += !(prev < cur + fu);
         if (RULE != EBIC_TIE_INDEX) dec_bad += !(cur < prev + fd);
         prev = cur;

@@ -26,18 +26,30 @@ __global__ void __launch_bounds__(256) check_finite_kernel(const float *__restri
     if (__ballot(bad) != 0 && (threadIdx.x % kWave) == 0) atomicOr(flag, 1);
 }
 
-// One workgroup per row. The row's values go to LDS, padded to a power of
-// two with +inf, and are sorted there (bitonic network: every stage
-// compares n/2 disjoint pairs, one per thread step, then a barrier); a
-// cell's rank, the number of cells with a smaller value, is then the lower
-// bound of its value in the sorted row (binary search). Equal values, and
-// -0 and +0, get the same rank. Padding rows (r >= rows) get rank 0; the
-// evaluators mask them out. Non-finite input is rejected by the caller
-// after the flag check, so its ranks are never used.
+// Order-preserving integer key of a finite float: -0 becomes +0, then
+// non-negative values get the sign bit set and negative ones have every
+// bit flipped, so unsigned key order is the IEEE order of the values,
+// denormals included, whatever the device's denormal mode (integer
+// compares never flush).
+__device__ inline uint32_t order_key(float v) {
+    uint32_t b = __float_as_uint(v);
+    if ((b << 1) == 0u) b = 0u;  // -0 == +0
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// One workgroup per row. The row's keys go to LDS, padded to a power of two
+// with the largest key (above every finite value's), and are sorted there
+// (bitonic network: every stage compares n/2 disjoint pairs, one per
+// thread step, then a barrier); a cell's rank, the number of cells with a
+// smaller value, is then the lower bound of its key in the sorted row
+// (binary search). Equal values, and -0 and +0, get the same rank. Padding
+// rows (r >= rows) get rank 0; the evaluators mask them out. Non-finite
+// input is rejected by the caller after the flag check, so its ranks are
+// never used.
 __global__ void __launch_bounds__(256) rank_rows_kernel(const float *__restrict__ x, int32_t rows,
                                                         int32_t cols, int32_t rows_pad, int32_t n,
                                                         uint16_t *__restrict__ ranks) {
-    extern __shared__ float s_sorted[];
+    extern __shared__ uint32_t s_sorted[];
     // Workgroups are dealt to the 8 XCDs in turn and each XCD has its own
     // L2: give XCD x the contiguous rows x * rows_pad/8 .. so that the 2-byte
     // ranks of neighbouring rows merge into whole lines in one L2 before
@@ -51,7 +63,7 @@ __global__ void __launch_bounds__(256) rank_rows_kernel(const float *__restrict_
     }
     const float *xr = x + (size_t)r * cols;
     for (int32_t c = threadIdx.x; c < n; c += blockDim.x)
-        s_sorted[c] = c < cols ? xr[c] : __builtin_inff();
+        s_sorted[c] = c < cols ? order_key(xr[c]) : 0xFFFFFFFFu;
     __syncthreads();
     for (int32_t k = 2; k <= n; k <<= 1) {
         for (int32_t lj = __builtin_ctz((uint32_t)k) - 1; lj >= 0; lj--) {
@@ -59,7 +71,7 @@ __global__ void __launch_bounds__(256) rank_rows_kernel(const float *__restrict_
             for (int32_t q = threadIdx.x; q < n / 2; q += blockDim.x) {
                 // lower index of the pair: q with a zero bit inserted at bit lj
                 const int32_t i = ((q >> lj) << (lj + 1)) | (q & (j - 1));
-                const float a = s_sorted[i], b = s_sorted[i + j];
+                const uint32_t a = s_sorted[i], b = s_sorted[i + j];
                 const bool up = (i & k) == 0;  // this run ascends
                 if ((b < a) == up) {
                     s_sorted[i] = b;
@@ -70,8 +82,8 @@ __global__ void __launch_bounds__(256) rank_rows_kernel(const float *__restrict_
         }
     }
     for (int32_t c = threadIdx.x; c < cols; c += blockDim.x) {
-        const float v = xr[c];
-        int32_t lo = 0, hi = n;  // first index whose value is not below v
+        const uint32_t v = order_key(xr[c]);
+        int32_t lo = 0, hi = n;  // first index whose key is not below v
         while (lo < hi) {
             const int32_t mid = (lo + hi) >> 1;
             if (s_sorted[mid] < v)
@@ -97,7 +109,7 @@ int launch_prepare(const float *x, int32_t rows, int32_t cols, uint16_t *ranks, 
     const int32_t rows_pad = rows_padded(rows);
     int32_t width = 2;  // the row padded to a power of two
     while (width < cols) width <<= 1;  // at most EBIC_MAX_COLS = 16,384: 64 KB of LDS
-    rank_rows_kernel<<<rows_pad, 256, (size_t)width * sizeof(float), stream>>>(
+    rank_rows_kernel<<<rows_pad, 256, (size_t)width * sizeof(uint32_t), stream>>>(
         x, rows, cols, rows_pad, width, ranks);
     EBIC_HIP(hipGetLastError());
     return EBIC_OK;

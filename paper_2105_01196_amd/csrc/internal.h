@@ -38,9 +38,13 @@ inline int tolerance(int k, int approx_permille) {
 // Host-side validation of the evaluation parameters.
 int check_eval_params(const ebic_params *p);
 
-// Per-device 4-byte status word in device memory (allocated once per device
-// on first use, kept until the process ends).
-int device_flag(int **flag);
+// 4-byte status words in device memory for matrix ingest, one per call in
+// flight: acquire_flag takes a word of the current device for the caller
+// alone (words come in blocks of 64, allocated when a device has none free
+// and kept until the process ends), release_flag returns it. Concurrent
+// ingests on several threads and streams therefore never share a word.
+int acquire_flag(int **flag, int *device);
+void release_flag(int *flag, int device);
 
 // Arguments of one evaluation, as the kernels see them.
 struct EvalJob {

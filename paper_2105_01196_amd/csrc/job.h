@@ -259,7 +259,11 @@ struct PinnedArray {
 class Job {
   public:
     Job(const ebic_params &p, uint64_t seed, hipStream_t stream)
-        : p_(p), rng_(seed), stream_(stream), neg_(p.negative_trends != 0) {}
+        : p_(p), rng_(seed), stream_(stream), neg_(p.negative_trends != 0) {
+        bool any = false;
+        for (int o = 0; o < 5; o++) any |= p.op_permille[o] != 0;
+        for (int o = 0; o < 5; o++) op_w_[o] = any ? p.op_permille[o] : 200;
+    }
 
     // Device bytes a job of this shape holds (matrix, ranks, pair table when
     // used, population, outputs, archive).
@@ -358,6 +362,7 @@ class Job {
     }
 
     ebic_params p_;
+    int32_t op_w_[5];  // operator weights (all-zero op_permille: 200 each)
     SplitMix64 rng_;
     hipStream_t stream_;
     bool neg_;

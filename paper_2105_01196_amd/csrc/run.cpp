@@ -330,13 +330,19 @@ void Job::mutate(const std::vector<Series> &pop, const std::vector<double> &key,
     const Series &par = pop[tournament(key, n)];
     const int k = (int)par.size();
     enum { INSERT, DELETE, SUBST, SWAP, CROSS };
-    int op;
-    for (;;) {
-        op = rng_.below_int(5);
-        if (op == INSERT && !(k < p_.k_max && k < C_)) continue;
-        if (op == DELETE && !(k > p_.k_min)) continue;
-        if (op == SUBST && !(k < C_)) continue;
-        break;
+    // one draw among the operators that apply, weighted
+    const bool applies[5] = {k < p_.k_max && k < C_, k > p_.k_min, k < C_, true, true};
+    int total = 0;
+    for (int o = 0; o < 5; o++) total += applies[o] ? op_w_[o] : 0;
+    if (total == 0) {  // no weighted operator applies: a failed attempt
+        child.clear();
+        return;
+    }
+    int op = 0;
+    for (int x = rng_.below_int(total);; op++) {
+        const int w = applies[op] ? op_w_[op] : 0;
+        if (x < w) break;
+        x -= w;
     }
     child.assign(par.begin(), par.end());
     switch (op) {
@@ -557,6 +563,15 @@ int check_run_params(int32_t rows, int32_t cols, const ebic_params *p) {
         p->archive_size > EBIC_MAX_ARCHIVE || p->tournament < 1 || p->max_attempts < 1 ||
         p->max_tabu_hits < 1 || p->n_out < 0)
         return fail(EBIC_ERR_INVALID_ARG, "run parameters out of range");
+    int32_t sum = 0;
+    for (int o = 0; o < 5; o++) {
+        if (p->op_permille[o] < 0 || p->op_permille[o] > 1000)
+            return fail(EBIC_ERR_INVALID_ARG, "op_permille[%d] = %d outside 0..1000", o,
+                        p->op_permille[o]);
+        sum += p->op_permille[o];
+    }
+    if (sum != 0 && sum != 1000)
+        return fail(EBIC_ERR_INVALID_ARG, "op_permille sums to %d, not 1000 (or all 0)", sum);
     return EBIC_OK;
 }
 
@@ -624,7 +639,7 @@ uint64_t matrix_hash(const float *x, size_t n) {
 namespace {
 
 constexpr char kMagic[8] = {'E', 'B', 'I', 'C', 'C', 'K', 'P', '1'};
-constexpr uint32_t kVersion = 1;
+constexpr uint32_t kVersion = 2;  // 2: ebic_params with op_permille
 
 struct Writer {
     std::vector<uint8_t> &out;

@@ -43,7 +43,8 @@ class ebic_params(ctypes.Structure):
     _fields_ = [(n, _i32) for n in (
         "approx_permille", "negative_trends", "overlap_permille", "min_rows", "k_score_min",
         "k_min", "k_max", "archive_size", "n_out", "population", "generations",
-        "max_tabu_hits", "tournament", "max_attempts", "tie_rule")]
+        "max_tabu_hits", "tournament", "max_attempts", "tie_rule")] + \
+        [("op_permille", _i32 * 5)]
 
 
 class ebic_matrix(ctypes.Structure):
@@ -224,11 +225,16 @@ DEFAULT_PARAMS = dict(approx_permille=850, negative_trends=0, overlap_permille=7
 
 
 def make_params(**kw) -> ebic_params:
+    """Parameters with the defaults above; op_permille (insertion, deletion,
+    substitution, swap, crossover weights, per mille) defaults to 200 each."""
     d = dict(DEFAULT_PARAMS)
     if "negative_trends" in kw and "k_score_min" not in kw:
         d["k_score_min"] = 3 if kw["negative_trends"] else 2
     d.update(kw)
-    return ebic_params(**d)
+    ops = d.pop("op_permille", (200,) * 5)
+    p = ebic_params(**d)
+    p.op_permille[:] = list(ops)
+    return p
 
 
 def ebic_version() -> int:

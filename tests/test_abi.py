@@ -41,7 +41,7 @@ def test_binding_covers_header():
 
 def test_host_only_calls():
     from paper_2105_01196_amd import ebic
-    assert ebic.ebic_version() == 100
+    assert ebic.ebic_version() == 200
     assert ebic.ebic_matrix_bytes(100, 20) == 20 * 128 * 2
     assert ebic.ebic_matrix_bytes(0, 20) == 0
     # pair rows: 64-bit row words rounded up to 16 (128-byte lines)
@@ -91,7 +91,9 @@ def test_run_rejects_bad_parameters_on_host():
     res = ctypes.POINTER(ebic.ebic_result)()
     for bad in (dict(k_min=1), dict(k_max=6), dict(k_min=4, k_max=3), dict(population=0),
                 dict(archive_size=65), dict(tournament=0), dict(max_tabu_hits=0),
-                dict(generations=0), dict(approx_permille=-1)):
+                dict(generations=0), dict(approx_permille=-1),
+                dict(op_permille=[200, 200, 200, 200, 199]), dict(op_permille=[-1, 201, 200, 200, 400]),
+                dict(op_permille=[1001, 0, 0, 0, -1])):
         p = ebic.make_params(**{**dict(k_min=2, k_max=4), **bad})
         rc = L.ebic_run(X.ctypes.data, 10, 5, ctypes.byref(p), 1, None, None, ctypes.byref(res))
         assert rc == ebic.EBIC_ERR_INVALID_ARG, bad

@@ -163,6 +163,55 @@ def test_large_workload_sampled(E):
     _run(E, case.X, seqs, _kw(), order=True, sample=sample)
 
 
+@pytest.mark.slow
+def test_large_workload_gather_equals_table_with_archives(E):
+    """large-40000x1000 in full: 8,192 individuals as 8 populations of
+    1,024, each against a 20-member archive (its own top 20 by score), in
+    one launch of the pair form and one of the gather form. Count, support,
+    overlap and fitness bits agree for every individual, and a sample of 256
+    individuals matches the oracle with its archive."""
+    case = synth.workload_matrix(3)
+    X, R, C = case.X, case.R, case.C
+    seqs = synth.workload_population(3, case)
+    kw = _kw()
+    m = _matrix(E, X)
+    jobs_t, jobs_g, archs = [], [], []
+    rng = np.random.default_rng(12)
+    for j in range(8):
+        part = seqs[j * 1024:(j + 1) * 1024]
+        pop = E.ebic_population_upload(part, C)
+        E.set_order(pop, E.longest_first(part))
+        first = E.ebic_evaluate(m, pop, None, E.make_params(**kw))
+        torch.cuda.synchronize()
+        fit = first.fitness.cpu().numpy()[:len(part)]
+        top = [int(i) for i in np.argsort(-fit, kind="stable")[:20]]
+        arch = E.archive_from_device(first.support, top, part)
+        flags = E.support_to_flags(first.support[top], R)
+        archs.append((part, oracle.Archive(flags, [part[i] for i in top])))
+        jobs_t.append(E.make_job(m, pop, arch, E.make_params(**kw)))
+        jobs_g.append(E.make_job(m, pop, arch, E.make_params(**kw)))
+    bt, bg = E.Batch(jobs_t), E.Batch(jobs_g, gather=True)
+    bt.run()
+    bg.run()
+    torch.cuda.synchronize()
+    for jt, jg in zip(jobs_t, jobs_g):
+        assert torch.equal(jt.out.count, jg.out.count)
+        assert torch.equal(jt.out.fitness, jg.out.fitness)
+        assert torch.equal(jt.out.support, jg.out.support)
+        assert torch.equal(jt.out.overlap, jg.out.overlap)
+    pen = 0
+    for j in (0, 5):
+        part, arch = archs[j]
+        sample = np.sort(rng.choice(len(part), 128, replace=False))
+        _check_job(E, jobs_t[j], X, part, kw, arch=arch, sample=sample)
+        cnt = jobs_t[j].out.count.cpu().numpy()[:len(part)]
+        pen += int((jobs_t[j].out.fitness.cpu().numpy()[:len(part)] <
+                    np.ldexp(cnt.astype(np.float64), [len(s) for s in part])).sum())
+    assert pen > 0  # the archives penalise some individuals
+    bt.close()
+    bg.close()
+
+
 @pytest.mark.parametrize("approx", [1000, 900, 700, 500, 300, 0])
 def test_tolerance_regimes(E, approx):
     """Thermometer counters (t+1 <= 16) and exact bit-sliced counters (larger

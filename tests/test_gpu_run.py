@@ -108,6 +108,56 @@ def test_batched_workload_lockstep_few_generations(E):
     _lockstep(E, case.X, kw, synth.GA_SEED + 2)
 
 
+@pytest.mark.slow
+def test_batched_workload_lockstep_full(E):
+    """batched-10000x500 with its own loop settings: 100 generations of
+    4,096 individuals."""
+    w = synth.workload(2)
+    case = synth.workload_matrix(2)
+    kw = _params(negative_trends=1, k_min=w.k_min, k_max=w.k_max, population=w.population,
+                 generations=100, n_out=w.n_out)
+    got = _lockstep(E, case.X, kw, synth.GA_SEED + 2)
+    assert got.generations == 100
+
+
+@pytest.mark.slow
+def test_large_workload_lockstep(E):
+    """large-40000x1000: 20 generations of 8,192 individuals, 20 biclusters
+    returned."""
+    w = synth.workload(3)
+    case = synth.workload_matrix(3)
+    kw = _params(negative_trends=1, k_min=w.k_min, k_max=w.k_max, population=w.population,
+                 generations=20, n_out=20)
+    got = _lockstep(E, case.X, kw, synth.GA_SEED + 3)
+    assert got.generations == 20
+
+
+@pytest.mark.parametrize("ops", [[1000, 0, 0, 0, 0], [100, 200, 300, 400, 0],
+                                 [0, 0, 0, 0, 1000], [0, 500, 0, 500, 0]])
+def test_operator_weights_lockstep(E, ops):
+    """Operator weights other than uniform: the library's loop follows the
+    oracle's (insertion alone stops once every slot's parent is at k_max)."""
+    w = synth.workload(1)
+    case = synth.workload_matrix(1)
+    kw = _params(negative_trends=1, k_min=w.k_min, k_max=w.k_max, population=w.population,
+                 generations=40, n_out=w.n_out, op_permille=ops)
+    _lockstep(E, case.X, kw, 17)
+
+
+def test_reversed_series_share_a_tabu_entry(E):
+    """Three columns, series of three: with reversed trends on, a series
+    and its reverse are one tabu entry and the run stops on tabu hits after
+    one generation; with them off it goes on. Library = oracle."""
+    X = synth.random_matrix(12, 3, seed=4)
+    base = dict(k_min=3, k_max=3, population=3, generations=20, max_tabu_hits=40, min_rows=1,
+                n_out=3)
+    for seed in (1, 2):
+        on = _lockstep(E, X, _params(negative_trends=1, **base), seed)
+        assert (on.generations, on.stop_reason, on.tabu_hits) == (1, E.EBIC_STOP_TABU, 40)
+        off = _lockstep(E, X, _params(negative_trends=0, **base), seed)
+        assert off.generations >= 2
+
+
 def test_many_clashing_candidates_lockstep(E):
     """With no overlap allowed and 12 columns the top-rank list never fills,
     so every generation's update walks all its candidates: far past the

@@ -1,6 +1,7 @@
 """Job server: each job's result is identical alone (ebic_run) and in the
 mix; jobs queue under a small HBM budget and complete; an oversized job
 fails alone; stats report latency percentiles."""
+import os
 import time
 
 import numpy as np
@@ -162,3 +163,73 @@ def test_close_with_queued_jobs(E):
     for X, kw, seed in _mix()[:4]:
         srv.submit(X, E.make_params(**kw), seed)
     srv.close()  # active job finishes, queued ones are dropped; no hang, no fault
+
+
+def test_nonfinite_job_fails_alone(E):
+    """One matrix with a NaN among six valid jobs, all submitted at once so
+    their ingests run on the preparer threads together: only that job fails,
+    with EBIC_ERR_NONFINITE, and every other job equals its run alone."""
+    jobs = _mix()
+    bad = jobs[2][0].copy()
+    bad[17, 3] = np.nan
+    alone = [E.ebic_run(X, E.make_params(**kw), seed) for X, kw, seed in jobs]
+    srv = E.Server()
+    ids = [srv.submit(X, E.make_params(**kw), seed) for X, kw, seed in jobs[:3]]
+    bid = srv.submit(bad, E.make_params(**jobs[2][1]), 5)
+    ids += [srv.submit(X, E.make_params(**kw), seed) for X, kw, seed in jobs[3:]]
+    with pytest.raises(E.EbicError) as ei:
+        srv.wait(bid)
+    assert ei.value.code == E.EBIC_ERR_NONFINITE
+    for a, i in zip(alone, ids):
+        _same(a, srv.wait(i))
+    st = srv.stats()
+    assert st["completed"] == len(jobs) and st["failed"] == 1
+    srv.close()
+
+
+# Eight jobs of the 64-job serving mix (500-50,000 rows x 20-2,000 columns,
+# populations 256-4,096, 30 generations), one at each eighth of the mix
+# ordered by matrix size, from the smallest to the largest.
+SERVING_GENS = 30
+
+
+def _serving_sample():
+    specs = synth.serving_jobs(64)
+    by_size = sorted(specs, key=lambda s: (s.R * s.C, s.job))
+    return [by_size[i] for i in (0, 9, 18, 27, 36, 45, 54, 63)]
+
+
+def _serving_kw(s):
+    return dict(approx_permille=850, negative_trends=1, overlap_permille=750, min_rows=5,
+                k_score_min=3, k_min=3, k_max=min(64, s.C), archive_size=20, n_out=20,
+                population=s.population, generations=SERVING_GENS, max_tabu_hits=10 ** 9,
+                tournament=4, max_attempts=1000)
+
+
+@pytest.fixture(scope="module")
+def serving_sample_results(E):
+    """The eight jobs through the server together."""
+    specs = _serving_sample()
+    mats = [synth.job_matrix(s).X for s in specs]
+    srv = E.Server()
+    ids = [srv.submit(X, E.make_params(**_serving_kw(s)), s.seed) for s, X in zip(specs, mats)]
+    res = [srv.wait(i) for i in ids]
+    srv.close()
+    return specs, mats, res
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("which", range(8))
+def test_serving_mix_job_equals_oracle(E, serving_sample_results, which):
+    specs, mats, res = serving_sample_results
+    s, X, got = specs[which], mats[which], res[which]
+    want = oracle.run(X, oracle.make_params(**_serving_kw(s)), s.seed,
+                      nthreads=min(os.cpu_count() or 1, 16))
+    assert (got.generations, got.evaluations, got.tabu_hits, got.stop_reason) == \
+        (want.generations, want.evaluations, want.tabu_hits, want.stop_reason)
+    np.testing.assert_array_equal(got.trace, want.trace)
+    assert len(got.biclusters) == len(want.biclusters)
+    for x, y in zip(got.biclusters, want.biclusters):
+        np.testing.assert_array_equal(x.rows, y.rows)
+        np.testing.assert_array_equal(x.cols, y.cols)
+        assert x.score == y.score
