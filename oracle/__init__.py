@@ -101,6 +101,9 @@ def lib():
         L.oracle_splitmix64_next.argtypes = [P(ctypes.c_uint64)]
         L.oracle_uniform.restype = ctypes.c_uint64
         L.oracle_uniform.argtypes = [P(ctypes.c_uint64), ctypes.c_uint64]
+        L.oracle_crowding_keys.restype = ctypes.c_int
+        L.oracle_crowding_keys.argtypes = [P(ctypes.c_int32), P(ctypes.c_uint16), ctypes.c_int,
+                                           ctypes.c_int, P(ctypes.c_double), P(ctypes.c_double)]
         L.oracle_mutants.restype = ctypes.c_int
         L.oracle_mutants.argtypes = [P(ctypes.c_int32), P(ctypes.c_uint16), ctypes.c_int,
                                      P(ctypes.c_double), ctypes.c_int, P(Params),
@@ -242,6 +245,19 @@ def mutants(seqs: Sequence[Sequence[int]], C: int, params: Params, seed: int, n:
     if rc != 0:
         raise ValueError("oracle_mutants: invalid argument")
     return [out[i, :min(lens[i], K_LIMIT)].astype(np.int64) for i in range(n)]
+
+
+def crowding_keys(seqs: Sequence[Sequence[int]], C: int, fitness) -> np.ndarray:
+    """Tournament keys of a population: each fitness halved once per column
+    of the individual that more individuals hold than ceil(sum k / C)."""
+    off, cols = _csr(seqs)
+    fit = np.ascontiguousarray(fitness, dtype=np.float64)
+    keys = np.zeros(max(len(seqs), 1), np.float64)
+    if lib().oracle_crowding_keys(_ptr(off, ctypes.c_int32), _ptr(cols, ctypes.c_uint16),
+                                  len(seqs), C, _ptr(fit, ctypes.c_double),
+                                  _ptr(keys, ctypes.c_double)) != 0:
+        raise ValueError("oracle_crowding_keys: invalid argument")
+    return keys[:len(seqs)]
 
 
 def splitmix64_stream(seed: int, count: int) -> List[int]:

@@ -520,6 +520,48 @@ static int update_archive(ga_state *G, const series *pop, int P, const uint8_t *
     return rc;
 }
 
+/* Crowding (reading of the exponential penalty for overused columns,
+ * Sec. 2.3): a column is overused when more individuals hold it than the
+ * mean share ceil(sum k / C); the tournament key is the fitness halved once
+ * per overused column the individual holds. use[C] is scratch. */
+static void crowding_keys(const series *pop, int P, int C, const double *fit, int32_t *use,
+                          double *key)
+{
+    int64_t ksum = 0;
+    memset(use, 0, sizeof(int32_t) * C);
+    for (int i = 0; i < P; i++) {
+        ksum += pop[i].k;
+        for (int q = 0; q < pop[i].k; q++) use[pop[i].c[q]]++;
+    }
+    int64_t share = (ksum + C - 1) / C;
+    for (int i = 0; i < P; i++) {
+        int e = 0;
+        for (int q = 0; q < pop[i].k; q++) e += use[pop[i].c[q]] > share;
+        key[i] = ldexp(fit[i], -e);
+    }
+}
+
+/* The crowding keys of a population given in CSR form (offsets[P+1], cols)
+ * and its fitness, for testing. Returns 0, or -1 for an invalid argument. */
+int oracle_crowding_keys(const int32_t *offsets, const uint16_t *cols, int P, int C,
+                         const double *fitness, double *keys)
+{
+    if (P < 0 || C < 1) return -1;
+    series *pop = malloc(sizeof(series) * (P ? P : 1));
+    int32_t *use = malloc(sizeof(int32_t) * C);
+    if (!pop || !use) { free(pop); free(use); return -1; }
+    for (int i = 0; i < P; i++) {
+        int k = offsets[i + 1] - offsets[i];
+        if (!series_valid(cols + offsets[i], k, C)) { free(pop); free(use); return -1; }
+        pop[i].k = k;
+        memcpy(pop[i].c, cols + offsets[i], sizeof(uint16_t) * k);
+    }
+    crowding_keys(pop, P, C, fitness, use, keys);
+    free(pop);
+    free(use);
+    return 0;
+}
+
 /* Tournament: T uniform draws with replacement; the largest key wins, the
  * lowest index among equal keys. */
 static int tournament(ga_state *G, const double *key, int P)
@@ -746,22 +788,7 @@ int oracle_run(const float *X, int R, int C, const oracle_params *p, uint64_t se
         int ne = G.nA < P / 2 ? G.nA : P / 2;
         for (int j = 0; j < ne; j++) next[Nn++] = G.A[j].s;
 
-        /* Crowding (reading of the exponential penalty for overused
-         * columns): a column is overused when more individuals hold it than
-         * the mean share ceil(sum k / C); the tournament key is the fitness
-         * halved once per overused column the individual holds. */
-        int64_t ksum = 0;
-        memset(use, 0, sizeof(int32_t) * C);
-        for (int i = 0; i < Pn; i++) {
-            ksum += pop[i].k;
-            for (int q = 0; q < pop[i].k; q++) use[pop[i].c[q]]++;
-        }
-        int64_t share = (ksum + C - 1) / C;
-        for (int i = 0; i < Pn; i++) {
-            int e = 0;
-            for (int q = 0; q < pop[i].k; q++) e += use[pop[i].c[q]] > share;
-            key[i] = ldexp(fit[i], -e);
-        }
+        crowding_keys(pop, Pn, C, fit, use, key);
 
         /* Step 5: replenish with mutants; step 6: tabu hits. */
         while (Nn < P && !stop) {

@@ -667,3 +667,44 @@ def test_operator_weights_validated_and_default():
     b = oracle.run(X, _c0_params(k_max=4, generations=5), seed=2)
     np.testing.assert_array_equal(a.trace, b.trace)
     assert a.tabu_hits == b.tabu_hits
+
+
+def test_crowding_keys_worked_examples():
+    """Worked by hand. Four series over 4 columns, 8 entries: the mean share
+    is ceil(8/4) = 2 and only column 0 (held 3 times) is overused, so the
+    three series holding it are halved. Over 5 columns the share is
+    ceil(8/5) = 2 as well, column 0 still the only one above it."""
+    seqs = [[0, 1], [0, 2], [3, 0], [1, 2]]
+    fit = np.array([16.0, 8.0, 0.0, 4.0])
+    np.testing.assert_array_equal(oracle.crowding_keys(seqs, 4, fit), [8.0, 4.0, 0.0, 4.0])
+    np.testing.assert_array_equal(oracle.crowding_keys(seqs, 5, fit), [8.0, 4.0, 0.0, 4.0])
+    # 3 columns: share ceil(8/3) = 3; column 0 held 3 times is not above it
+    seqs3 = [[0, 1], [0, 2], [2, 0], [1, 2]]
+    np.testing.assert_array_equal(oracle.crowding_keys(seqs3, 3, fit), fit)
+    # share ceil(9/4) = 3: column 0 (held 4 times) is overused, column 1
+    # (held 3 times, exactly the share) is not
+    seqs4 = [[0, 1, 2], [0, 1], [0, 1], [0, 3]]
+    np.testing.assert_array_equal(oracle.crowding_keys(seqs4, 4, [64.0, 8.0, 8.0, 8.0]),
+                                  [32.0, 4.0, 4.0, 4.0])
+    # share ceil(10/4) = 3: columns 0 and 1 (held 4 times each) are both
+    # overused, so every series is quartered
+    seqs5 = [[0, 1, 2], [0, 1], [0, 1], [0, 1, 3]]
+    np.testing.assert_array_equal(oracle.crowding_keys(seqs5, 4, [64.0, 8.0, 8.0, 8.0]),
+                                  [16.0, 2.0, 2.0, 2.0])
+
+
+def test_crowding_keys_invariants():
+    """Relabelling columns leaves the keys unchanged; a population using
+    every column equally is never penalised; e never exceeds k."""
+    rng = np.random.default_rng(3)
+    C = 30
+    seqs = [list(map(int, rng.permutation(C)[:int(rng.integers(2, 9))])) for _ in range(50)]
+    fit = np.ldexp(1.0, rng.integers(0, 30, 50)).astype(np.float64)
+    keys = oracle.crowding_keys(seqs, C, fit)
+    perm = rng.permutation(C)
+    np.testing.assert_array_equal(oracle.crowding_keys([[int(perm[c]) for c in s] for s in seqs],
+                                                       C, fit), keys)
+    e = np.log2(fit / np.where(keys > 0, keys, 1.0))
+    assert np.all(e >= 0) and np.all(e <= np.array([len(s) for s in seqs]))
+    even = [[(i + j) % C for j in range(5)] for i in range(C)]  # each column 5 times
+    np.testing.assert_array_equal(oracle.crowding_keys(even, C, np.ones(C)), np.ones(C))
