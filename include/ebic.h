@@ -284,6 +284,23 @@ int ebic_batch_timings(ebic_batch *b, float *ms, int32_t *n);
 /* One-shot batched evaluation: create, run, wait, destroy. Synchronous. */
 int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream);
 
+/* For callers that cannot allocate device or pinned memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same evaluation as ebic_evaluate_batched, bit for bit (the same kernel in
+ * the same untuned item shape), with no hipMalloc, hipFree, hipHostMalloc or
+ * other allocating call. The job table goes to a fixed device array of the
+ * library (16 KiB per device, held until the process ends), so at most
+ * EBIC_NOALLOC_MAX_JOBS jobs per call, and every job must bring its support
+ * output (out.d_support; the others as for ebic_evaluate_batched). The
+ * array's address is looked up once per device on the first call there.
+ * Calls on one device run one at a time (a mutex per device, held until the
+ * kernel has finished); the array keeps the last call's table, which no call
+ * reads before writing it. Synchronous on `stream`. Errors: EBIC_ERR_INVALID_ARG
+ * for more jobs than the limit, a missing support output or a bad job (the
+ * outputs are then untouched); EBIC_ERR_DEVICE for a HIP failure. */
+#define EBIC_NOALLOC_MAX_JOBS 64
+int ebic_evaluate_batched_noalloc(const ebic_job *jobs, int32_t njobs, void *stream);
+
 /* One bicluster of a run: rows ascending, columns in series order. */
 typedef struct ebic_bicluster {
     int32_t n_rows;

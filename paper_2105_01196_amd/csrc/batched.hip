@@ -591,6 +591,7 @@ struct Batch {
     int32_t flags = 0;
     bool two = false;          // some job reads both pair tables (strict or loose rule)
     std::vector<DevJob> jobs;
+    std::vector<int> perm;     // scratch of lay_out
     DevJob *d_jobs = nullptr;  // device: DevJob[njobs] by population size, descending;
     int64_t *d_sched = nullptr;  // then the schedule (phase starts, phase rounds)
     int32_t cap_jobs = 0;      // capacity of d_jobs / h_stage
@@ -677,46 +678,89 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
     return d;
 }
 
-// Lay the items out for `cpi` groups of b->wpl chunks per item (more when an
-// individual would need more than kMaxWaves items) and queue the table's
-// upload on `stream` from pinned staging, growing the device table when
-// needed.
-int upload_table(Batch *b, int cpi, hipStream_t stream) {
-    b->cpi = cpi;
-    const int32_t n = b->njobs;
-    bool two = false;
-    for (const DevJob &d : b->jobs)
-        two |= d.mode == 1 && d.tie_rule != EBIC_TIE_INDEX && d.pairs_strict != nullptr;
-    if (two != b->two) {  // another kernel: a graph of the old one is rebuilt on the next run
-        if (b->exec) (void)hipGraphExecDestroy(b->exec);
-        if (b->graph) (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
-        b->two = two;
+// What a launch needs besides the job table: the workgroup shape, the LDS
+// partition and the grid.
+struct Layout {
+    bool two = false;        // some job reads both pair tables
+    int waves = 1;           // waves per workgroup: the largest items per individual
+    int32_t sup_words = 0;   // LDS support words per workgroup (0: global only)
+    int32_t bits_words = 1;  // LDS column-bitmap words per workgroup
+    int32_t acol_words = 0;  // LDS archive columns per workgroup (0: global only)
+    int64_t total_ind = 0;   // workgroups
+};
+
+constexpr size_t table_bytes_max(int32_t n) {
+    return sizeof(DevJob) * n + sizeof(int64_t) * 2 * n;
+}
+size_t table_bytes(int32_t n) { return table_bytes_max(n); }
+// Size of the array behind the allocation-free batched evaluation.
+constexpr size_t kNoAllocScratchBytes = 16384;
+
+// Lay the items out for `cpi` groups of `wpl` chunks per item (more when an
+// individual would need more than kMaxWaves items) and write the job table
+// (jobs by population size, descending) and the schedule (phase starts,
+// phase rounds) to h, table_bytes(n) bytes. `perm` is scratch for n ints.
+// Allocates nothing.
+Layout lay_out(DevJob *jobs, int32_t n, int cpi, int wpl, int *perm, char *h) {
+    Layout L;
+    for (int32_t i = 0; i < n; i++) {
+        const DevJob &d = jobs[i];
+        L.two |= d.mode == 1 && d.tie_rule != EBIC_TIE_INDEX && d.pairs_strict != nullptr;
     }
-    int waves = 1;
-    for (DevJob &d : b->jobs) {
+    int32_t wmax = 0, cmax = 0, amax = 0;
+    for (int32_t i = 0; i < n; i++) {
+        DevJob &d = jobs[i];
         // whole groups per item, so that no two items share a group
-        int32_t cpc = cpi * b->wpl;
+        int32_t cpc = cpi * wpl;
         const int32_t need = (d.nchunks + kMaxWaves - 1) / kMaxWaves;
-        if (cpc < need) cpc = (need + b->wpl - 1) / b->wpl * b->wpl;
+        if (cpc < need) cpc = (need + wpl - 1) / wpl * wpl;
         d.cpi = cpc < d.nchunks ? cpc : d.nchunks;
         if (d.cpi < 1) d.cpi = 1;
         d.ipi = (d.nchunks + d.cpi - 1) / d.cpi;
-        waves = d.ipi > waves ? d.ipi : waves;
-    }
-    b->waves = waves;
-    int32_t wmax = 0, cmax = 0;
-    for (const DevJob &d : b->jobs) {
+        L.waves = d.ipi > L.waves ? d.ipi : L.waves;
         wmax = d.w64 > wmax ? d.w64 : wmax;
         cmax = d.cols > cmax ? d.cols : cmax;
+        amax = d.arch_len > amax ? d.arch_len : amax;
     }
-    b->sup_words = wmax <= kSupLdsWords ? wmax : 0;
-    b->bits_words = (cmax + 31) / 32;
-    int32_t amax = 0;
-    for (const DevJob &d : b->jobs) amax = d.arch_len > amax ? d.arch_len : amax;
-    b->acol_words = amax <= kArchLdsCols ? amax : 0;
-    const size_t jbytes = sizeof(DevJob) * n, bytes = jbytes + sizeof(int64_t) * 2 * n;
+    L.sup_words = wmax <= kSupLdsWords ? wmax : 0;
+    L.bits_words = (cmax + 31) / 32;
+    L.acol_words = amax <= kArchLdsCols ? amax : 0;
+    // Individuals of all jobs are interleaved round-robin, so that each
+    // job's longest-first order holds across the batch: with the jobs stored
+    // by population size, descending, phase p takes one individual of each
+    // of the first n - p jobs per round, over the rounds that those jobs
+    // still have. (Stable insertion sort: no temporary buffer.)
+    for (int32_t i = 0; i < n; i++) {
+        int32_t q = i;
+        while (q > 0 && jobs[perm[q - 1]].pop_size < jobs[i].pop_size) {
+            perm[q] = perm[q - 1];
+            q--;
+        }
+        perm[q] = i;
+    }
+    const size_t jbytes = sizeof(DevJob) * n;
+    DevJob *hj = reinterpret_cast<DevJob *>(h);
+    int64_t *ph_start = reinterpret_cast<int64_t *>(h + jbytes);
+    int64_t *ph_round = ph_start + n;
+    int64_t start = 0;
+    for (int32_t p = 0; p < n; p++) {
+        hj[p] = jobs[perm[p]];
+        const int64_t first = p == 0 ? 0 : jobs[perm[n - p]].pop_size;
+        ph_start[p] = start;
+        ph_round[p] = first;
+        start += (int64_t)(n - p) * (jobs[perm[n - 1 - p]].pop_size - first);
+    }
+    L.total_ind = start;
+    return L;
+}
+
+// Lay the batch's items out for `cpi` chunk groups per item and queue the
+// table's upload on `stream` from pinned staging, growing the device table
+// when needed.
+int upload_table(Batch *b, int cpi, hipStream_t stream) {
+    b->cpi = cpi;
+    const int32_t n = b->njobs;
+    const size_t bytes = table_bytes(n);
     if (n > b->cap_jobs) {
         if (b->d_jobs) device_release(b->al, b->d_jobs, b->al_stream);
         if (b->h_stage) (void)hipHostFree(b->h_stage);
@@ -729,31 +773,24 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
         EBIC_HIP(hipHostMalloc(&b->h_stage, bytes, hipHostMallocDefault));
         b->cap_jobs = n;
     }
-    b->d_sched = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) + jbytes);
-    // Individuals of all jobs are interleaved round-robin, so that each
-    // job's longest-first order holds across the batch: with the jobs stored
-    // by population size, descending, phase p takes one individual of each
-    // of the first n - p jobs per round, over the rounds that those jobs
-    // still have.
-    std::vector<int> perm(n);
-    for (int i = 0; i < n; i++) perm[i] = i;
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int c) {
-        return b->jobs[a].pop_size > b->jobs[c].pop_size;
-    });
-    char *h = static_cast<char *>(b->h_stage);
-    DevJob *hj = reinterpret_cast<DevJob *>(h);
-    int64_t *ph_start = reinterpret_cast<int64_t *>(h + jbytes);
-    int64_t *ph_round = ph_start + n;
-    int64_t start = 0;
-    for (int p = 0; p < n; p++) {
-        hj[p] = b->jobs[perm[p]];
-        const int64_t first = p == 0 ? 0 : b->jobs[perm[n - p]].pop_size;
-        ph_start[p] = start;
-        ph_round[p] = first;
-        start += (int64_t)(n - p) * (b->jobs[perm[n - 1 - p]].pop_size - first);
+    b->perm.resize(n);
+    const Layout L =
+        lay_out(b->jobs.data(), n, cpi, b->wpl, b->perm.data(), static_cast<char *>(b->h_stage));
+    if (L.two != b->two) {  // another kernel: a graph of the old one is rebuilt on the next run
+        if (b->exec) (void)hipGraphExecDestroy(b->exec);
+        if (b->graph) (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        b->two = L.two;
     }
-    b->total_ind = start;
-    EBIC_HIP(hipMemcpyAsync(b->d_jobs, h, bytes, hipMemcpyHostToDevice, stream));
+    b->waves = L.waves;
+    b->sup_words = L.sup_words;
+    b->bits_words = L.bits_words;
+    b->acol_words = L.acol_words;
+    b->total_ind = L.total_ind;
+    b->d_sched = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) +
+                                             sizeof(DevJob) * n);
+    EBIC_HIP(hipMemcpyAsync(b->d_jobs, b->h_stage, bytes, hipMemcpyHostToDevice, stream));
     return EBIC_OK;
 }
 
@@ -771,13 +808,14 @@ void *kernel_fn(const Batch *b, int kb, int wpl) {
     return b->two ? kernel_fn<true>(kb, wpl) : kernel_fn<false>(kb, wpl);
 }
 
-size_t lds_bytes(const Batch *b) {
+size_t lds_bytes(int32_t sup_words, int32_t bits_words, int32_t acol_words) {
     // support, step descriptors, column bitmap, archive offsets, archive
     // columns, 8 bytes of alignment slack, their hit masks
-    return (size_t)b->sup_words * 8 + (size_t)EBIC_MAX_K * 4 + (size_t)b->bits_words * 4 +
-           (size_t)(EBIC_MAX_ARCHIVE + 1) * 4 + (size_t)b->acol_words * 2 + 8 +
-           (size_t)(b->acol_words + kWave - 1) / kWave * 8;
+    return (size_t)sup_words * 8 + (size_t)EBIC_MAX_K * 4 + (size_t)bits_words * 4 +
+           (size_t)(EBIC_MAX_ARCHIVE + 1) * 4 + (size_t)acol_words * 2 + 8 +
+           (size_t)(acol_words + kWave - 1) / kWave * 8;
 }
+size_t lds_bytes(const Batch *b) { return lds_bytes(b->sup_words, b->bits_words, b->acol_words); }
 
 int launch_batch(Batch *b, hipStream_t stream) {
     void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind, &b->sup_words,
@@ -1115,6 +1153,86 @@ int batch_destroy(Batch *b) {
     if (b->h_stage) (void)hipHostFree(b->h_stage);
     for (void *p : b->scratch) (void)hipFree(p);
     delete b;
+    return EBIC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched evaluation that allocates nothing: the job table and schedule go
+// to a fixed device array of this library instead of a batch's allocation.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;  // devices a process can use this entry point on
+static_assert(table_bytes_max(EBIC_NOALLOC_MAX_JOBS) <= kNoAllocScratchBytes,
+              "the job table of the largest call fits the array");
+
+// The array itself. Its name in host code is a host-side stand-in, not the
+// device address: kernels and copies get the address that
+// hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+std::mutex g_noalloc_mu[kNoAllocDevices];  // one call at a time per device
+void *g_noalloc_ptr[kNoAllocDevices];       // the array's address on each device
+
+// The array's address on `dev` (current), looked up once per device with
+// the device's mutex held.
+int scratch_address(int dev, void **out) {
+    if (!g_noalloc_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return check_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(EBIC_ERR_DEVICE, "scratch array has no address on device %d", dev);
+        g_noalloc_ptr[dev] = ptr;
+    }
+    *out = g_noalloc_ptr[dev];
+    return EBIC_OK;
+}
+
+}  // namespace
+
+int batch_run_noalloc(const ebic_job *jobs, int32_t njobs, hipStream_t stream) {
+    if (!jobs || njobs < 1) return fail(EBIC_ERR_INVALID_ARG, "no jobs");
+    if (njobs > EBIC_NOALLOC_MAX_JOBS)
+        return fail(EBIC_ERR_INVALID_ARG, "%d jobs: the allocation-free batched evaluation "
+                    "takes at most %d", njobs, EBIC_NOALLOC_MAX_JOBS);
+    for (int i = 0; i < njobs; i++) {
+        int rc = check_job(&jobs[i], i);
+        if (rc) return rc;
+        if (jobs[i].population.size > 0 && !jobs[i].out.d_support)
+            return fail(EBIC_ERR_INVALID_ARG, "job %d: support output required", i);
+    }
+    int dev = 0;
+    EBIC_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocDevices)
+        return fail(EBIC_ERR_INVALID_ARG, "device %d: at most %d devices", dev, kNoAllocDevices);
+    DevJob dj[EBIC_NOALLOC_MAX_JOBS];
+    int perm[EBIC_NOALLOC_MAX_JOBS];
+    alignas(16) char h[table_bytes_max(EBIC_NOALLOC_MAX_JOBS)];
+    for (int i = 0; i < njobs; i++) dj[i] = make_devjob(jobs[i], 0);
+    constexpr int kb = 2, wpl = 1;  // the shape ebic_evaluate_batched runs untuned
+    Layout L = lay_out(dj, njobs, kDefaultCpi, wpl, perm, h);
+    if (L.total_ind == 0) return EBIC_OK;
+    if (L.total_ind > INT32_MAX)
+        return fail(EBIC_ERR_INVALID_ARG, "%lld individuals in one launch", (long long)L.total_ind);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu[dev]);
+    void *base = nullptr;
+    int rc = scratch_address(dev, &base);
+    if (rc) return rc;
+    // the table from the stack: a copy from pageable memory has read it when
+    // the call returns
+    EBIC_HIP(hipMemcpyAsync(base, h, table_bytes(njobs), hipMemcpyHostToDevice, stream));
+    DevJob *d_jobs = static_cast<DevJob *>(base);
+    int64_t *d_sched = reinterpret_cast<int64_t *>(static_cast<char *>(base) +
+                                                   sizeof(DevJob) * njobs);
+    int32_t n = njobs;
+    void *args[] = {&d_jobs, &d_sched, &n, &L.total_ind, &L.sup_words, &L.bits_words,
+                    &L.acol_words};
+    void *fn = L.two ? kernel_fn<true>(kb, wpl) : kernel_fn<false>(kb, wpl);
+    EBIC_HIP(hipLaunchKernel(fn, dim3((unsigned)L.total_ind), dim3(L.waves * kWave), args,
+                             lds_bytes(L.sup_words, L.bits_words, L.acol_words), stream));
+    // the next call may rewrite the array only after this launch has read it
+    EBIC_HIP(hipStreamSynchronize(stream));
     return EBIC_OK;
 }
 

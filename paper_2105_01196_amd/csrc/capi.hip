@@ -306,6 +306,11 @@ int ebic_evaluate_batched(const ebic_job *jobs, int32_t njobs, void *stream) {
     return rc;
 }
 
+int ebic_evaluate_batched_noalloc(const ebic_job *jobs, int32_t njobs, void *stream) {
+    clear_error();
+    return batch_run_noalloc(jobs, njobs, static_cast<hipStream_t>(stream));
+}
+
 int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
              const ebic_allocator *alloc, void *stream, ebic_result **out) {
     clear_error();

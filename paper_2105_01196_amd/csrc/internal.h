@@ -110,6 +110,9 @@ void server_destroy(Server *s);
 struct Batch;
 int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out);
 int batch_run(Batch *b, hipStream_t stream);
+// ebic_evaluate_batched_noalloc: the job table in the library's fixed
+// device array, no allocation.
+int batch_run_noalloc(const ebic_job *jobs, int32_t njobs, hipStream_t stream);
 int batch_set(Batch **b, const ebic_job *jobs, int32_t njobs, hipStream_t stream,
               const ebic_allocator *al = nullptr);
 // Device memory from the caller's allocator when one is given, else hipMalloc.

@@ -28,6 +28,7 @@ EBIC_ERR_CAPACITY = -5
 EBIC_MAX_K = 512
 EBIC_MAX_ARCHIVE = 64
 EBIC_MAX_COLS = 16384
+EBIC_NOALLOC_MAX_JOBS = 64
 
 
 class EbicError(RuntimeError):
@@ -140,6 +141,7 @@ _SIGNATURES = {
     "ebic_batch_run": (ctypes.c_int, [_vp, _vp]),
     "ebic_batch_destroy": (ctypes.c_int, [_vp]),
     "ebic_evaluate_batched": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _vp]),
+    "ebic_evaluate_batched_noalloc": (ctypes.c_int, [ctypes.POINTER(ebic_job), _i32, _vp]),
     "ebic_run": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params), ctypes.c_uint64,
                                 ctypes.POINTER(ebic_allocator), _vp,
                                 ctypes.POINTER(ctypes.POINTER(ebic_result))]),
@@ -528,6 +530,14 @@ class Batch:
 def ebic_evaluate_batched(jobs: Sequence[Job], stream=None) -> None:
     views = (ebic_job * len(jobs))(*[j.view() for j in jobs])
     _check(lib().ebic_evaluate_batched(views, len(jobs), _stream(stream)))
+
+
+def ebic_evaluate_batched_noalloc(jobs: Sequence[Job], stream=None) -> None:
+    """ebic_evaluate_batched without any allocation (job table in the
+    library's fixed device array; at most EBIC_NOALLOC_MAX_JOBS jobs, each
+    with its support output)."""
+    views = (ebic_job * len(jobs))(*[j.view() for j in jobs])
+    _check(lib().ebic_evaluate_batched_noalloc(views, len(jobs), _stream(stream)))
 
 
 @dataclasses.dataclass
