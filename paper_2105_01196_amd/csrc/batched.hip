@@ -22,6 +22,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "device.h"
@@ -132,7 +133,7 @@ __device__ __forceinline__ void add_sticky(uint64_t *C, const uint64_t *S, uint6
 // once; after each group the wave stops once every row has failed both
 // trends. Writes the fit words to fit[].
 template <int P, bool NEG, int KB, int WPL, bool TWO>
-__device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs,
+__device__ __forceinline__ void pairs_count_two(const uint64_t *__restrict__ pairs,
                                             const uint64_t *__restrict__ strict, bool loose,
                                             int64_t pstride, int wlim, const int32_t *s_pd, int k,
                                             int t, int w, uint64_t *fit) {
@@ -208,6 +209,201 @@ __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs,
     }
 #pragma unroll
     for (int v = 0; v < WPL; v++) fit[v] = ~dov[v] | (NEG ? ~uov[v] : 0ull);
+}
+
+// Three-input bitwise operation (v_bitop3_b32). IMM is the truth table:
+// bit (a << 2 | b << 1 | c) of IMM is the result for input bits a, b, c,
+// i.e. the operation applied to a = 0xF0, b = 0xCC, c = 0xAA.
+template <int IMM>
+__device__ __forceinline__ uint32_t lop3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, IMM);
+}
+constexpr int kXor3 = 0x96;    // a ^ b ^ c
+constexpr int kMaj = 0xE8;     // at least two of a, b, c
+constexpr int kAndXor = 0x60;  // a & (b ^ c)
+constexpr int kOr3 = 0xFE;     // a | b | c
+constexpr int kNor2 = 0x03;    // ~(a | b)
+constexpr int kNor3 = 0x01;    // ~(a | b | c)
+
+// C (P planes of one 32-bit half) += S (B planes); the carry out of the top
+// plane, and any bit of S at or above plane P, set the sticky flag ov.
+template <int P, int B>
+__device__ __forceinline__ void add_half(uint32_t *C, const uint32_t *S, uint32_t &ov) {
+    if constexpr (P == 0) {
+        // no room: any step against the trend ends the row
+        if constexpr (B == 1) ov |= S[0];
+        else if constexpr (B == 2) ov = lop3<kOr3>(ov, S[0], S[1]);
+        else ov = lop3<kOr3>(ov, S[0], S[1]) | S[2];
+    } else {
+        uint32_t c;
+        {
+            const uint32_t a = C[0];
+            C[0] = a ^ S[0];
+            c = a & S[0];
+        }
+#pragma unroll
+        for (int p = 1; p < P; p++) {
+            const uint32_t a = C[p];
+            if (p < B) {
+                C[p] = lop3<kXor3>(a, S[p], c);
+                c = lop3<kMaj>(a, S[p], c);
+            } else {
+                C[p] = a ^ c;
+                c = a & c;
+            }
+        }
+#pragma unroll
+        for (int p = P; p < B; p++) c |= S[p];
+        ov |= c;
+    }
+}
+
+// Bit-sliced count of n in {1, 2, 3, 4} steps of one 32-bit half: the rows'
+// up-steps (ups) and down-steps (dns, n - ups), B = 1, 2, 2, 3 planes. A
+// step's up bits are its table bits b, inverted when the step runs from the
+// higher column to the lower one (m = ~0 then, uniform).
+template <int N>
+struct StepSum {
+    static constexpr int B = N == 1 ? 1 : N == 4 ? 3 : 2;
+    __device__ __forceinline__ static void sum(const uint32_t *b, const uint32_t *m, uint32_t *ups,
+                                               uint32_t *dns) {
+        if constexpr (N == 1) {
+            ups[0] = b[0] ^ m[0];
+            dns[0] = ~ups[0];
+        } else if constexpr (N == 2) {
+            const uint32_t x0 = b[0] ^ m[0];
+            ups[0] = lop3<kXor3>(x0, b[1], m[1]);
+            ups[1] = lop3<kAndXor>(x0, b[1], m[1]);
+            dns[0] = ups[0];                         // 2 - u has u's parity
+            dns[1] = lop3<kNor2>(ups[0], ups[1], 0);  // 2 - u >= 2 only for u = 0
+        } else if constexpr (N == 3) {
+            const uint32_t x0 = b[0] ^ m[0], x1 = b[1] ^ m[1], x2 = b[2] ^ m[2];
+            ups[0] = lop3<kXor3>(x0, x1, x2);
+            ups[1] = lop3<kMaj>(x0, x1, x2);
+            dns[0] = ~ups[0];  // 3 - u is u's two-bit complement
+            dns[1] = ~ups[1];
+        } else {
+            const uint32_t x0 = b[0] ^ m[0], x1 = b[1] ^ m[1], x2 = b[2] ^ m[2];
+            const uint32_t a0 = lop3<kXor3>(x0, x1, x2), a1 = lop3<kMaj>(x0, x1, x2);
+            // add the fourth step, x3 = b3 ^ m3
+            const uint32_t c = lop3<kAndXor>(a0, b[3], m[3]);
+            ups[0] = lop3<kXor3>(a0, b[3], m[3]);
+            ups[1] = a1 ^ c;
+            ups[2] = a1 & c;
+            // 4 - u: same parity; bit 1 set for u = 1, 2; bit 2 only for u = 0
+            dns[0] = ups[0];
+            dns[1] = ups[1] ^ ups[0];
+            dns[2] = lop3<kNor3>(ups[0], ups[1], ups[2]);
+        }
+    }
+};
+
+// The column-index tie rule (one table; every step is either up or down in
+// a row): the same counters as pairs_count_two, on 32-bit halves with
+// three-input logic, groups of KB steps loaded together through buffer
+// loads whose row base is computed in scalar registers.
+template <int P, bool NEG, int KB, int WPL>
+__device__ __forceinline__ void pairs_count_one(const uint64_t *__restrict__ pairs,
+                                                int64_t pstride, int wlim, const int32_t *s_pd,
+                                                int k, int t, int w, uint64_t *fit) {
+    constexpr int NP = P > 0 ? P : 1;
+    uint32_t start = __builtin_amdgcn_readfirstlane((1u << P) - (uint32_t)(t + 1));
+    asm volatile("" : "+s"(start));
+    const uint32_t row_bytes = (uint32_t)(pstride * 8);
+    bool active[WPL];
+    int voff[WPL];
+    uint32_t D[WPL][2][NP], U[WPL][2][NP], dov[WPL][2], uov[WPL][2];
+#pragma unroll
+    for (int v = 0; v < WPL; v++) {
+        active[v] = w + kWave * v < wlim;
+        // an inactive lane reads past the row's end: the buffer returns 0
+        voff[v] = active[v] ? (w + kWave * v) * 8 : (int)row_bytes;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+#pragma unroll
+            for (int p = 0; p < P; p++) D[v][h][p] = U[v][h][p] = ((start >> p) & 1u) ? ~0u : 0u;
+            dov[v][h] = uov[v][h] = 0;
+        }
+    }
+    // loads and flips of up to KB steps from step j on
+    auto load = [&](int j, int n, uint32_t (*b)[WPL][2], uint32_t *m) {
+#pragma unroll
+        for (int q = 0; q < KB; q++) {
+            if (q < n) {
+                const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
+                const uint64_t *row = pairs + (int64_t)(pd & 0x7fffffff) * pstride;
+                const __amdgpu_buffer_rsrc_t rs = make_rsrc(row, row_bytes);
+                m[q] = pd < 0 ? ~0u : 0u;
+#pragma unroll
+                for (int v = 0; v < WPL; v++) {
+                    const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, voff[v], 0, 0);
+                    b[q][v][0] = x[0];
+                    b[q][v][1] = x[1];
+                }
+            }
+        }
+    };
+    auto count = [&](auto nconst, uint32_t (*b)[WPL][2], const uint32_t *m) {
+        constexpr int N = decltype(nconst)::value;
+        constexpr int B = StepSum<N>::B;
+#pragma unroll
+        for (int v = 0; v < WPL; v++) {
+#pragma unroll
+            for (int h = 0; h < 2; h++) {
+                uint32_t bb[N], ups[B], dns[B];
+#pragma unroll
+                for (int q = 0; q < N; q++) bb[q] = b[q][v][h];
+                StepSum<N>::sum(bb, m, ups, dns);
+                add_half<P, B>(D[v][h], dns, dov[v][h]);
+                if (NEG) add_half<P, B>(U[v][h], ups, uov[v][h]);
+            }
+        }
+    };
+    int j = 1;
+    for (; j + KB <= k; j += KB) {
+        uint32_t b[KB][WPL][2], m[KB];
+        load(j, KB, b, m);
+        count(std::integral_constant<int, KB>{}, b, m);
+        bool live = false;
+#pragma unroll
+        for (int v = 0; v < WPL; v++) {
+            const uint32_t lo = NEG ? dov[v][0] & uov[v][0] : dov[v][0];
+            const uint32_t hi = NEG ? dov[v][1] & uov[v][1] : dov[v][1];
+            live |= active[v] && (lo & hi) != ~0u;
+        }
+        if (__ballot(live) == 0) {
+            j = k + 1;  // every row is out of both trends: skip the tail
+            break;
+        }
+    }
+    const int rest = k - j;  // 0 .. KB - 1 steps left (negative after an early exit)
+    if (rest > 0) {
+        uint32_t b[KB][WPL][2], m[KB];
+        load(j, rest, b, m);
+        if (rest == 1) count(std::integral_constant<int, 1>{}, b, m);
+        if constexpr (KB > 2) {
+            if (rest == 2) count(std::integral_constant<int, 2>{}, b, m);
+            if (rest == 3) count(std::integral_constant<int, 3>{}, b, m);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < WPL; v++) {
+        const uint32_t lo = ~dov[v][0] | (NEG ? ~uov[v][0] : 0u);
+        const uint32_t hi = ~dov[v][1] | (NEG ? ~uov[v][1] : 0u);
+        fit[v] = ((uint64_t)hi << 32) | lo;
+    }
+}
+
+template <int P, bool NEG, int KB, int WPL, bool TWO>
+__device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs,
+                                            const uint64_t *__restrict__ strict, bool loose,
+                                            int64_t pstride, int wlim, const int32_t *s_pd, int k,
+                                            int t, int w, uint64_t *fit) {
+    if constexpr (TWO)
+        pairs_count_two<P, NEG, KB, WPL, true>(pairs, strict, loose, pstride, wlim, s_pd, k, t, w,
+                                               fit);
+    else
+        pairs_count_one<P, NEG, KB, WPL>(pairs, pstride, wlim, s_pd, k, t, w, fit);
 }
 
 // Widest counter the pair path instantiates for KB steps per group and WPL

@@ -27,10 +27,19 @@ def test_traffic_file_matches_its_kernel_sources():
         taken = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("source_sha256_16:")]
     if taken != [bench.kernel_source_hash()]:
         pytest.skip("the counters predate the kernel sources: retake them")
-    blocks = {}
-    for name in ("batched-10000x500", "large-40000x1000"):
-        for shape in ((1, 2, 1), (2, 2, 2)):
-            blocks[(name, shape)] = bench.measured_traffic(name, *shape)
-    assert blocks[("batched-10000x500", (1, 2, 1))] is not None
-    assert blocks[("large-40000x1000", (2, 2, 2))] is not None
-    assert blocks[("batched-10000x500", (2, 2, 2))] is None
+    shapes, cur = {}, None
+    with open(bench.TRAFFIC_FILE) as f:
+        for ln in f:
+            if ":" not in ln or ln.startswith("#"):
+                continue
+            k, v = (x.strip() for x in ln.split(":", 1))
+            if k == "workload":
+                cur = shapes.setdefault(v, [0, 0, 0])
+            elif cur is not None and k in ("chunk_groups_per_item", "loads_in_flight",
+                                           "words_per_lane"):
+                cur[("chunk_groups_per_item", "loads_in_flight", "words_per_lane").index(k)] = int(v)
+    assert set(shapes) == {"batched-10000x500", "large-40000x1000"}
+    for name, shape in shapes.items():
+        assert bench.measured_traffic(name, *shape) is not None
+        other = (shape[0], shape[1], 3 - shape[2])  # the other words-per-lane count
+        assert bench.measured_traffic(name, *other) is None
