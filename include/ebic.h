@@ -360,6 +360,25 @@ typedef struct ebic_allocator {
  * EBIC_ERR_DEVICE. On success *out is set. */
 int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
              const ebic_allocator *alloc, void *stream, ebic_result **out);
+
+/* ebic_run with every generation after the first on the device (Sec. 2.4,
+ * steps 3-7; the paper names moving the CPU parts to the GPU as future work,
+ * Sec. 4): the top-rank list update, elitism, the crowding keys, the
+ * tournaments and mutations, the tabu set (a hash table of canonical series
+ * in device memory) and the tabu-hit and attempt limits all run as kernels;
+ * between generations the host reads only a status block. Step 1 (the first
+ * population) and step 9 (the final supports) run as in ebic_run. The draws
+ * are ebic_run's: SplitMix64 gives any draw of the stream directly, and an
+ * attempt's draws do not depend on whether earlier children were rejected,
+ * so each generation's attempts are drawn, built and checked in parallel and
+ * the loop's rules are then applied in attempt order. The result equals
+ * ebic_run's for the same seed (rows, series, scores, trace, counts).
+ * Arguments, ownership and errors as for ebic_run; besides,
+ * EBIC_ERR_INVALID_ARG for tournament > 16 or population > 8192, and
+ * EBIC_ERR_CAPACITY when the tabu set for population * generations series
+ * would take more than half the free device memory. */
+int ebic_run_device(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                    uint64_t seed, const ebic_allocator *alloc, void *stream, ebic_result **out);
 void ebic_result_free(ebic_result *r);
 
 /* Clustering error (Sec. 2.2, Eq. 1) of detected biclusters against a

@@ -317,6 +317,13 @@ int ebic_run(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
     return run_method(h_x, rows, cols, p, seed, alloc, static_cast<hipStream_t>(stream), out);
 }
 
+int ebic_run_device(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                    uint64_t seed, const ebic_allocator *alloc, void *stream, ebic_result **out) {
+    clear_error();
+    return run_method_device(h_x, rows, cols, p, seed, alloc, static_cast<hipStream_t>(stream),
+                             out);
+}
+
 int ebic_session_create(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
                         uint64_t seed, const ebic_allocator *alloc, void *stream,
                         ebic_session **out) {

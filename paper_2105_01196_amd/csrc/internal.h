@@ -85,6 +85,9 @@ int launch_build_pairs(const uint16_t *ranks, int32_t rows, int32_t cols, int32_
 
 int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
                const ebic_allocator *al, hipStream_t stream, ebic_result **out);
+int run_method_device(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                      uint64_t seed, const ebic_allocator *al, hipStream_t stream,
+                      ebic_result **out);
 void free_result(ebic_result *r);
 int ce_score(const ebic_bicluster *found, int32_t n_found, const ebic_bicluster *truth,
              int32_t n_truth, int32_t rows, int32_t cols, double *score, double *ce);

@@ -256,7 +256,11 @@ struct PinnedArray {
         if (e_ != hipSuccess) return check_hip(e_, #call); \
     } while (0)
 
+struct DevLoopAccess;
+
 class Job {
+    friend struct DevLoopAccess;  // the generations on the device (devloop.hip)
+
   public:
     Job(const ebic_params &p, uint64_t seed, hipStream_t stream)
         : p_(p), rng_(seed), stream_(stream), neg_(p.negative_trends != 0) {
@@ -433,6 +437,11 @@ class Job {
 };
 
 int check_run_params(int32_t rows, int32_t cols, const ebic_params *p);
+// The device loop's own limits on the run parameters.
+int devloop_check(int32_t cols, const ebic_params &p);
+// Runs a started job's generations on the device (devloop.hip), scoring
+// each population with *batch; on return the job is in its final step.
+int devloop_run(Job &job, Batch **batch, hipStream_t stream);
 // 64-bit hash of a float matrix's bytes (FNV-1a over 8-byte words).
 uint64_t matrix_hash(const float *x, size_t n);
 

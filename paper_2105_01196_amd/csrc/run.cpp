@@ -931,6 +931,21 @@ int session_result(Session *s, ebic_result **out) {
 
 void session_free(Session *s) { delete s; }
 
+int run_method_device(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p,
+                      uint64_t seed, const ebic_allocator *al, hipStream_t stream,
+                      ebic_result **out) {
+    if (!out || !p) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");
+    int rc = devloop_check(cols, *p);
+    if (rc) return rc;
+    std::unique_ptr<Session> s;
+    rc = session_begin(h_x, rows, cols, p, seed, al, stream, false, &s);
+    if (rc == EBIC_OK) rc = devloop_run(*s->job, &s->batch, s->stream);
+    int32_t done = 0;
+    while (rc == EBIC_OK && !done) rc = session_step(s.get(), 1 << 30, &done);
+    if (rc) return rc;
+    return session_result(s.get(), out);
+}
+
 int run_method(const float *h_x, int32_t rows, int32_t cols, const ebic_params *p, uint64_t seed,
                const ebic_allocator *al, hipStream_t stream, ebic_result **out) {
     if (!out) return fail(EBIC_ERR_INVALID_ARG, "NULL argument");

@@ -145,6 +145,9 @@ _SIGNATURES = {
     "ebic_run": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params), ctypes.c_uint64,
                                 ctypes.POINTER(ebic_allocator), _vp,
                                 ctypes.POINTER(ctypes.POINTER(ebic_result))]),
+    "ebic_run_device": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params), ctypes.c_uint64,
+                                ctypes.POINTER(ebic_allocator), _vp,
+                                ctypes.POINTER(ctypes.POINTER(ebic_result))]),
     "ebic_session_create": (ctypes.c_int, [_vp, _i32, _i32, ctypes.POINTER(ebic_params),
                                            ctypes.c_uint64, ctypes.POINTER(ebic_allocator), _vp,
                                            ctypes.POINTER(_vp)]),
@@ -625,6 +628,19 @@ def ebic_run(x: np.ndarray, params: ebic_params, seed: int, stream=None,
     res = ctypes.POINTER(ebic_result)()
     _check(lib().ebic_run(x.ctypes.data, R, C, ctypes.byref(params), ctypes.c_uint64(seed),
                           _alloc_ref(alloc), _stream(stream), ctypes.byref(res)))
+    return _take_result(res)
+
+
+def ebic_run_device(x: np.ndarray, params: ebic_params, seed: int, stream=None,
+                    alloc: Optional[TorchAllocator] = None) -> RunResult:
+    """ebic_run with every generation after the first on the device; the
+    same result for the same seed (synchronous)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    R, C = x.shape
+    res = ctypes.POINTER(ebic_result)()
+    _check(lib().ebic_run_device(x.ctypes.data, R, C, ctypes.byref(params),
+                                 ctypes.c_uint64(seed), _alloc_ref(alloc), _stream(stream),
+                                 ctypes.byref(res)))
     return _take_result(res)
 
 
