@@ -1287,6 +1287,21 @@ int batch_run(Batch *b, hipStream_t stream) {
     return EBIC_OK;
 }
 
+int batch_archive_fields(Batch *b, int32_t job, int32_t **size, int32_t **len) {
+    if (!b || job < 0 || job >= b->njobs || !b->d_jobs)
+        return fail(EBIC_ERR_INVALID_ARG, "bad batch or job");
+    // the table holds the jobs by population size, descending (stable)
+    int32_t at = 0;
+    for (int32_t i = 0; i < b->njobs; i++)
+        if (b->jobs[i].pop_size > b->jobs[job].pop_size ||
+            (b->jobs[i].pop_size == b->jobs[job].pop_size && i < job))
+            at++;
+    DevJob *d = b->d_jobs + at;
+    *size = &d->arch_size;
+    *len = &d->arch_len;
+    return EBIC_OK;
+}
+
 int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb, int32_t *wpl) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (cpi) *cpi = b->cpi;

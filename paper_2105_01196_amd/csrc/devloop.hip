@@ -39,7 +39,8 @@ constexpr int kDlMaxT = 16;        // largest tournament of the device loop
 constexpr int kDlMaxP = 8192;      // largest population (sort keys of the list update in LDS)
 constexpr int kSeg = 256;          // draw offsets per segment of the chain walk
 constexpr int kSpanMax = 65535;    // draw offsets tried per chunk
-constexpr int kChunkMax = 8192;    // attempts per chunk
+constexpr int kChunkMax = 6144;    // attempts per chunk
+constexpr int kDedupSlots = 8192;  // LDS hash table of a chunk's children (load <= 3/4)
 constexpr int kBlock = 1024;       // threads of the single-workgroup kernels
 constexpr int kChildWaves = 4;     // waves per workgroup of the child kernel
 constexpr int kMaxCols = EBIC_MAX_COLS;
@@ -72,6 +73,10 @@ struct DlState {
     int32_t error;        // the tabu arena is full
     int32_t arch_len;     // columns of the packed top-rank list
     int32_t slow;         // chunks whose chain needed the sequential walk
+    int32_t over;         // the run has stopped: every later kernel does nothing
+    int32_t pending;      // the chunk's accepted children await insertion
+    int32_t stalled;      // a fill needs more chunks than were queued: kernels
+                          // wait (do nothing) until the host has finished it
     int32_t slot[EBIC_MAX_ARCHIVE + 2];   // the list in rank order: slot ids
     int32_t a_len[EBIC_MAX_ARCHIVE + 2];  // per slot id: length, rows, score
     int32_t a_n[EBIC_MAX_ARCHIVE + 2];
@@ -88,6 +93,7 @@ struct DlBufs {
     int32_t *cnt;
     uint64_t *sup;          // [P][W]
     double *keys;           // tournament keys
+    int32_t *use[2];        // column use counts of a population (by its parity), [C]
     uint16_t *aslot_cols;   // top-rank list members by slot, [K+2][kmax]
     uint64_t *aslot_sup;    // [K+2][W]
     int32_t *arch_off;      // the list packed for the evaluator, in rank order
@@ -99,6 +105,8 @@ struct DlBufs {
     int32_t *clen;          // [kChunkMax] 0: no weighted operator applied
     uint32_t *cflag;        // [kChunkMax] kValid, kRev, kInSet, kAccept
     uint64_t *chash;        // [kChunkMax] hash of the canonical child
+    int32_t *cslot;         // [kChunkMax] an accepted child's slot in the next population
+    int32_t *carena;        // [kChunkMax] and its tabu arena entry
     uint64_t *thash;        // tabu table: hash (0 = empty slot)
     int32_t *tref;          // tabu table: arena entry
     uint16_t *tarena;       // [tabu_cap][kmax] canonical series
@@ -344,6 +352,11 @@ __device__ void bitonic_sort(uint64_t *hi, uint64_t *lo, int n) {
 
 // ---- kernels ----
 
+// Whether the fill has a chunk of attempts to run now.
+__device__ __forceinline__ bool fill_active(const DlState *st) {
+    return !st->over && !st->stalled && st->need_more;
+}
+
 // Steps 3 and 7 (top-rank list) for the population just scored, the trace
 // entry, the stop checks and step 4 (elitism); finally the list packed for
 // the next evaluation. One workgroup.
@@ -351,44 +364,82 @@ __device__ void bitonic_sort(uint64_t *hi, uint64_t *lo, int n) {
 // Candidates (a positive size score, not on the list already in canonical
 // form) are sorted by (score descending, series ascending): a bitonic sort
 // on (score bits, first three columns, index), runs that tie on both then
-// ordered by their whole series. Candidates are then taken in that order as
-// on the host: the wave of each member counts the columns and rows the
-// candidate shares with it.
+// ordered by their whole series. They are then taken in that order as on
+// the host, a batch at a time: each wave compares one candidate of the
+// batch with every member of the list as it stands (shared columns from the
+// candidate's column bitmap, shared rows when the columns allow a clash),
+// and one thread applies the admission rule to the batch's candidates in
+// order. A rejected candidate leaves the list as it was, so the next
+// candidate's comparisons still hold; after an admission the next batch
+// starts from the following candidate against the new list.
+constexpr int kListWaves = kBlock / kWave;
+constexpr int kListSlots = EBIC_MAX_ARCHIVE + 2;
+
+// Dynamic LDS of the list kernel: the sort keys, later the candidate order
+// and one column bitmap per wave; then a byte per individual (its tier).
+__host__ __device__ inline size_t list_lds_shared(int Ppad, int C) {
+    const size_t sort = (size_t)Ppad * 16;
+    const size_t loop = (size_t)Ppad * 4 + (size_t)kListWaves * ((C + 31) / 32) * 4;
+    return ((sort > loop ? sort : loop) + 7) & ~(size_t)7;
+}
+size_t list_lds_bytes(int Ppad, int C) { return list_lds_shared(Ppad, C) + (size_t)Ppad; }
+
+__device__ inline uint32_t pow2_dev(uint32_t x) {
+    uint32_t v = 1;
+    while (v < x) v <<= 1;
+    return v;
+}
+
 __global__ void __launch_bounds__(kBlock) dl_list_kernel(DlParams q, DlBufs B, int cur, int Pn,
                                                          int Ppad) {
     extern __shared__ uint64_t s_dyn[];
     uint64_t *s_k1 = s_dyn, *s_k2 = s_dyn + Ppad;
-    uint32_t *s_bits = reinterpret_cast<uint32_t *>(s_dyn + 2 * (size_t)Ppad);
-    __shared__ int s_tmp[33];
-    __shared__ int32_t s_list[EBIC_MAX_ARCHIVE + 2], s_arev[EBIC_MAX_ARCHIVE + 2];
-    __shared__ int32_t s_ov[EBIC_MAX_ARCHIVE + 2], s_abv[EBIC_MAX_ARCHIVE + 2];
-    __shared__ int32_t s_nA, s_nc, s_fix, s_cand, s_brk, s_new;
+    int32_t *s_order = reinterpret_cast<int32_t *>(s_dyn);
+    const int BW = (q.C + 31) / 32;
+    uint32_t *s_wbits = reinterpret_cast<uint32_t *>(s_dyn) + Ppad;
+    uint8_t *s_tier = reinterpret_cast<uint8_t *>(s_dyn) + list_lds_shared(Ppad, q.C);
+    __shared__ int32_t s_list[kListSlots], s_arev[kListSlots];
+    __shared__ int32_t s_alen[kListSlots], s_an[kListSlots];
+    __shared__ double s_asc[kListSlots];
+    __shared__ int8_t s_ov[kListWaves][kListSlots], s_abv[kListWaves][kListSlots];
+    __shared__ int32_t s_nA, s_nc, s_fix, s_next, s_done, s_new, s_newi, s_stop;
+    (void)s_next;
     DlState *st = B.st;
     const int tid = threadIdx.x, nt = blockDim.x, lane = tid % kWave, wave = tid / kWave;
-    const int nwaves = nt / kWave, kmax = q.kmax, W = q.W;
+    const int kmax = q.kmax, W = q.W;
     const uint16_t *pop = B.pop[cur];
     const int32_t *plen = B.plen[cur];
     auto score_of = [&](int i) {
         const int n = B.cnt[i], k = plen[i];
         return (n >= q.min_rows && k >= q.k_score_min) ? ldexp((double)n, k) : 0.0;
     };
+    auto mcols = [&](int sl) { return B.aslot_cols + (size_t)sl * kmax; };
+    if (st->over || st->stalled) return;
     if (tid == 0) {
         s_nA = st->nA;
         s_nc = 0;
         s_fix = 0;
     }
-    for (int j = tid; j < EBIC_MAX_ARCHIVE + 2; j += nt) s_list[j] = st->slot[j];
-    for (int w = tid; w < (q.C + 31) / 32; w += nt) s_bits[w] = 0;
+    for (int j = tid; j < kListSlots; j += nt) {
+        s_list[j] = st->slot[j];
+        s_alen[j] = st->a_len[j];
+        s_an[j] = st->a_n[j];
+        s_asc[j] = st->a_score[j];
+    }
     __syncthreads();
     int nA = s_nA;
     for (int j = tid; j < nA; j += nt) {
         const int sl = s_list[j];
-        s_arev[j] = q.neg && reverse_smaller_seq(B.aslot_cols + (size_t)sl * kmax, st->a_len[sl]);
+        s_arev[j] = q.neg && reverse_smaller_seq(mcols(sl), s_alen[sl]);
     }
     __syncthreads();
-    // sort keys: candidates first by (score descending, first columns, index)
+    // Candidates in two tiers: while the list is full only those ranking
+    // above its last member can enter (tier 1); the rest (tier 2) are needed
+    // only if the list falls short of full after tier 1 (an admission can
+    // remove several members). Each tier is sorted when it is reached.
+    const int nA0 = nA;
     for (int i = tid; i < Ppad; i += nt) {
-        uint64_t k1 = ~0ull, k2 = ~0ull;
+        int t = 0;
         if (i < Pn) {
             const int k = plen[i];
             const uint16_t *si = pop + (size_t)i * kmax;
@@ -398,199 +449,278 @@ __global__ void __launch_bounds__(kBlock) dl_list_kernel(DlParams q, DlBufs B, i
                 const bool rv = q.neg && reverse_smaller_seq(si, k);
                 for (int j = 0; j < nA && cand; j++) {
                     const int sl = s_list[j];
-                    if (st->a_len[sl] != k) continue;
-                    const uint16_t *ms = B.aslot_cols + (size_t)sl * kmax;
+                    if (s_alen[sl] != k) continue;
+                    const uint16_t *ms = mcols(sl);
                     int e = 0;
                     while (e < k && canon_at(si, k, rv, e) == canon_at(ms, k, s_arev[j] != 0, e)) e++;
                     if (e == k) cand = false;
                 }
             }
             if (cand) {
-                k1 = ~(uint64_t)__double_as_longlong(sc);
-                uint64_t pre = 0;
-                for (int e = 0; e < 3; e++) pre = pre << 17 | (e < k ? (uint64_t)si[e] + 1 : 0);
-                k2 = pre << 13 | (uint64_t)i;
-            }
-        }
-        s_k1[i] = k1;
-        s_k2[i] = k2;
-    }
-    __syncthreads();
-    bitonic_sort(s_k1, s_k2, Ppad);
-    for (int i = tid; i < Ppad; i += nt) {
-        if (s_k1[i] != ~0ull && (i + 1 == Ppad || s_k1[i + 1] == ~0ull)) s_nc = i + 1;
-        if (i + 1 < Ppad && s_k1[i] != ~0ull && s_k1[i] == s_k1[i + 1] &&
-            (s_k2[i] >> 13) == (s_k2[i + 1] >> 13))
-            s_fix = 1;
-    }
-    __syncthreads();
-    const int nc = s_nc;
-    if (s_fix && tid == 0) {
-        // runs equal in score and first three columns: order by the whole series
-        for (int a = 0; a < nc;) {
-            int b = a + 1;
-            while (b < nc && s_k1[b] == s_k1[a] && (s_k2[b] >> 13) == (s_k2[a] >> 13)) b++;
-            for (int x = a + 1; x < b; x++) {
-                const uint64_t kx = s_k2[x];
-                const int ix = (int)(kx & 0x1FFF);
-                int y = x - 1;
-                while (y >= a) {
-                    const int iy = (int)(s_k2[y] & 0x1FFF);
-                    if (series_cmp_seq(pop + (size_t)ix * kmax, plen[ix], pop + (size_t)iy * kmax,
-                                       plen[iy]) >= 0)
-                        break;
-                    s_k2[y + 1] = s_k2[y];
-                    y--;
+                t = 1;
+                if (nA0 == q.K) {
+                    const int sl = s_list[nA0 - 1];
+                    if (!ranks_above_dev(sc, si, k, s_asc[sl], mcols(sl), s_alen[sl])) t = 2;
                 }
-                s_k2[y + 1] = kx;
             }
-            a = b;
         }
+        s_tier[i] = (uint8_t)t;
     }
     __syncthreads();
-    for (int ci = 0; ci < nc; ci++) {
-        if (tid == 0) {
-            const int i = (int)(s_k2[ci] & 0x1FFF);
-            s_cand = i;
-            bool brk = false;
-            if (s_nA == q.K) {
-                const int sl = s_list[s_nA - 1];
-                brk = !ranks_above_dev(score_of(i), pop + (size_t)i * kmax, plen[i],
-                                       st->a_score[sl], B.aslot_cols + (size_t)sl * kmax,
-                                       st->a_len[sl]);
-            }
-            s_brk = brk;
-        }
-        __syncthreads();
-        if (s_brk) break;
-        const int i = s_cand, k = plen[i], n = B.cnt[i];
+    uint32_t *bits = s_wbits + (size_t)wave * BW;
+    // one wave: its candidate against the member in slot sl
+    auto compare = [&](int i, int sl) {
+        const int k = plen[i], n = B.cnt[i], lj = s_alen[sl];
         const double sc = score_of(i);
-        const uint16_t *si = pop + (size_t)i * kmax;
-        const uint64_t *supi = B.sup + (size_t)i * W;
-        for (int e = tid; e < k; e += nt) {
-            const int c = si[e];
-            atomicOr(&s_bits[c >> 5], 1u << (c & 31));
-        }
-        __syncthreads();
-        nA = s_nA;
+        const uint16_t *si = pop + (size_t)i * kmax, *ms = mcols(sl);
         const long long bound = (long long)q.theta * n * k;
-        for (int j = wave; j < nA; j += nwaves) {
-            const int sl = s_list[j], lj = st->a_len[sl];
-            const uint16_t *ms = B.aslot_cols + (size_t)sl * kmax;
-            int g = 0;
-            for (int e = lane; e < lj; e += kWave) {
-                const int c = ms[e];
-                g += (s_bits[c >> 5] >> (c & 31)) & 1;
-            }
-            g = wave_sum(g);
-            const int nj = st->a_n[sl];
-            int ov = 0;
-            // h <= min(n, n_j): when even that cannot reach the bound the rows
-            // need no counting
-            if (1000LL * (n < nj ? n : nj) * g > bound) {
-                const uint64_t *supj = B.aslot_sup + (size_t)sl * W;
-                int h = 0;
-                for (int w = lane; w < W; w += kWave) h += __popcll(supi[w] & supj[w]);
-                h = wave_sum(h);
-                ov = 1000LL * h * g > bound;
-            }
-            if (lane == 0) {
-                s_ov[j] = ov;
-                s_abv[j] = ov ? ranks_above_dev(sc, si, k, st->a_score[sl], ms, lj) : 1;
-            }
+        int g = 0;
+        for (int e = lane; e < lj; e += kWave) {
+            const int c = ms[e];
+            g += (bits[c >> 5] >> (c & 31)) & 1;
         }
-        __syncthreads();
+        g = wave_sum(g);
+        const int nj = s_an[sl];
+        int ov = 0;
+        // h <= min(n, n_j): when even that cannot reach the bound the rows
+        // need no counting
+        if (1000LL * (n < nj ? n : nj) * g > bound) {
+            const uint64_t *supi = B.sup + (size_t)i * W, *supj = B.aslot_sup + (size_t)sl * W;
+            int h = 0;
+            for (int w = lane; w < W; w += kWave) h += __popcll(supi[w] & supj[w]);
+            h = wave_sum(h);
+            ov = 1000LL * h * g > bound;
+        }
+        if (lane == 0) {
+            s_ov[wave][sl] = (int8_t)ov;
+            s_abv[wave][sl] = (int8_t)(ov ? ranks_above_dev(sc, si, k, s_asc[sl], ms, lj) : 1);
+        }
+    };
+    if (tid == 0) s_done = 0;
+    for (int tier = 1; tier <= 2; tier++) {
         if (tid == 0) {
-            bool any = false, beats = true;
-            for (int j = 0; j < nA; j++)
-                if (s_ov[j]) {
-                    any = true;
-                    if (!s_abv[j]) beats = false;
-                }
-            int ns = -1;
-            if (!any || beats) {
-                // the members it overlaps leave (it outranks them)
-                int m = 0;
-                for (int j = 0; j < nA; j++)
-                    if (!s_ov[j]) s_list[m++] = s_list[j];
-                nA = m;
-                // a free slot (at most K are in use)
-                for (ns = 0;; ns++) {
-                    bool taken = false;
-                    for (int j = 0; j < nA; j++) taken |= s_list[j] == ns;
-                    if (!taken) break;
-                }
-                int pos = 0;
-                while (pos < nA) {
-                    const int sl = s_list[pos];
-                    if (!ranks_above_dev(st->a_score[sl], B.aslot_cols + (size_t)sl * kmax,
-                                         st->a_len[sl], sc, si, k))
-                        break;
-                    pos++;
-                }
-                for (int j = nA; j > pos; j--) s_list[j] = s_list[j - 1];
-                s_list[pos] = ns;
-                nA++;
-                st->a_len[ns] = k;
-                st->a_n[ns] = n;
-                st->a_score[ns] = sc;
-                if (nA > q.K) nA--;  // the last one leaves
-                s_nA = nA;
-            }
-            s_new = ns;
+            s_nc = 0;
+            // every tier-2 candidate ranks below the list's last member while
+            // it is full: nothing more can enter
+            if (tier == 2 && s_nA == q.K) s_done = 1;
         }
         __syncthreads();
-        const int ns = s_new;
-        if (ns >= 0) {
-            for (int e = tid; e < k; e += nt) B.aslot_cols[(size_t)ns * kmax + e] = si[e];
-            for (int w = tid; w < W; w += nt) B.aslot_sup[(size_t)ns * W + w] = supi[w];
+        if (s_done) break;
+        for (int i = tid; i < Pn; i += nt) {
+            if (s_tier[i] != tier) continue;
+            const int k = plen[i];
+            const uint16_t *si = pop + (size_t)i * kmax;
+            uint64_t pre = 0;
+            for (int e = 0; e < 3; e++) pre = pre << 17 | (e < k ? (uint64_t)si[e] + 1 : 0);
+            const int x = atomicAdd(&s_nc, 1);
+            s_k1[x] = ~(uint64_t)__double_as_longlong(score_of(i));
+            s_k2[x] = pre << 13 | (uint64_t)i;
         }
-        for (int e = tid; e < k; e += nt) {
-            const int c = si[e];
-            atomicAnd(&s_bits[c >> 5], ~(1u << (c & 31)));
+        __syncthreads();
+        const int nc = s_nc;
+        if (nc == 0) continue;
+        const int Pt = (int)pow2_dev((uint32_t)(nc < 2 ? 2 : nc));
+        for (int x = nc + tid; x < Pt; x += nt) s_k1[x] = s_k2[x] = ~0ull;
+        if (tid == 0) s_fix = 0;
+        __syncthreads();
+        bitonic_sort(s_k1, s_k2, Pt);
+        for (int x = tid; x + 1 < nc; x += nt)
+            if (s_k1[x] == s_k1[x + 1] && (s_k2[x] >> 13) == (s_k2[x + 1] >> 13)) s_fix = 1;
+        __syncthreads();
+        if (s_fix) {
+            // runs equal in score and first three columns: by the whole series,
+            // each run by the thread that finds its start
+            auto same_key = [&](int x, int y) {
+                return s_k1[x] == s_k1[y] && (s_k2[x] >> 13) == (s_k2[y] >> 13);
+            };
+            for (int a = tid; a + 1 < nc; a += nt) {
+                if ((a > 0 && same_key(a - 1, a)) || !same_key(a, a + 1)) continue;
+                int b = a + 1;
+                while (b < nc && same_key(a, b)) b++;
+                for (int x = a + 1; x < b; x++) {
+                    const uint64_t kx = s_k2[x];
+                    const int ix = (int)(kx & 0x1FFF);
+                    int y = x - 1;
+                    while (y >= a) {
+                        const int iy = (int)(s_k2[y] & 0x1FFF);
+                        if (series_cmp_seq(pop + (size_t)ix * kmax, plen[ix],
+                                           pop + (size_t)iy * kmax, plen[iy]) >= 0)
+                            break;
+                        s_k2[y + 1] = s_k2[y];
+                        y--;
+                    }
+                    s_k2[y + 1] = kx;
+                }
+            }
+        }
+        __syncthreads();
+        // the order, then the waves' column bitmaps, in the sort's LDS
+        {
+            constexpr int kMaxPer = kDlMaxP / kBlock;
+            int32_t mine[kMaxPer];
+#pragma unroll
+            for (int r = 0; r < kMaxPer; r++) {
+                const int x = tid + r * nt;
+                mine[r] = x < nc ? (int32_t)(s_k2[x] & 0x1FFF) : 0;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < kMaxPer; r++) {
+                const int x = tid + r * nt;
+                if (x < nc) s_order[x] = mine[r];
+            }
+            for (int w = tid; w < kListWaves * BW; w += nt) s_wbits[w] = 0;
+            __syncthreads();
+        }
+        for (int ci = 0; ci < nc; ci += kListWaves) {
+            // each wave: one candidate of the batch against the list
+            nA = s_nA;
+            const int cw = ci + wave, ic = cw < nc ? s_order[cw] : -1;
+            if (ic >= 0) {
+                const uint16_t *si = pop + (size_t)ic * kmax;
+                for (int e = lane; e < plen[ic]; e += kWave) {
+                    const int c = si[e];
+                    atomicOr(&bits[c >> 5], 1u << (c & 31));
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                for (int j = 0; j < nA; j++) compare(ic, s_list[j]);
+            }
+            __syncthreads();
+            int from = 0;
+            for (;;) {
+                if (tid == 0) {
+                    int ns = -1, ni = -1, w = from;
+                    for (; w < kListWaves; w++) {
+                        const int c = ci + w;
+                        if (c >= nc) break;
+                        const int i = s_order[c], k = plen[i];
+                        const double sc = score_of(i);
+                        const uint16_t *si = pop + (size_t)i * kmax;
+                        if (nA == q.K) {
+                            const int sl = s_list[nA - 1];
+                            if (!ranks_above_dev(sc, si, k, s_asc[sl], mcols(sl), s_alen[sl])) {
+                                s_done = 1;
+                                break;
+                            }
+                        }
+                        bool any = false, beats = true;
+                        for (int j = 0; j < nA; j++) {
+                            const int sl = s_list[j];
+                            if (s_ov[w][sl]) {
+                                any = true;
+                                if (!s_abv[w][sl]) beats = false;
+                            }
+                        }
+                        if (any && !beats) continue;  // rejected: the list stays as it is
+                        // admitted: the members it overlaps leave (it outranks them)
+                        int m = 0;
+                        for (int j = 0; j < nA; j++)
+                            if (!s_ov[w][s_list[j]]) s_list[m++] = s_list[j];
+                        nA = m;
+                        for (ns = 0;; ns++) {  // a free slot (at most K are in use)
+                            bool taken = false;
+                            for (int j = 0; j < nA; j++) taken |= s_list[j] == ns;
+                            if (!taken) break;
+                        }
+                        int pos = 0;
+                        while (pos < nA) {
+                            const int sl = s_list[pos];
+                            if (!ranks_above_dev(s_asc[sl], mcols(sl), s_alen[sl], sc, si, k)) break;
+                            pos++;
+                        }
+                        for (int j = nA; j > pos; j--) s_list[j] = s_list[j - 1];
+                        s_list[pos] = ns;
+                        nA++;
+                        s_alen[ns] = k;
+                        s_an[ns] = B.cnt[i];
+                        s_asc[ns] = sc;
+                        if (nA > q.K) nA--;  // the last one leaves
+                        ni = i;
+                        w++;
+                        break;
+                    }
+                    s_nA = nA;
+                    s_new = ns;
+                    s_newi = ni;
+                    s_next = w;
+                }
+                __syncthreads();
+                const int ns = s_new;
+                if (ns < 0) break;
+                {
+                    const int i = s_newi, k = plen[i];
+                    for (int e = tid; e < k; e += nt)
+                        B.aslot_cols[(size_t)ns * kmax + e] = pop[(size_t)i * kmax + e];
+                    for (int w = tid; w < W; w += nt)
+                        B.aslot_sup[(size_t)ns * W + w] = B.sup[(size_t)i * W + w];
+                }
+                __syncthreads();
+                from = s_next;
+                if (s_done) break;
+                // the rest of the batch against the new member only
+                if (ic >= 0 && wave >= from) compare(ic, ns);
+                __syncthreads();
+                nA = s_nA;
+            }
+            if (ic >= 0) {
+                const uint16_t *si = pop + (size_t)ic * kmax;
+                for (int e = lane; e < plen[ic]; e += kWave) {
+                    const int c = si[e];
+                    atomicAnd(&bits[c >> 5], ~(1u << (c & 31)));
+                }
+            }
+            __syncthreads();
+            if (s_done) break;
         }
         __syncthreads();
     }
-    __syncthreads();
     nA = s_nA;
     if (tid == 0) {
         st->nA = nA;
-        for (int j = 0; j < EBIC_MAX_ARCHIVE + 2; j++) st->slot[j] = j < nA ? s_list[j] : -1;
+        for (int j = 0; j < kListSlots; j++) {
+            st->slot[j] = j < nA ? s_list[j] : -1;
+            st->a_len[j] = s_alen[j];
+            st->a_n[j] = s_an[j];
+            st->a_score[j] = s_asc[j];
+        }
         const int g = st->g;
         double *tr = B.trace + (size_t)g * 4;
         tr[0] = (double)Pn;
         tr[1] = (double)nA;
-        tr[2] = nA ? st->a_score[s_list[0]] : 0.0;
+        tr[2] = nA ? s_asc[s_list[0]] : 0.0;
         tr[3] = (double)st->hits;
         st->evaluations += Pn;
         st->g = g + 1;
         if (!st->stop && g + 1 == q.G) st->stop = EBIC_STOP_GENERATIONS;
+        if (st->stop) st->over = 1;
         int at = 0;
         for (int j = 0; j < nA; j++) {
             B.arch_off[j] = at;
-            at += st->a_len[s_list[j]];
+            at += s_alen[s_list[j]];
         }
         B.arch_off[nA] = at;
         st->arch_len = at;
-        s_tmp[0] = st->stop;
+        s_stop = st->stop;
     }
     __syncthreads();
-    // the list packed for the evaluator, in rank order
-    for (int j = 0; j < nA; j++) {
-        const int sl = s_list[j], lj = st->a_len[sl], at = B.arch_off[j];
-        for (int e = tid; e < lj; e += nt) B.arch_cols[at + e] = B.aslot_cols[(size_t)sl * kmax + e];
-        for (int w = tid; w < W; w += nt)
+    // the list packed for the evaluator, in rank order: a wave per member
+    for (int j = wave; j < nA; j += kListWaves) {
+        const int sl = s_list[j], lj = s_alen[sl], at = B.arch_off[j];
+        for (int e = lane; e < lj; e += kWave)
+            B.arch_cols[at + e] = B.aslot_cols[(size_t)sl * kmax + e];
+        for (int w = lane; w < W; w += kWave)
             B.arch_sup[(size_t)j * W + w] = B.aslot_sup[(size_t)sl * W + w];
     }
-    if (s_tmp[0]) return;
+    if (s_stop) return;
     // step 4: the list's first members (at most half the population) start
     // the next one
     const int nxt = cur ^ 1, ne = nA < q.P / 2 ? nA : q.P / 2;
-    for (int j = 0; j < ne; j++) {
-        const int sl = s_list[j], lj = st->a_len[sl];
-        for (int e = tid; e < lj; e += nt)
+    for (int j = wave; j < ne; j += kListWaves) {
+        const int sl = s_list[j], lj = s_alen[sl];
+        for (int e = lane; e < lj; e += kWave)
             B.pop[nxt][(size_t)j * kmax + e] = B.aslot_cols[(size_t)sl * kmax + e];
-        if (tid == 0) B.plen[nxt][j] = lj;
+        if (lane == 0) B.plen[nxt][j] = lj;
     }
     if (tid == 0) {
         st->Nn = ne;
@@ -600,33 +730,33 @@ __global__ void __launch_bounds__(kBlock) dl_list_kernel(DlParams q, DlBufs B, i
 }
 
 // Step 5, tournament keys: each fitness halved once per column of the
-// individual that more individuals hold than ceil(sum k / C). One workgroup.
-__global__ void __launch_bounds__(kBlock) dl_keys_kernel(DlParams q, DlBufs B, int cur, int Pn) {
-    extern __shared__ int32_t s_use[];
-    __shared__ long long s_sum[kBlock / kWave];
-    const int tid = threadIdx.x, nt = blockDim.x, kmax = q.kmax;
-    const uint16_t *pop = B.pop[cur];
-    const int32_t *plen = B.plen[cur];
-    for (int c = tid; c < q.C; c += nt) s_use[c] = 0;
-    __syncthreads();
-    long long ks = 0;
-    for (int i = tid; i < Pn; i += nt) {
-        const int k = plen[i];
-        ks += k;
-        for (int e = 0; e < k; e++) atomicAdd(&s_use[pop[(size_t)i * kmax + e]], 1);
-    }
-    for (int o = 32; o >= 1; o >>= 1) ks += __shfl_xor(ks, o, kWave);
-    if (tid % kWave == 0) s_sum[tid / kWave] = ks;
-    __syncthreads();
-    long long ksum = 0;
-    for (int w = 0; w < nt / kWave; w++) ksum += s_sum[w];
+// individual that more individuals hold than ceil(sum k / C). Two grid-wide
+// kernels, a wave per individual: the column use counts (into the count
+// array of the population's parity), then the keys (the counts of the other
+// parity are cleared for the next generation).
+__global__ void __launch_bounds__(256) dl_use_kernel(DlParams q, DlBufs B, int cur, int Pn) {
+    if (B.st->over || B.st->stalled) return;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    if (i >= Pn) return;
+    const int k = B.plen[cur][i];
+    const uint16_t *s = B.pop[cur] + (size_t)i * q.kmax;
+    for (int e = lane; e < k; e += kWave) atomicAdd(&B.use[cur][s[e]], 1);
+}
+
+__global__ void __launch_bounds__(256) dl_keys_kernel(DlParams q, DlBufs B, int cur, int Pn) {
+    if (B.st->over || B.st->stalled) return;
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int c = gt; c < q.C; c += gridDim.x * blockDim.x) B.use[cur ^ 1][c] = 0;
+    const int i = gt / kWave, lane = threadIdx.x % kWave;
+    if (i >= Pn) return;
+    const long long ksum = B.csr_off[Pn];  // columns of the population
     const long long share = (ksum + q.C - 1) / q.C;
-    for (int i = tid; i < Pn; i += nt) {
-        const int k = plen[i];
-        int over = 0;
-        for (int e = 0; e < k; e++) over += s_use[pop[(size_t)i * kmax + e]] > share;
-        B.keys[i] = ldexp(B.fit[i], -over);
-    }
+    const int k = B.plen[cur][i];
+    const uint16_t *s = B.pop[cur] + (size_t)i * q.kmax;
+    int over = 0;
+    for (int e = lane; e < k; e += kWave) over += B.use[cur][s[e]] > share;
+    over = wave_sum(over);
+    if (lane == 0) B.keys[i] = ldexp(B.fit[i], -over);
 }
 
 // The number of draws an attempt starting at each offset of the span would
@@ -634,7 +764,7 @@ __global__ void __launch_bounds__(kBlock) dl_keys_kernel(DlParams q, DlBufs B, i
 __global__ void __launch_bounds__(256) dl_span_kernel(DlParams q, DlBufs B, int cur, int Pn,
                                                       int S) {
     const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= S) return;
+    if (o >= S || !fill_active(B.st)) return;
     Draws d{B.st->rng, (uint64_t)o};
     Attempt at;
     draw_attempt(d, q, B.keys, B.plen[cur], Pn, at);
@@ -660,7 +790,13 @@ __global__ void __launch_bounds__(kBlock) dl_chain_kernel(DlParams q, DlBufs B, 
     int32_t *s_entry = reinterpret_cast<int32_t *>(s_exit + (((size_t)nseg * E + 7) & ~(size_t)7));
     int32_t *s_base = s_entry + nseg;
     __shared__ int s_bad, s_total;
+    constexpr int kGroup = 16, kMaxGroups = (kSpanMax / kSeg + 1 + kGroup - 1) / kGroup;
+    __shared__ uint16_t s_gcnt[kMaxGroups * (2 * kDlMaxT + 12)];
+    __shared__ uint8_t s_gexit[kMaxGroups * (2 * kDlMaxT + 12)];
+    __shared__ int32_t s_gentry[kMaxGroups], s_gbase[kMaxGroups];
     const int tid = threadIdx.x, nt = blockDim.x;
+    if (tid == 0) B.st->pending = 0;  // nothing of an earlier chunk is inserted again
+    if (!fill_active(B.st)) return;
     if (tid == 0) {
         s_bad = 0;
         s_total = 0;
@@ -686,20 +822,42 @@ __global__ void __launch_bounds__(kBlock) dl_chain_kernel(DlParams q, DlBufs B, 
             s_exit[pr] = (uint8_t)(ex > 0 ? ex : 0);
         }
         __syncthreads();
+        // link the segments: groups of kGroup segments composed from every
+        // entry offset in parallel, the groups linked in order, then each
+        // group's segments given their entries and first attempt indices
+        const int ngroup = (nseg + kGroup - 1) / kGroup;
+        for (int pr = tid; pr < ngroup * E; pr += nt) {
+            const int gr = pr / E, s0 = gr * kGroup;
+            const int s1 = s0 + kGroup < nseg ? s0 + kGroup : nseg;
+            int e = pr % E, cnt = 0;
+            for (int sg = s0; sg < s1; sg++) {
+                cnt += s_cnt[sg * E + e];
+                e = s_exit[sg * E + e];  // the next segment's entry offset (below E)
+            }
+            s_gcnt[pr] = (uint16_t)cnt;
+            s_gexit[pr] = (uint8_t)e;
+        }
+        __syncthreads();
         if (tid == 0) {
-            int pos = 0, idx = 0;
-            for (int sg = 0; sg < nseg; sg++) {
-                const int e = pos - sg * kSeg;
-                s_entry[sg] = pos;
-                s_base[sg] = idx;
-                if (e >= E) {  // cannot happen with every draw count below E
-                    s_bad = 1;
-                    break;
-                }
-                idx += s_cnt[sg * E + e];
-                pos = (sg + 1) * kSeg + s_exit[sg * E + e];
+            int e = 0, idx = 0;
+            for (int gr = 0; gr < ngroup; gr++) {
+                s_gentry[gr] = e;
+                s_gbase[gr] = idx;
+                idx += s_gcnt[gr * E + e];
+                e = s_gexit[gr * E + e];
             }
             s_total = idx;
+        }
+        __syncthreads();
+        for (int gr = tid; gr < ngroup; gr += nt) {
+            const int s0 = gr * kGroup, s1 = s0 + kGroup < nseg ? s0 + kGroup : nseg;
+            int e = s_gentry[gr], idx = s_gbase[gr];
+            for (int sg = s0; sg < s1; sg++) {
+                s_entry[sg] = sg * kSeg + e;
+                s_base[sg] = idx;
+                idx += s_cnt[sg * E + e];
+                e = s_exit[sg * E + e];
+            }
         }
         __syncthreads();
     }
@@ -791,7 +949,7 @@ __global__ void __launch_bounds__(kChildWaves *kWave) dl_child_kernel(DlParams q
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int i = blockIdx.x * kChildWaves + wave;
     const int A = B.st->chunk_n;
-    if (i >= A) return;  // whole wave
+    if (i >= A || !fill_active(B.st)) return;  // whole wave
     uint32_t *bits = s_bits[wave];
     uint16_t *ch = s_child[wave];
     const int kmax = q.kmax;
@@ -924,52 +1082,81 @@ __global__ void __launch_bounds__(kChildWaves *kWave) dl_child_kernel(DlParams q
 // next population. One workgroup.
 __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
                                                            const int32_t *att_end, int cur,
-                                                           int Apad) {
+                                                           int last_chunk) {
     extern __shared__ uint64_t s_dyn[];
-    uint64_t *s_h = s_dyn, *s_i = s_dyn + Apad;
+    uint64_t *s_th = s_dyn;                                          // hash, 0 = empty
+    uint32_t *s_ti = reinterpret_cast<uint32_t *>(s_dyn + kDedupSlots);  // smallest attempt
     __shared__ int s_tmp[33];
     DlState *st = B.st;
     const int tid = threadIdx.x, nt = blockDim.x, kmax = q.kmax;
+    if (!fill_active(st)) return;
     const int A = st->chunk_n;
-    for (int i = tid; i < Apad; i += nt) {
-        const bool v = i < A && (B.cflag[i] & kValid);
-        s_h[i] = v ? B.chash[i] : ~0ull;
-        s_i[i] = v ? (uint64_t)i : ~0ull;
+    constexpr uint32_t kMask = kDedupSlots - 1;
+    for (int x = tid; x < kDedupSlots; x += nt) {
+        s_th[x] = 0;
+        s_ti[x] = 0xFFFFFFFFu;
     }
     __syncthreads();
-    bitonic_sort(s_h, s_i, Apad);
-    for (int x = tid; x < Apad; x += nt) {
-        if (s_i[x] == ~0ull) continue;
-        const int i = (int)s_i[x];
-        const int li = B.clen[i];
-        const bool ri = (B.cflag[i] & kRev) != 0;
-        const uint16_t *ci = B.child + (size_t)i * kmax;
-        for (int y = x - 1; y >= 0 && s_h[y] == s_h[x] && s_i[y] != ~0ull; y--) {
-            const int j = (int)s_i[y];  // j < i: sorted by (hash, index)
-            if (B.clen[j] != li) continue;
-            const bool rj = (B.cflag[j] & kRev) != 0;
-            const uint16_t *cj = B.child + (size_t)j * kmax;
-            int e = 0;
-            while (e < li && canon_at(ci, li, ri, e) == canon_at(cj, li, rj, e)) e++;
-            if (e == li) {
-                atomicOr(&B.cflag[i], kDup);
+    // a chunk's children that repeat an earlier child of the chunk: every
+    // valid child enters a table keyed by its hash, keeping the smallest
+    // attempt index; a child whose entry holds a smaller index with the same
+    // canonical series repeats it (a different series under the same hash,
+    // vanishingly rare, falls back to comparing every earlier child)
+    for (int i = tid; i < A; i += nt) {
+        if (!(B.cflag[i] & kValid)) continue;
+        const uint64_t h = B.chash[i];
+        uint32_t slot = (uint32_t)h & kMask;
+        for (;;) {
+            const unsigned long long prev = atomicCAS(
+                reinterpret_cast<unsigned long long *>(&s_th[slot]), 0ull, (unsigned long long)h);
+            if (prev == 0ull || prev == h) {
+                atomicMin(&s_ti[slot], (uint32_t)i);
                 break;
             }
+            slot = (slot + 1) & kMask;
         }
     }
     __syncthreads();
-    const int Nn0 = st->Nn, att0 = st->att;
+    auto same_series = [&](int i, int j) {
+        const int li = B.clen[i];
+        if (B.clen[j] != li) return false;
+        const bool ri = (B.cflag[i] & kRev) != 0, rj = (B.cflag[j] & kRev) != 0;
+        const uint16_t *ci = B.child + (size_t)i * kmax, *cj = B.child + (size_t)j * kmax;
+        int e = 0;
+        while (e < li && canon_at(ci, li, ri, e) == canon_at(cj, li, rj, e)) e++;
+        return e == li;
+    };
+    for (int i = tid; i < A; i += nt) {
+        const uint32_t f = B.cflag[i];
+        if (!(f & kValid)) continue;
+        const uint64_t h = B.chash[i];
+        uint32_t slot = (uint32_t)h & kMask;
+        while (s_th[slot] != h) slot = (slot + 1) & kMask;
+        const int m = (int)s_ti[slot];
+        if (m >= i) continue;
+        bool dup = same_series(i, m);
+        for (int j = 0; j < i && !dup; j++)
+            if (j != m && (B.cflag[j] & kValid) && B.chash[j] == h && same_series(i, j)) dup = true;
+        if (dup) B.cflag[i] = f | kDup;
+    }
+    __syncthreads();
+    const int Nn0 = st->Nn, att0 = st->att, tabu0 = st->tabu_n;
     const int64_t hits0 = st->hits;
+    // each thread takes a contiguous range of attempts, its flags in registers
+    constexpr int kPer = (kChunkMax + kBlock - 1) / kBlock;
     const int per = (A + nt - 1) / nt, lo = tid * per, hi = lo + per < A ? lo + per : A;
+    uint32_t fl[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; r++) fl[r] = lo + r < hi ? B.cflag[lo + r] : 0u;
     auto is_hit = [&](uint32_t f) { return (f & kValid) && (f & (kInSet | kDup)); };
     auto is_acc = [&](uint32_t f) { return (f & kValid) && !(f & (kInSet | kDup)); };
     int nacc = 0, nhit = 0, last = -1;
-    for (int i = lo; i < hi; i++) {
-        const uint32_t f = B.cflag[i];
-        nhit += is_hit(f);
-        if (is_acc(f)) {
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        nhit += is_hit(fl[r]);
+        if (is_acc(fl[r])) {
             nacc++;
-            last = i;
+            last = lo + r;
         }
     }
     int tot_acc = 0, tot_hit = 0;
@@ -980,21 +1167,21 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
     int event = 0x7fffffff;
     {
         int acc = e_acc, hit = e_hit, la = prev_last;
-        for (int i = lo; i < hi; i++) {
+        for (int r = 0; r < kPer && lo + r < hi; r++) {
+            const int i = lo + r;
             const int att_before = la < 0 ? att0 + i : i - la - 1;
             if (att_before >= q.max_att) {
                 event = i * 4;
                 break;
             }
-            const uint32_t f = B.cflag[i];
-            if (is_hit(f)) {
+            if (is_hit(fl[r])) {
                 hit++;
                 if (hits0 + hit >= q.max_hits) {
                     event = i * 4 + 1;
                     break;
                 }
             }
-            if (is_acc(f)) {
+            if (is_acc(fl[r])) {
                 acc++;
                 la = i;
                 if (Nn0 + acc == q.P) {
@@ -1007,27 +1194,21 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
     const int ev = block_min(event, s_tmp);
     const int kind = ev == 0x7fffffff ? -1 : ev & 3, iev = ev == 0x7fffffff ? A : ev >> 2;
     const int lim = kind < 0 ? A : (kind == 0 ? iev : iev + 1);  // attempts made
-    // accepted children of the attempts made go to their slots
+    // accepted children of the attempts made: their slots in the next
+    // population and their tabu arena entries (the insert kernel copies them)
+    int uacc = 0, uhit = 0, ulast = -1;
     {
         const int nxt = cur ^ 1;
         int acc = e_acc;
-        for (int i = lo; i < hi && i < lim; i++) {
-            const uint32_t f = B.cflag[i];
-            if (!is_acc(f)) continue;
-            const int slot = Nn0 + acc;
+        for (int r = 0; r < kPer && lo + r < hi && lo + r < lim; r++) {
+            const int i = lo + r;
+            uhit += is_hit(fl[r]);
+            if (!is_acc(fl[r])) continue;
+            B.cslot[i] = Nn0 + acc;
+            B.carena[i] = tabu0 + acc;
+            B.plen[nxt][Nn0 + acc] = B.clen[i];
+            B.cflag[i] = fl[r] | kAccept;
             acc++;
-            const int len = B.clen[i];
-            for (int e = 0; e < len; e++)
-                B.pop[nxt][(size_t)slot * kmax + e] = B.child[(size_t)i * kmax + e];
-            B.plen[nxt][slot] = len;
-            B.cflag[i] = f | kAccept;
-        }
-    }
-    int uacc = 0, uhit = 0, ulast = -1;
-    for (int i = lo; i < hi && i < lim; i++) {
-        const uint32_t f = B.cflag[i];
-        uhit += is_hit(f);
-        if (is_acc(f)) {
             uacc++;
             ulast = i;
         }
@@ -1052,60 +1233,106 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
             consumed = kind == 0 ? B.att_off[iev] : att_end[iev];
         }
         st->rng += (uint64_t)consumed * kGamma;
+        st->tabu_n = tabu0 + used_acc;
+        if (tabu0 + used_acc > q.tabu_cap) st->error = 1;
+        st->pending = 1;
+        if (st->stop) st->over = 1;
+        // the queued chunks are used up and the fill goes on: the host runs
+        // the rest of it
+        if (last_chunk && st->need_more && !st->stop) st->stalled = 1;
     }
 }
 
-// Inserts canonical series into the tabu set: the chunk's accepted children
-// (cols = children, flags with kAccept), or (flags NULL) the n series given,
-// already canonical. A thread each.
-__global__ void __launch_bounds__(256) dl_insert_kernel(DlParams q, DlBufs B, const uint16_t *cols,
-                                                        const int32_t *lens, const uint32_t *flags,
-                                                        const uint64_t *hashes, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// Inserts canonical series into the tabu set, a wave each: the chunk's
+// accepted children (cols = the children, flags with kAccept), each also
+// copied to its slot of the next population (buffer nxt); or (flags NULL)
+// the n series given, already canonical.
+constexpr int kInsertWaves = 4;
+
+__global__ void __launch_bounds__(kInsertWaves *kWave)
+    dl_insert_kernel(DlParams q, DlBufs B, const uint16_t *cols, const int32_t *lens,
+                     const uint32_t *flags, const uint64_t *hashes, int n, int nxt) {
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int i = blockIdx.x * kInsertWaves + wave;
     if (i >= n) return;
     const int kmax = q.kmax;
+    const int len = lens[i];
+    const uint16_t *s = cols + (size_t)i * kmax;
     bool rev = false;
     uint64_t h;
     if (flags) {
+        // the accepted children of a chunk whose acceptance ran
+        if (!B.st->pending) return;
         if (i >= B.st->chunk_n || !(flags[i] & kAccept)) return;
         rev = (flags[i] & kRev) != 0;
         h = hashes[i];
+        const int slot = B.cslot[i];
+        for (int j = lane; j < len; j += kWave) B.pop[nxt][(size_t)slot * kmax + j] = s[j];
     } else {
-        h = series_hash_seq(cols + (size_t)i * kmax, lens[i], false);
+        uint64_t hl = 0;
+        for (int j = lane; j < len; j += kWave) hl ^= col_hash(s[j], j, len);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) hl ^= __shfl_xor(hl, o, kWave);
+        h = (sm_mix((uint64_t)len + 0x632BE59BD9B4E019ULL) ^ hl) | 1;
     }
-    const int len = lens[i];
-    const int e = atomicAdd(&B.st->tabu_n, 1);
-    if (e >= q.tabu_cap) {
-        B.st->error = 1;
-        return;
+    // the arena entry: given by the acceptance (children), or the entry's
+    // own index (the first population's series)
+    const int e = flags ? B.carena[i] : i;
+    if (e >= q.tabu_cap) return;
+    for (int j = lane; j < len; j += kWave)
+        B.tarena[(size_t)e * kmax + j] = (uint16_t)canon_at(s, len, rev, j);
+    if (lane == 0) {
+        B.tlen[e] = len;
+        uint64_t slot = h & q.tabu_mask;
+        while (atomicCAS(reinterpret_cast<unsigned long long *>(&B.thash[slot]), 0ull,
+                         (unsigned long long)h) != 0ull)
+            slot = (slot + 1) & q.tabu_mask;
+        B.tref[slot] = e;
     }
-    const uint16_t *s = cols + (size_t)i * kmax;
-    for (int j = 0; j < len; j++) B.tarena[(size_t)e * kmax + j] = (uint16_t)canon_at(s, len, rev, j);
-    B.tlen[e] = len;
-    uint64_t slot = h & q.tabu_mask;
-    while (atomicCAS(reinterpret_cast<unsigned long long *>(&B.thash[slot]), 0ull,
-                     (unsigned long long)h) != 0ull)
-        slot = (slot + 1) & q.tabu_mask;
-    B.tref[slot] = e;
 }
 
-// The population in buffer `which` packed as CSR for the evaluator. One
-// workgroup.
-__global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, int which, int n) {
+// The evaluator's job table takes the list's size and length from the state
+// (the table was laid out for the largest list).
+__global__ void dl_patch_kernel(DlBufs B, int32_t *size_field, int32_t *len_field) {
+    if (threadIdx.x == 0) {
+        *size_field = B.st->nA;
+        *len_field = B.st->arch_len;
+    }
+}
+
+__global__ void dl_resume_kernel(DlBufs B) {
+    if (threadIdx.x == 0) B.st->stalled = 0;
+}
+
+// The population in buffer `which` packed as CSR for the evaluator (with
+// `check`, only while the run goes on). One workgroup.
+__global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, int which, int n,
+                                                         int check) {
     __shared__ int s_tmp[33];
-    const int tid = threadIdx.x, nt = blockDim.x, kmax = q.kmax;
+    if (check && (B.st->over || B.st->stalled)) return;
+    const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (n + nt - 1) / nt, lo = tid * per, hi = lo + per < n ? lo + per : n;
     int sum = 0;
     for (int i = lo; i < hi; i++) sum += B.plen[which][i];
     int total = 0;
     int at = block_excl_scan(sum, s_tmp, &total);
     for (int i = lo; i < hi; i++) {
-        const int k = B.plen[which][i];
         B.csr_off[i] = at;
-        for (int e = 0; e < k; e++) B.csr_cols[at + e] = B.pop[which][(size_t)i * kmax + e];
-        at += k;
+        at += B.plen[which][i];
     }
     if (tid == 0) B.csr_off[n] = total;
+}
+
+// The columns of the packed population, a wave per individual (after
+// dl_pack_kernel).
+__global__ void __launch_bounds__(256) dl_copy_kernel(DlParams q, DlBufs B, int which, int n,
+                                                      int check) {
+    if (check && (B.st->over || B.st->stalled)) return;
+    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
+    if (i >= n) return;
+    const int k = B.plen[which][i], o = B.csr_off[i];
+    const uint16_t *s = B.pop[which] + (size_t)i * q.kmax;
+    for (int e = lane; e < k; e += kWave) B.csr_cols[o + e] = s[e];
 }
 
 // ---- host driver ----
@@ -1190,7 +1417,8 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
                     bytes, (long long)cap);
     const ebic_allocator *al = job.al_;
     DeviceArray<uint16_t> pop0, pop1, csr_cols, aslot_cols, arch_cols, child, tarena;
-    DeviceArray<int32_t> plen0, plen1, csr_off, cnt, arch_off, att_off, att_end, clen, tref, tlen;
+    DeviceArray<int32_t> plen0, plen1, csr_off, cnt, arch_off, att_off, att_end, clen, tref, tlen,
+        cslot, carena, use0, use1;
     DeviceArray<double> fit, keys, trace;
     DeviceArray<uint64_t> sup, aslot_sup, arch_sup, chash, thash;
     DeviceArray<uint8_t> span;
@@ -1216,6 +1444,12 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     DL_HIP(att_end.alloc(kChunkMax, al, stream));
     DL_HIP(child.alloc((size_t)kChunkMax * kmax, al, stream));
     DL_HIP(clen.alloc(kChunkMax, al, stream));
+    DL_HIP(cslot.alloc(kChunkMax, al, stream));
+    DL_HIP(carena.alloc(kChunkMax, al, stream));
+    DL_HIP(use0.alloc(C, al, stream));
+    DL_HIP(use1.alloc(C, al, stream));
+    DL_HIP(hipMemsetAsync(use0.p, 0, sizeof(int32_t) * C, stream));
+    DL_HIP(hipMemsetAsync(use1.p, 0, sizeof(int32_t) * C, stream));
     DL_HIP(cflag.alloc(kChunkMax, al, stream));
     DL_HIP(chash.alloc(kChunkMax, al, stream));
     DL_HIP(thash.alloc(slots, al, stream));
@@ -1237,6 +1471,8 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     B.cnt = cnt.p;
     B.sup = sup.p;
     B.keys = keys.p;
+    B.use[0] = use0.p;
+    B.use[1] = use1.p;
     B.aslot_cols = aslot_cols.p;
     B.aslot_sup = aslot_sup.p;
     B.arch_off = arch_off.p;
@@ -1248,6 +1484,8 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     B.clen = clen.p;
     B.cflag = cflag.p;
     B.chash = chash.p;
+    B.cslot = cslot.p;
+    B.carena = carena.p;
     B.thash = thash.p;
     B.tref = tref.p;
     B.tarena = tarena.p;
@@ -1284,6 +1522,13 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             tl.push_back((int32_t)k);
         });
         const int nt = (int)tl.size();
+        {
+            // the first population's series take arena entries 0 .. nt - 1
+            const int32_t ntv = nt;
+            DL_HIP(hipMemcpyAsync(&st.p->tabu_n, &ntv, sizeof(int32_t), hipMemcpyHostToDevice,
+                                  stream));
+            DL_HIP(hipStreamSynchronize(stream));
+        }
         if (nt > 0) {
             DeviceArray<uint16_t> dtc;
             DeviceArray<int32_t> dtl;
@@ -1293,89 +1538,128 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
                                   hipMemcpyHostToDevice, stream));
             DL_HIP(hipMemcpyAsync(dtl.p, tl.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice,
                                   stream));
-            hipLaunchKernelGGL(dl_insert_kernel, dim3((nt + 255) / 256), dim3(256), 0, stream, q, B,
-                               dtc.p, dtl.p, nullptr, nullptr, nt);
+            hipLaunchKernelGGL(dl_insert_kernel, dim3((nt + kInsertWaves - 1) / kInsertWaves),
+                               dim3(kInsertWaves * kWave), 0, stream, q, B, dtc.p, dtl.p, nullptr,
+                               nullptr, nt, 0);
             DL_HIP(hipGetLastError());
             DL_HIP(hipStreamSynchronize(stream));  // before the host copies go out of scope
         }
         if (Pn0 > 0) {
-            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, 0, Pn0);
+            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, 0, Pn0, 0);
+            hipLaunchKernelGGL(dl_copy_kernel, dim3((Pn0 + 3) / 4), dim3(256), 0, stream, q, B, 0,
+                               Pn0, 0);
             DL_HIP(hipGetLastError());
         }
         DL_HIP(hipStreamSynchronize(stream));
     }
 
     const int Ppad = (int)pow2_at_least((size_t)std::max(P, 2));
-    const size_t lds_list = (size_t)Ppad * 16 + (size_t)((C + 31) / 32) * 4;
-    const size_t lds_keys = (size_t)C * 4;
+    const size_t lds_list = list_lds_bytes(Ppad, C);
     DL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(dl_list_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_list));
-    DL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(dl_keys_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_keys));
     DL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(dl_chain_kernel),
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)chain_lds(kSpanMax, q.span_e)));
     DL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(dl_accept_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kChunkMax * 16));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kDedupSlots * 12));
     auto read_state = [&]() -> int {
         DL_HIP(hipMemcpyAsync(hs.p, st.p, sizeof(DlState), hipMemcpyDeviceToHost, stream));
         DL_HIP(hipStreamSynchronize(stream));
         return EBIC_OK;
     };
 
-    int cur = 0, Pn = Pn0, nA = 0, arch_len = 0;
-    for (;;) {
-        // steps 2 / 7: score the population against the list
+    // The evaluator's batch, laid out once for the largest list; before each
+    // evaluation a kernel copies the list's size and length into its table.
+    {
         ebic_job v{};
         v.matrix = job.m_;
-        v.population = ebic_population{Pn, Pn * kmax, csr_off.p, csr_cols.p, nullptr};
-        v.archive = ebic_archive{nA, arch_len, arch_sup.p, arch_off.p, arch_cols.p};
+        v.population = ebic_population{Pn0, Pn0 * kmax, csr_off.p, csr_cols.p, nullptr};
+        v.archive = ebic_archive{K, K * kmax, arch_sup.p, arch_off.p, arch_cols.p};
         v.params = p;
         v.out = ebic_eval_out{fit.p, cnt.p, sup.p, nullptr};
         rc = batch_set(batch, &v, 1, stream, al);
-        if (rc == EBIC_OK && Pn > 0) rc = batch_run(*batch, stream);
         if (rc) return rc;
+    }
+    int32_t *f_size = nullptr, *f_len = nullptr;
+    rc = batch_archive_fields(*batch, 0, &f_size, &f_len);
+    if (rc) return rc;
+    auto chunk = [&](int cur, int Pn, int R, int last) -> int {
+        const int A_target = std::min(kChunkMax, R + R / 2 + 64);
+        const int S = std::min(kSpanMax, A_target * (2 * q.T + 3));
+        hipLaunchKernelGGL(dl_span_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, q, B, cur,
+                           Pn, S);
+        hipLaunchKernelGGL(dl_chain_kernel, dim3(1), dim3(kBlock), chain_lds(S, q.span_e), stream,
+                           q, B, att_end.p, cur, Pn, S, A_target);
+        hipLaunchKernelGGL(dl_child_kernel, dim3((A_target + kChildWaves - 1) / kChildWaves),
+                           dim3(kChildWaves * kWave), 0, stream, q, B, cur, Pn);
+        hipLaunchKernelGGL(dl_accept_kernel, dim3(1), dim3(kBlock), (size_t)kDedupSlots * 12,
+                           stream, q, B, (const int32_t *)att_end.p, cur, last);
+        hipLaunchKernelGGL(dl_insert_kernel, dim3((A_target + kInsertWaves - 1) / kInsertWaves),
+                           dim3(kInsertWaves * kWave), 0, stream, q, B, (const uint16_t *)child.p,
+                           (const int32_t *)clen.p, (const uint32_t *)cflag.p,
+                           (const uint64_t *)chash.p, A_target, cur ^ 1);
+        DL_HIP(hipGetLastError());
+        return EBIC_OK;
+    };
+    // One generation queued: score population gi (buffer gi % 2), update the
+    // list, keys, the fill's first chunks, pack the next population. Every
+    // kernel does nothing once the run is over or a fill has stalled.
+    constexpr int kChunksQueued = 2;
+    auto queue_generation = [&](int gi) -> int {
+        const int cur = gi & 1, Pn = gi == 0 ? Pn0 : P;
+        hipLaunchKernelGGL(dl_patch_kernel, dim3(1), dim3(64), 0, stream, B, f_size, f_len);
+        DL_HIP(hipGetLastError());
+        if (Pn > 0) {
+            int r = batch_run(*batch, stream);
+            if (r) return r;
+        }
         hipLaunchKernelGGL(dl_list_kernel, dim3(1), dim3(kBlock), lds_list, stream, q, B, cur, Pn,
                            Ppad);
+        hipLaunchKernelGGL(dl_use_kernel, dim3((Pn + 3) / 4), dim3(256), 0, stream, q, B, cur, Pn);
+        hipLaunchKernelGGL(dl_keys_kernel, dim3((std::max(Pn, C / 64 + 1) + 3) / 4), dim3(256), 0,
+                           stream, q, B, cur, Pn);
         DL_HIP(hipGetLastError());
-        if ((rc = read_state())) return rc;
-        nA = hs.p->nA;
-        arch_len = hs.p->arch_len;
-        if (hs.p->stop) break;
-        hipLaunchKernelGGL(dl_keys_kernel, dim3(1), dim3(kBlock), lds_keys, stream, q, B, cur, Pn);
-        DL_HIP(hipGetLastError());
-        // steps 5-6, in chunks of attempts
-        for (;;) {
-            const int R = P - hs.p->Nn;
-            const int A_target = std::min(kChunkMax, R + R / 2 + 64);
-            const int S = std::min(kSpanMax, A_target * (2 * q.T + 3));
-            hipLaunchKernelGGL(dl_span_kernel, dim3((S + 255) / 256), dim3(256), 0, stream, q, B,
-                               cur, Pn, S);
-            DL_HIP(hipGetLastError());
-            hipLaunchKernelGGL(dl_chain_kernel, dim3(1), dim3(kBlock), chain_lds(S, q.span_e),
-                               stream, q, B, att_end.p, cur, Pn, S, A_target);
-            DL_HIP(hipGetLastError());
-            hipLaunchKernelGGL(dl_child_kernel, dim3((A_target + kChildWaves - 1) / kChildWaves),
-                               dim3(kChildWaves * kWave), 0, stream, q, B, cur, Pn);
-            DL_HIP(hipGetLastError());
-            const int Apad = (int)pow2_at_least((size_t)std::max(A_target, 2));
-            hipLaunchKernelGGL(dl_accept_kernel, dim3(1), dim3(kBlock), (size_t)Apad * 16, stream,
-                               q, B, (const int32_t *)att_end.p, cur, Apad);
-            DL_HIP(hipGetLastError());
-            hipLaunchKernelGGL(dl_insert_kernel, dim3((A_target + 255) / 256), dim3(256), 0,
-                               stream, q, B, (const uint16_t *)child.p, (const int32_t *)clen.p,
-                               (const uint32_t *)cflag.p, (const uint64_t *)chash.p, A_target);
-            DL_HIP(hipGetLastError());
-            if ((rc = read_state())) return rc;
-            if (hs.p->error)
-                return fail(EBIC_ERR_CAPACITY, "device loop: the tabu set is full");
-            if (!hs.p->need_more || hs.p->stop) break;
+        for (int c = 0; c < kChunksQueued; c++) {
+            int r = chunk(cur, Pn, P, c == kChunksQueued - 1);
+            if (r) return r;
         }
-        if (hs.p->stop) break;
-        cur ^= 1;
-        Pn = P;
-        hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur, Pn);
+        hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P, 1);
+        hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B, cur ^ 1, P,
+                           1);
         DL_HIP(hipGetLastError());
+        return EBIC_OK;
+    };
+    // generations are queued a few at a time; the host reads the state
+    // between groups
+    constexpr int kAhead = 8;
+    int gi = 0;
+    for (;;) {
+        const int upto = std::min(q.G, gi + kAhead);
+        for (int x = gi; x < upto; x++)
+            if ((rc = queue_generation(x))) return rc;
+        if ((rc = read_state())) return rc;
+        if (hs.p->error) return fail(EBIC_ERR_CAPACITY, "device loop: the tabu set is full");
+        if (hs.p->over) break;
+        if (hs.p->stalled) {
+            // finish the stalled fill chunk by chunk, then go on
+            const int cur = (hs.p->g - 1) & 1;
+            dl_resume_kernel<<<1, 64, 0, stream>>>(B);
+            for (;;) {
+                if ((rc = chunk(cur, P, P - hs.p->Nn, 0))) return rc;
+                if ((rc = read_state())) return rc;
+                if (hs.p->error) return fail(EBIC_ERR_CAPACITY, "device loop: the tabu set is full");
+                if (!hs.p->need_more || hs.p->stop) break;
+            }
+            if (hs.p->over) break;
+            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P,
+                               1);
+            hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B,
+                               cur ^ 1, P, 1);
+            DL_HIP(hipGetLastError());
+        }
+        if (hs.p->g >= q.G) return fail(EBIC_ERR_DEVICE, "device loop: no stop after %d generations",
+                                         hs.p->g);
+        gi = hs.p->g;
     }
 
     // the run's state back into the job, which then takes the final step

@@ -123,6 +123,11 @@ void *device_alloc(const ebic_allocator *al, size_t bytes, hipStream_t stream);
 void device_release(const ebic_allocator *al, void *p, hipStream_t stream);
 int batch_tuning(Batch *b, int32_t *cpi, int32_t *kb, int32_t *wpl);
 int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb, int32_t wpl);
+// Device addresses of job `job`'s archive size and column count in the
+// batch's job table, for code that changes the archive on the device
+// between runs (the table must have room: its LDS sizing used the lengths
+// given to batch_set).
+int batch_archive_fields(Batch *b, int32_t job, int32_t **size, int32_t **len);
 int batch_destroy(Batch *b);
 int batch_profile(Batch *b, int32_t n);
 int batch_timings(Batch *b, float *ms, int32_t *n);
