@@ -1583,6 +1583,18 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     int32_t *f_size = nullptr, *f_len = nullptr;
     rc = batch_archive_fields(*batch, 0, &f_size, &f_len);
     if (rc) return rc;
+    // The generations run on a stream of their own when the caller's is the
+    // null stream (which cannot be captured into a graph); everything before
+    // is finished first, and the loop ends with its stream synchronized.
+    struct OwnStream {
+        hipStream_t s = nullptr;
+        ~OwnStream() {
+            if (s) (void)hipStreamDestroy(s);
+        }
+    } own;
+    DL_HIP(hipStreamSynchronize(stream));
+    if (!stream && hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking) == hipSuccess)
+        stream = own.s;
     auto chunk = [&](int cur, int Pn, int R, int last) -> int {
         const int A_target = std::min(kChunkMax, R + R / 2 + 64);
         const int S = std::min(kSpanMax, A_target * (2 * q.T + 3));
@@ -1604,7 +1616,9 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     // One generation queued: score population gi (buffer gi % 2), update the
     // list, keys, the fill's first chunks, pack the next population. Every
     // kernel does nothing once the run is over or a fill has stalled.
-    constexpr int kChunksQueued = 2;
+    // chunks queued per generation: enough for half as many attempts again
+    // as the population (tabu hits and children of the wrong length)
+    const int kChunksQueued = std::max(1, (P + P / 2 + 64 + kChunkMax - 1) / kChunkMax);
     auto queue_generation = [&](int gi) -> int {
         const int cur = gi & 1, Pn = gi == 0 ? Pn0 : P;
         hipLaunchKernelGGL(dl_patch_kernel, dim3(1), dim3(64), 0, stream, B, f_size, f_len);
@@ -1629,6 +1643,42 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         DL_HIP(hipGetLastError());
         return EBIC_OK;
     };
+    // Generations after the first replay one of two captured graphs (by the
+    // population's parity: every kernel argument is the same otherwise),
+    // which saves the launch cost of a generation's kernels; without them
+    // (capture unavailable) the kernels are launched one by one.
+    struct Graphs {
+        hipGraph_t g[2] = {nullptr, nullptr};
+        hipGraphExec_t x[2] = {nullptr, nullptr};
+        ~Graphs() {
+            for (int i = 0; i < 2; i++) {
+                if (x[i]) (void)hipGraphExecDestroy(x[i]);
+                if (g[i]) (void)hipGraphDestroy(g[i]);
+            }
+        }
+    } graphs;
+    bool use_graphs = Pn0 == P && stream != nullptr && q.G > 2;
+    for (int par = 0; par < 2 && use_graphs; par++) {
+        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            use_graphs = false;
+            break;
+        }
+        const int r = queue_generation(2 + par);  // any generation after the first of this parity
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(stream, &gr);
+        graphs.g[par] = gr;
+        if (r || e != hipSuccess || !gr ||
+            hipGraphInstantiate(&graphs.x[par], gr, nullptr, nullptr, 0) != hipSuccess)
+            use_graphs = false;
+    }
+    (void)hipGetLastError();  // a refused capture leaves nothing for later calls
+    auto queue = [&](int gi) -> int {
+        if (gi > 0 && use_graphs) {
+            DL_HIP(hipGraphLaunch(graphs.x[gi & 1], stream));
+            return EBIC_OK;
+        }
+        return queue_generation(gi);
+    };
     // generations are queued a few at a time; the host reads the state
     // between groups
     constexpr int kAhead = 8;
@@ -1636,7 +1686,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     for (;;) {
         const int upto = std::min(q.G, gi + kAhead);
         for (int x = gi; x < upto; x++)
-            if ((rc = queue_generation(x))) return rc;
+            if ((rc = queue(x))) return rc;
         if ((rc = read_state())) return rc;
         if (hs.p->error) return fail(EBIC_ERR_CAPACITY, "device loop: the tabu set is full");
         if (hs.p->over) break;
