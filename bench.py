@@ -51,6 +51,12 @@ def parse():
                     help="instead of the evaluation step, run the whole method on a planted "
                          "workload (0, 1 or 2) with its parameters and print the clustering "
                          "error of the biclusters found against the planted ones")
+    ap.add_argument("--loop", type=int, default=None, metavar="WORKLOAD",
+                    help="instead of the evaluation step, run the whole method on a workload "
+                         "(1, 2 or 3) with the loop on the host (ebic_run) and on the device "
+                         "(ebic_run_device), and print the time per generation of each")
+    ap.add_argument("--loop-only", choices=["host", "device"], default=None,
+                    help="with --loop: run only that loop (for profiling)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (calibrates the HBM "
                          "byte counters of rocprofv3) and exit")
@@ -115,6 +121,9 @@ def main():
         return
     if args.gpus == 1 and args.recovery is not None:
         recovery(args)
+        return
+    if args.gpus == 1 and args.loop is not None:
+        loop_times(args)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the evaluation path "
@@ -368,6 +377,52 @@ def recovery(args):
                    "negative_trends": w.negative_trends},
         "wall_s": wall, "evaluations": res.evaluations,
         "evaluations_per_s": res.evaluations / wall}), flush=True)
+
+
+def loop_times(args):
+    """ebic_run and ebic_run_device on one workload with its loop settings
+    (the batched and large workloads with 100 and 20 generations): wall time
+    per generation, median of three runs after a warm-up run, and whether the
+    two loops gave the same run."""
+    sys.path.insert(0, ROOT)
+    import synth
+    from paper_2105_01196_amd import ebic as E
+    wi = args.loop
+    w = synth.workload(wi)
+    case = synth.workload_matrix(wi)
+    gens = {1: w.generations, 2: 100, 3: 20}.get(wi, w.generations)
+    p = E.make_params(approx_permille=850, negative_trends=1, overlap_permille=750, min_rows=5,
+                      k_min=w.k_min, k_max=w.k_max, archive_size=20, n_out=w.n_out,
+                      population=w.population, generations=gens, max_tabu_hits=100000,
+                      tournament=4, max_attempts=1000)
+    seed = synth.GA_SEED + wi
+    out = {"metric": "wall time per generation of the method's loop",
+           "unit": "us per generation", "higher_is_better": False, "n_gpus": 1,
+           "data": "synthetic",
+           "config": {"workload": w.name, "population": w.population, "generations": gens,
+                      "archive": 20, "negative_trends": 1}}
+    results = {}
+    for name, fn in (("host", E.ebic_run), ("device", E.ebic_run_device)):
+        if args.loop_only and name != args.loop_only:
+            continue
+        fn(case.X, p, seed)  # warm-up
+        ts = []
+        for _ in range(3):
+            t = time.perf_counter()
+            r = fn(case.X, p, seed)
+            ts.append(time.perf_counter() - t)
+        results[name] = r
+        out[f"{name}_us_per_generation"] = sorted(ts)[1] / r.generations * 1e6
+    if len(results) == 2:
+        a, b = results["host"], results["device"]
+        out["same_run"] = bool(
+            (a.generations, a.evaluations, a.tabu_hits, a.stop_reason) ==
+            (b.generations, b.evaluations, b.tabu_hits, b.stop_reason)
+            and np.array_equal(a.trace, b.trace)
+            and all(np.array_equal(x.rows, y.rows) and np.array_equal(x.cols, y.cols)
+                    for x, y in zip(a.biclusters, b.biclusters)))
+        out["device_vs_host"] = out["host_us_per_generation"] / out["device_us_per_generation"]
+    print(json.dumps(out), flush=True)
 
 
 def cpu_threads():
