@@ -254,8 +254,9 @@ int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_b
 /* Item shape of the kernel: a wave takes one item of its individual's rows,
  * i.e. chunks_per_item groups (1, 2 or 4) of words_per_lane (1 or 2) chunks
  * of 4,096 rows, walking a group's chunks together (each lane holds one
- * 64-row word of each), with loads_in_flight (2 or 4) pair-bitmap loads
- * issued per group of steps (an individual with more than 16 items gets
+ * 64-row word of each), with loads_in_flight (2 or 4, or 8 with one word
+ * per lane) pair-bitmap loads issued per group of steps (an individual with
+ * more than 16 items gets
  * proportionally larger ones). With EBIC_BATCH_TUNE the first run times every candidate
  * shape on the batch's own inputs, waits for the timings (that run is
  * synchronous), keeps the fastest, and caches the choice per batch shape in

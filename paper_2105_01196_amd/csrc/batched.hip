@@ -301,23 +301,32 @@ struct StepSum {
 // The column-index tie rule (one table; every step is either up or down in
 // a row): the same counters as pairs_count_two, on 32-bit halves with
 // three-input logic, groups of KB steps loaded together through buffer
-// loads whose row base is computed in scalar registers.
-template <int P, bool NEG, int KB, int WPL>
+// loads with a scalar row offset. FLAT (a table below 4 GB): the step
+// descriptors hold each pair row's byte offset (bit 0: the step runs from
+// the higher column to the lower one) and every load goes through one
+// resource for the whole table; else they hold the pair index (sign bit:
+// direction) and each step builds its row's resource. The next group's
+// descriptors are read from LDS while this group's loads are in flight.
+// KB = 8 loads eight steps at once and counts them as two groups of four.
+template <int P, bool NEG, int KB, int WPL, bool FLAT>
 __device__ __forceinline__ void pairs_count_one(const uint64_t *__restrict__ pairs,
-                                                int64_t pstride, int wlim, const int32_t *s_pd,
-                                                int k, int t, int w, uint64_t *fit) {
+                                                int64_t pstride, uint32_t table_bytes, int wlim,
+                                                const int32_t *s_pd, int k, int t, int w,
+                                                uint64_t *fit) {
     constexpr int NP = P > 0 ? P : 1;
     uint32_t start = __builtin_amdgcn_readfirstlane((1u << P) - (uint32_t)(t + 1));
     asm volatile("" : "+s"(start));
     const uint32_t row_bytes = (uint32_t)(pstride * 8);
+    const __amdgpu_buffer_rsrc_t trs = make_rsrc(pairs, FLAT ? table_bytes : row_bytes);
     bool active[WPL];
     int voff[WPL];
     uint32_t D[WPL][2][NP], U[WPL][2][NP], dov[WPL][2], uov[WPL][2];
 #pragma unroll
     for (int v = 0; v < WPL; v++) {
         active[v] = w + kWave * v < wlim;
-        // an inactive lane reads past the row's end: the buffer returns 0
-        voff[v] = active[v] ? (w + kWave * v) * 8 : (int)row_bytes;
+        // an inactive lane reads the row's first word (FLAT) or past the
+        // row's end (the buffer returns 0); its result is never used
+        voff[v] = active[v] ? (w + kWave * v) * 8 : (FLAT ? 0 : (int)row_bytes);
 #pragma unroll
         for (int h = 0; h < 2; h++) {
 #pragma unroll
@@ -325,18 +334,34 @@ __device__ __forceinline__ void pairs_count_one(const uint64_t *__restrict__ pai
             dov[v][h] = uov[v][h] = 0;
         }
     }
-    // loads and flips of up to KB steps from step j on
-    auto load = [&](int j, int n, uint32_t (*b)[WPL][2], uint32_t *m) {
+    // descriptors of KB steps from step j on (indexes past the series read
+    // unused LDS words inside the array)
+    auto descr = [&](int j, int32_t *pd) {
+#pragma unroll
+        for (int q = 0; q < KB; q++) {
+            const int i = j + q < EBIC_MAX_K ? j + q : EBIC_MAX_K - 1;
+            pd[q] = s_pd[i];
+        }
+    };
+    // loads and flips of the first n of those steps
+    auto load = [&](const int32_t *pdv, int n, uint32_t (*b)[WPL][2], uint32_t *m) {
 #pragma unroll
         for (int q = 0; q < KB; q++) {
             if (q < n) {
-                const int pd = __builtin_amdgcn_readfirstlane(s_pd[j + q]);
-                const uint64_t *row = pairs + (int64_t)(pd & 0x7fffffff) * pstride;
-                const __amdgpu_buffer_rsrc_t rs = make_rsrc(row, row_bytes);
-                m[q] = pd < 0 ? ~0u : 0u;
+                const int pd = __builtin_amdgcn_readfirstlane(pdv[q]);
+                __amdgpu_buffer_rsrc_t rs = trs;
+                uint32_t soff = 0;
+                if constexpr (FLAT) {
+                    m[q] = (pd & 1) ? ~0u : 0u;
+                    soff = (uint32_t)pd & ~1u;
+                } else {
+                    const uint64_t *row = pairs + (int64_t)(pd & 0x7fffffff) * pstride;
+                    rs = make_rsrc(row, row_bytes);
+                    m[q] = pd < 0 ? ~0u : 0u;
+                }
 #pragma unroll
                 for (int v = 0; v < WPL; v++) {
-                    const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, voff[v], 0, 0);
+                    const auto x = __builtin_amdgcn_raw_buffer_load_b64(rs, voff[v], soff, 0);
                     b[q][v][0] = x[0];
                     b[q][v][1] = x[1];
                 }
@@ -359,11 +384,27 @@ __device__ __forceinline__ void pairs_count_one(const uint64_t *__restrict__ pai
             }
         }
     };
+    // n in 0 .. 3 steps
+    auto count_few = [&](int n, uint32_t (*b)[WPL][2], const uint32_t *m) {
+        if (n == 1) count(std::integral_constant<int, 1>{}, b, m);
+        if constexpr (KB > 2) {
+            if (n == 2) count(std::integral_constant<int, 2>{}, b, m);
+            if (n == 3) count(std::integral_constant<int, 3>{}, b, m);
+        }
+    };
+    int32_t pn[KB];
+    descr(1, pn);
     int j = 1;
     for (; j + KB <= k; j += KB) {
         uint32_t b[KB][WPL][2], m[KB];
-        load(j, KB, b, m);
-        count(std::integral_constant<int, KB>{}, b, m);
+        load(pn, KB, b, m);
+        descr(j + KB, pn);
+        if constexpr (KB == 8) {
+            count(std::integral_constant<int, 4>{}, b, m);
+            count(std::integral_constant<int, 4>{}, b + 4, m + 4);
+        } else {
+            count(std::integral_constant<int, KB>{}, b, m);
+        }
         bool live = false;
 #pragma unroll
         for (int v = 0; v < WPL; v++) {
@@ -379,11 +420,16 @@ __device__ __forceinline__ void pairs_count_one(const uint64_t *__restrict__ pai
     const int rest = k - j;  // 0 .. KB - 1 steps left (negative after an early exit)
     if (rest > 0) {
         uint32_t b[KB][WPL][2], m[KB];
-        load(j, rest, b, m);
-        if (rest == 1) count(std::integral_constant<int, 1>{}, b, m);
-        if constexpr (KB > 2) {
-            if (rest == 2) count(std::integral_constant<int, 2>{}, b, m);
-            if (rest == 3) count(std::integral_constant<int, 3>{}, b, m);
+        load(pn, rest, b, m);
+        if constexpr (KB == 8) {
+            if (rest >= 4) {
+                count(std::integral_constant<int, 4>{}, b, m);
+                count_few(rest - 4, b + 4, m + 4);
+            } else {
+                count_few(rest, b, m);
+            }
+        } else {
+            count_few(rest, b, m);
         }
     }
 #pragma unroll
@@ -394,42 +440,52 @@ __device__ __forceinline__ void pairs_count_one(const uint64_t *__restrict__ pai
     }
 }
 
+// flat: the one-table descriptors hold byte offsets (a table below 4 GB of
+// table_bytes); the two-table path always takes pair indexes, at most four
+// loads in flight.
 template <int P, bool NEG, int KB, int WPL, bool TWO>
 __device__ __forceinline__ void pairs_count(const uint64_t *__restrict__ pairs,
                                             const uint64_t *__restrict__ strict, bool loose,
-                                            int64_t pstride, int wlim, const int32_t *s_pd, int k,
-                                            int t, int w, uint64_t *fit) {
+                                            int64_t pstride, bool flat, uint32_t table_bytes,
+                                            int wlim, const int32_t *s_pd, int k, int t, int w,
+                                            uint64_t *fit) {
     if constexpr (TWO)
-        pairs_count_two<P, NEG, KB, WPL, true>(pairs, strict, loose, pstride, wlim, s_pd, k, t, w,
+        pairs_count_two<P, NEG, (KB > 4 ? 4 : KB), WPL, true>(pairs, strict, loose, pstride, wlim,
+                                                              s_pd, k, t, w, fit);
+    else if (flat)
+        pairs_count_one<P, NEG, KB, WPL, true>(pairs, pstride, table_bytes, wlim, s_pd, k, t, w,
                                                fit);
     else
-        pairs_count_one<P, NEG, KB, WPL>(pairs, pstride, wlim, s_pd, k, t, w, fit);
+        pairs_count_one<P, NEG, KB, WPL, false>(pairs, pstride, table_bytes, wlim, s_pd, k, t, w,
+                                                fit);
 }
 
 // Widest counter the pair path instantiates for KB steps per group and WPL
-// words per lane: with one word per lane, what keeps the kernel within 64
-// VGPRs (8 waves per SIMD); with two, the widths past which registers climb
-// steeply. Items with a larger tolerance (t >= 2^P) take the gather form.
+// words per lane: with one word per lane and two or four loads in flight,
+// what keeps the kernel within 64 VGPRs (8 waves per SIMD); eight loads in
+// flight hold 72 (7 waves) from P = 4 on; with two words, the widths past
+// which registers climb steeply. Items with a larger tolerance (t >= 2^P)
+// take the gather form.
 template <int KB, int WPL>
 struct PairLimit {
-    static constexpr int P = WPL == 1 ? (KB == 4 ? 6 : 8) : (KB == 4 ? 3 : 4);
+    static constexpr int P = WPL == 1 ? (KB == 8 ? 4 : KB == 4 ? 5 : 8) : (KB == 4 ? 3 : 4);
     static constexpr int T = (1 << P) - 1;
 };
 
 template <int PP, int MAXP, bool NEG, int KB, int WPL, bool TWO>
 __device__ __forceinline__ void pairs_width(int P, const uint64_t *pairs, const uint64_t *strict,
-                                            bool loose, int64_t pstride, int wlim,
-                                            const int32_t *s_pd, int k, int t, int w,
-                                            uint64_t *fit) {
+                                            bool loose, int64_t pstride, bool flat,
+                                            uint32_t table_bytes, int wlim, const int32_t *s_pd,
+                                            int k, int t, int w, uint64_t *fit) {
     if constexpr (PP == MAXP) {
-        pairs_count<PP, NEG, KB, WPL, TWO>(pairs, strict, loose, pstride, wlim, s_pd, k, t, w,
-                                           fit);
+        pairs_count<PP, NEG, KB, WPL, TWO>(pairs, strict, loose, pstride, flat, table_bytes, wlim,
+                                           s_pd, k, t, w, fit);
     } else {
         if (P == PP)
-            return pairs_count<PP, NEG, KB, WPL, TWO>(pairs, strict, loose, pstride, wlim, s_pd,
-                                                      k, t, w, fit);
-        pairs_width<PP + 1, MAXP, NEG, KB, WPL, TWO>(P, pairs, strict, loose, pstride, wlim, s_pd,
-                                                     k, t, w, fit);
+            return pairs_count<PP, NEG, KB, WPL, TWO>(pairs, strict, loose, pstride, flat,
+                                                      table_bytes, wlim, s_pd, k, t, w, fit);
+        pairs_width<PP + 1, MAXP, NEG, KB, WPL, TWO>(P, pairs, strict, loose, pstride, flat,
+                                                     table_bytes, wlim, s_pd, k, t, w, fit);
     }
 }
 
@@ -438,12 +494,14 @@ __device__ __forceinline__ void pairs_width(int P, const uint64_t *pairs, const 
 // TWO: both tables (the strict and loose tie rules; loose selects which).
 template <bool NEG, int KB, int WPL, bool TWO>
 __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, const uint64_t *strict,
-                                               bool loose, int64_t pstride, int wlim,
+                                               bool loose, int64_t pstride, bool flat,
+                                               uint32_t table_bytes, int wlim,
                                                const int32_t *s_pd, int k, int t, int w,
                                                uint64_t *fit) {
     const int P = t == 0 ? 0 : 32 - __builtin_clz((unsigned)t);
-    pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL, TWO>(P, pairs, strict, loose, pstride, wlim,
-                                                             s_pd, k, t, w, fit);
+    pairs_width<0, PairLimit<KB, WPL>::P, NEG, KB, WPL, TWO>(P, pairs, strict, loose, pstride,
+                                                             flat, table_bytes, wlim, s_pd, k, t,
+                                                             w, fit);
 }
 
 // One workgroup per individual, one wave per item (a few 4096-row chunks of
@@ -529,6 +587,9 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     const bool two = TWO && J.tie_rule != EBIC_TIE_INDEX;  // both tables
     const bool use_pairs = J.mode == 1 && t <= PairLimit<KB, WPL>::T &&
                            (J.tie_rule == EBIC_TIE_INDEX || (TWO && J.pairs_strict));
+    // one table below 4 GB: descriptors hold byte offsets into it
+    const int64_t tbytes = (int64_t)J.cols * (J.cols - 1) / 2 * J.pstride * 8;
+    const bool flat = use_pairs && !two && tbytes <= (int64_t)0xFFFFFFFF;
 
     // 1. stage and validate the series
     if (threadIdx.x == 0) {
@@ -564,9 +625,11 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                 if (j > 0) {
                     const int a = gmem(J.pop_cols)[beg + j - 1];
                     const int lo = a < c ? a : c, hi = a < c ? c : a;
-                    if (hi < J.cols)
-                        s_pd[j] = (int32_t)pair_index(lo, hi, J.cols) |
-                                  (a > c ? (int32_t)0x80000000 : 0);
+                    if (hi < J.cols) {
+                        const int64_t pi = pair_index(lo, hi, J.cols);
+                        s_pd[j] = flat ? (int32_t)((uint32_t)(pi * J.pstride * 8) | (a > c ? 1u : 0u))
+                                       : (int32_t)pi | (a > c ? (int32_t)0x80000000 : 0);
+                    }
                 }
             } else {
                 s_pd[j] = (int32_t)((uint32_t)c * (uint32_t)J.rows_pad * 2u);
@@ -594,19 +657,22 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
                     const int wlim = J.w64 < ch1 * 64 ? J.w64 : ch1 * 64;
                     uint64_t fit[WPL];
                     const bool loose = J.tie_rule == EBIC_TIE_LOOSE;
+                    const uint32_t tb = (uint32_t)(flat ? tbytes : 0);
                     if (two) {
                         if (neg)
                             pairs_dispatch<true, KB, WPL, TWO>(J.pairs, J.pairs_strict, loose,
-                                                               J.pstride, wlim, s_pd, k, t, w, fit);
+                                                               J.pstride, false, 0, wlim, s_pd, k,
+                                                               t, w, fit);
                         else
                             pairs_dispatch<false, KB, WPL, TWO>(J.pairs, J.pairs_strict, loose,
-                                                                J.pstride, wlim, s_pd, k, t, w, fit);
+                                                                J.pstride, false, 0, wlim, s_pd, k,
+                                                                t, w, fit);
                     } else if (neg) {
                         pairs_dispatch<true, KB, WPL, false>(J.pairs, nullptr, false, J.pstride,
-                                                             wlim, s_pd, k, t, w, fit);
+                                                             flat, tb, wlim, s_pd, k, t, w, fit);
                     } else {
                         pairs_dispatch<false, KB, WPL, false>(J.pairs, nullptr, false, J.pstride,
-                                                              wlim, s_pd, k, t, w, fit);
+                                                              flat, tb, wlim, s_pd, k, t, w, fit);
                     }
 #pragma unroll
                     for (int v = 0; v < WPL; v++) {
@@ -995,6 +1061,7 @@ void *kernel_fn(int kb, int wpl) {
     if (wpl == 2)
         return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 2, TWO>)
                        : reinterpret_cast<void *>(batch_kernel<2, 2, TWO>);
+    if (kb == 8) return reinterpret_cast<void *>(batch_kernel<8, 1, TWO>);
     return kb == 4 ? reinterpret_cast<void *>(batch_kernel<4, 1, TWO>)
                    : reinterpret_cast<void *>(batch_kernel<2, 1, TWO>);
 }
@@ -1055,7 +1122,8 @@ struct Shape {
 std::map<std::string, Shape> g_tune;
 
 bool valid_shape(int cpi, int kb, int wpl) {
-    return (cpi == 1 || cpi == 2 || cpi == 4) && (kb == 2 || kb == 4) && (wpl == 1 || wpl == 2);
+    return (cpi == 1 || cpi == 2 || cpi == 4) && (wpl == 1 || wpl == 2) &&
+           (kb == 2 || kb == 4 || (kb == 8 && wpl == 1));
 }
 bool g_tune_loaded = false;
 
@@ -1147,10 +1215,10 @@ int tune(Batch *b, hipStream_t stream) {
         if (wpl > maxch) break;
         for (int cpi : {1, 2, 4}) {
             if (cpi > 1 && cpi * wpl > maxch) break;
-            for (int kb : {2, 4}) {
+            for (int kb : {2, 4, 8}) {
                 // two words per lane leave room for narrow counters only
                 // with four loads in flight: not a candidate
-                if (wpl == 2 && kb == 4) continue;
+                if (wpl == 2 && kb >= 4) continue;
                 b->kb = kb;
                 b->wpl = wpl;
                 rc = upload_table(b, cpi, stream);
@@ -1314,7 +1382,8 @@ int batch_set_tuning(Batch *b, int32_t cpi, int32_t kb, int32_t wpl) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (!valid_shape(cpi, kb, wpl))
         return fail(EBIC_ERR_INVALID_ARG, "item shape (%d, %d, %d): chunk groups per item 1, 2 "
-                    "or 4, loads in flight 2 or 4, words per lane 1 or 2", cpi, kb, wpl);
+                    "or 4, loads in flight 2, 4 or 8 (8 with one word per lane), words per lane 1 or 2",
+                    cpi, kb, wpl);
     // a graph holds the old grid and kernel: rebuilt on the next run
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);

@@ -242,7 +242,7 @@ def _approx_for(k, t):
 
 
 @pytest.mark.parametrize("shape", [(1, 2, 1), (1, 4, 1), (2, 2, 1), (4, 4, 1), (1, 2, 2),
-                                   (1, 4, 2), (2, 2, 2)])
+                                   (1, 4, 2), (2, 2, 2), (1, 8, 1), (2, 8, 1)])
 def test_step_counts_at_counter_boundaries(E, shape):
     """Every count of steps against a trend, from 0 to k-1, meets tolerances
     at each counter width boundary (t = 2^P - 1 and 2^P) and beyond the
@@ -277,7 +277,8 @@ def test_set_tuning_rejects_other_shapes(E):
     m = _matrix(E, X)
     pop = E.ebic_population_upload([[0, 1, 2]], 20)
     b = E.Batch([E.make_job(m, pop, None, E.make_params(**_kw()))])
-    for bad in ((3, 2, 1), (1, 3, 1), (0, 2, 1), (8, 4, 1), (1, 2, 3), (1, 2, 0)):
+    for bad in ((3, 2, 1), (1, 3, 1), (0, 2, 1), (8, 4, 1), (1, 2, 3), (1, 2, 0), (1, 8, 2),
+                (1, 16, 1)):
         with pytest.raises(Exception):
             b.set_tuning(*bad)
     b.set_tuning(2, 4, 2)
@@ -368,7 +369,8 @@ def test_multi_job_batch(E):
     b.close()
 
 
-@pytest.mark.parametrize("shape", [(1, 2, 1), (2, 4, 1), (4, 2, 1), (1, 2, 2), (2, 4, 2)])
+@pytest.mark.parametrize("shape", [(1, 2, 1), (2, 4, 1), (4, 2, 1), (1, 2, 2), (2, 4, 2),
+                                   (2, 8, 1)])
 def test_uneven_jobs_interleaved(E, shape):
     """Jobs of uneven item counts (including an empty population) share one
     launch through the round-robin item schedule and its phases; each job
@@ -485,7 +487,8 @@ def test_autotuned_batch_identical(E, tmp_path, monkeypatch):
                          (plain.support, job.out.support)):
                 assert torch.equal(x, y)
         cpi, kb, wpl = b.tuning()
-        assert cpi in (1, 2, 4) and kb in (2, 4) and wpl in (1, 2)
+        assert cpi in (1, 2, 4) and kb in (2, 4, 8) and wpl in (1, 2)
+        assert kb < 8 or wpl == 1
         b.close()
     text = cache.read_text()
     assert "_i777_j1" in text and "[" in text

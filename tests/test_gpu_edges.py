@@ -1,8 +1,8 @@
 """GPU edge cases against the CPU oracle: denormal and signed-zero values on
 every evaluation path, a matrix tall enough that an individual's rows take
 more than 16 items and its support no longer fits the reduction's LDS copy,
-ingests on several threads and streams at once, and column byte offsets
-past 2^31."""
+ingests on several threads and streams at once, column byte offsets past
+2^31, and pair tables on either side of 2^32 bytes."""
 import os
 import threading
 
@@ -141,6 +141,43 @@ def test_tall_matrix_items_and_supports_outside_lds(E):
     for name, got, out in _paths(E, X, seqs, kw, arch_flags, arch_series):
         _compare(E, got, ev, X.shape[0])
         np.testing.assert_array_equal(out.overlap.cpu().numpy()[:len(seqs), :20], ev.overlap)
+
+
+@pytest.mark.parametrize("cols", [1290, 1300])
+def test_pair_table_near_and_past_4_gib(E, cols):
+    """40,000 rows make 5,120-byte pair rows: 1,290 columns give a 4.26 GB
+    table, below 2^32 bytes, whose steps address pair rows by byte offset
+    through one buffer resource (the last rows end close to 2^32); 1,300
+    columns give 4.33 GB, past it, where steps address rows by pair index.
+    Series reaching the table's last pairs, under every item shape, against
+    the oracle."""
+    R = 40000
+    case = synth.planted_matrix(R, cols, background="normal", n_planted=2,
+                                rows_range=(400, 800), cols_range=(4, 8), sigma=0.05, seed=cols)
+    X = case.X
+    rng = np.random.default_rng(cols)
+    hi = np.arange(cols - 60, cols)
+    seqs = [[cols - 2, cols - 1], [cols - 1, cols - 2], [cols - 3, cols - 1, cols - 2]]
+    seqs += [list(map(int, rng.permutation(hi)[:int(rng.integers(2, 13))])) for _ in range(60)]
+    seqs += [list(map(int, rng.permutation(cols)[:int(rng.integers(2, 13))])) for _ in range(60)]
+    seqs += [list(map(int, t.cols)) for t in case.truth]
+    kw = _kw(approx_permille=700, min_rows=1)
+    ev = oracle.evaluate(X, seqs, params=oracle.make_params(**kw), nthreads=NCPU)
+    assert ev.count.max() > 100
+    m = E.ebic_matrix_prepare(torch.from_numpy(np.ascontiguousarray(X)).cuda())
+    E.ebic_pairs_prepare(m)
+    torch.cuda.synchronize()
+    assert (E.ebic_pairs_bytes(R, cols) < 1 << 32) == (cols == 1290)
+    pop = E.ebic_population_upload(seqs, cols)
+    for shape in ((1, 2, 1), (2, 4, 1), (1, 8, 1), (1, 2, 2), (2, 4, 2)):
+        print(f"pair table {cols} columns, shape {shape}", flush=True)
+        job = E.make_job(m, pop, None, E.make_params(**kw))
+        b = E.Batch([job])
+        b.set_tuning(*shape)
+        b.run()
+        torch.cuda.synchronize()
+        _compare(E, _outputs(E, job.out, len(seqs)), ev, R)
+        b.close()
 
 
 def test_concurrent_ingest_on_three_streams(E):
