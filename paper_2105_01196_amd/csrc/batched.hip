@@ -529,7 +529,7 @@ __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, const uint
 template <int KB, int WPL, bool TWO>
 __global__ void __launch_bounds__(kMaxWaves * kWave)
     batch_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
-                 int32_t njobs, int64_t total_ind, int32_t sup_words, int32_t bits_words,
+                 int32_t njobs, int64_t ph1, int32_t sup_words, int32_t bits_words,
                  int32_t acol_words) {
     // dynamic LDS: the support words (sup_words, 0 when they stay in global
     // memory only), the series' step descriptors, the column bitmap, the
@@ -551,12 +551,14 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     const int nwaves = blockDim.x / kWave;
     // the grid has exactly total_ind workgroups
     const uint32_t slot = blockIdx.x;
-    // phase of this slot: the last phase start at or below it. The starts
-    // and first rounds of kSchedBatch phases are loaded together
-    // (independent scalar loads), then selected in registers.
+    // phase of this slot: the last phase start at or below it. Phase 0
+    // (every job, from round 0) ends at ph1, a kernel argument, so its slots
+    // (all of them when the jobs have equal populations) load nothing; past
+    // it the starts and first rounds of kSchedBatch phases are loaded
+    // together (independent scalar loads), then selected in registers.
     int p = 0;
     int64_t st = 0, rd = 0;
-    for (int q0 = 0; q0 < njobs; q0 += kSchedBatch) {
+    for (int q0 = (int64_t)slot < ph1 ? njobs : 0; q0 < njobs; q0 += kSchedBatch) {
         int64_t qs[kSchedBatch], qr[kSchedBatch];
 #pragma unroll
         for (int u = 0; u < kSchedBatch; u++) {
@@ -861,7 +863,8 @@ struct Batch {
     hipStream_t al_stream = nullptr;
     void *h_stage = nullptr;   // pinned staging of the table
     std::vector<void *> scratch;
-    int64_t total_ind = 0;     // kept alive: the graph's kernel arguments
+    int64_t total_ind = 0;
+    int64_t ph1 = 0;           // first slot past phase 0 (kernel argument, kept alive for a graph)
     int32_t njobs = 0;
     int waves = 1;             // waves per workgroup: the largest items per individual
     int32_t sup_words = 0;     // LDS support words per workgroup (0: global only)
@@ -949,6 +952,7 @@ struct Layout {
     int32_t bits_words = 1;  // LDS column-bitmap words per workgroup
     int32_t acol_words = 0;  // LDS archive columns per workgroup (0: global only)
     int64_t total_ind = 0;   // workgroups
+    int64_t ph1 = 0;         // first slot past phase 0
 };
 
 constexpr size_t table_bytes_max(int32_t n) {
@@ -1013,6 +1017,7 @@ Layout lay_out(DevJob *jobs, int32_t n, int cpi, int wpl, int *perm, char *h) {
         start += (int64_t)(n - p) * (jobs[perm[n - 1 - p]].pop_size - first);
     }
     L.total_ind = start;
+    L.ph1 = n > 1 ? ph_start[1] : start;
     return L;
 }
 
@@ -1050,6 +1055,7 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
     b->bits_words = L.bits_words;
     b->acol_words = L.acol_words;
     b->total_ind = L.total_ind;
+    b->ph1 = L.ph1;
     b->d_sched = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) +
                                              sizeof(DevJob) * n);
     EBIC_HIP(hipMemcpyAsync(b->d_jobs, b->h_stage, bytes, hipMemcpyHostToDevice, stream));
@@ -1081,7 +1087,7 @@ size_t lds_bytes(int32_t sup_words, int32_t bits_words, int32_t acol_words) {
 size_t lds_bytes(const Batch *b) { return lds_bytes(b->sup_words, b->bits_words, b->acol_words); }
 
 int launch_batch(Batch *b, hipStream_t stream) {
-    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind, &b->sup_words,
+    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->ph1, &b->sup_words,
                     &b->bits_words, &b->acol_words};
     EBIC_HIP(hipLaunchKernel(kernel_fn(b, b->kb, b->wpl), dim3((unsigned)b->total_ind),
                              dim3(b->waves * kWave), args, lds_bytes(b), stream));
@@ -1095,7 +1101,7 @@ int build_graph(Batch *b) {
     b->graph = nullptr;
     // one kernel node (no stream capture)
     hipGraphNode_t node = nullptr;
-    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->total_ind, &b->sup_words,
+    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->ph1, &b->sup_words,
                     &b->bits_words, &b->acol_words};
     hipKernelNodeParams pk{};
     pk.func = kernel_fn(b, b->kb, b->wpl);
@@ -1506,7 +1512,7 @@ int batch_run_noalloc(const ebic_job *jobs, int32_t njobs, hipStream_t stream) {
     int64_t *d_sched = reinterpret_cast<int64_t *>(static_cast<char *>(base) +
                                                    sizeof(DevJob) * njobs);
     int32_t n = njobs;
-    void *args[] = {&d_jobs, &d_sched, &n, &L.total_ind, &L.sup_words, &L.bits_words,
+    void *args[] = {&d_jobs, &d_sched, &n, &L.ph1, &L.sup_words, &L.bits_words,
                     &L.acol_words};
     void *fn = L.two ? kernel_fn<true>(kb, wpl) : kernel_fn<false>(kb, wpl);
     EBIC_HIP(hipLaunchKernel(fn, dim3((unsigned)L.total_ind), dim3(L.waves * kWave), args,
