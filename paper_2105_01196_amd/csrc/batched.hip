@@ -59,6 +59,7 @@ struct DevJob {
 namespace {
 
 constexpr int kMaxWaves = 16;     // waves per workgroup: items per individual
+constexpr int kMixedWaves = 4;    // the same, for jobs sharing a launch with smaller ones
 constexpr int kItemRows = 4096;   // 64 lanes x 64 rows, or 64 blocks x 64 rows
 // pair-bitmap loads in flight per wave (KB) and words per lane (WPL) are
 // template parameters, picked per batch by the autotuner
@@ -973,16 +974,36 @@ Layout lay_out(DevJob *jobs, int32_t n, int cpi, int wpl, int *perm, char *h) {
         const DevJob &d = jobs[i];
         L.two |= d.mode == 1 && d.tie_rule != EBIC_TIE_INDEX && d.pairs_strict != nullptr;
     }
-    int32_t wmax = 0, cmax = 0, amax = 0;
-    for (int32_t i = 0; i < n; i++) {
-        DevJob &d = jobs[i];
+    // Items per individual: `cpi` groups each, at most kMaxWaves items. The
+    // workgroup has as many waves as the job with the most items needs, so
+    // when jobs of different row counts share a launch, a small job's
+    // workgroups would carry idle waves through staging and hold wave
+    // slots; there the larger jobs' items are widened to at most
+    // kMixedWaves per individual.
+    auto items = [&](DevJob &d, int32_t waves_max) {
         // whole groups per item, so that no two items share a group
         int32_t cpc = cpi * wpl;
-        const int32_t need = (d.nchunks + kMaxWaves - 1) / kMaxWaves;
+        const int32_t need = (d.nchunks + waves_max - 1) / waves_max;
         if (cpc < need) cpc = (need + wpl - 1) / wpl * wpl;
         d.cpi = cpc < d.nchunks ? cpc : d.nchunks;
         if (d.cpi < 1) d.cpi = 1;
         d.ipi = (d.nchunks + d.cpi - 1) / d.cpi;
+    };
+    int32_t ipi_min = kMaxWaves, ipi_max = 0, busy = 0;
+    for (int32_t i = 0; i < n; i++) {
+        items(jobs[i], kMaxWaves);
+        if (jobs[i].pop_size > 0) {
+            busy++;
+            ipi_min = jobs[i].ipi < ipi_min ? jobs[i].ipi : ipi_min;
+            ipi_max = jobs[i].ipi > ipi_max ? jobs[i].ipi : ipi_max;
+        }
+    }
+    if (busy > 1 && ipi_max > kMixedWaves && ipi_min < ipi_max)
+        for (int32_t i = 0; i < n; i++)
+            if (jobs[i].ipi > kMixedWaves) items(jobs[i], kMixedWaves);
+    int32_t wmax = 0, cmax = 0, amax = 0;
+    for (int32_t i = 0; i < n; i++) {
+        const DevJob &d = jobs[i];
         L.waves = d.ipi > L.waves ? d.ipi : L.waves;
         wmax = d.w64 > wmax ? d.w64 : wmax;
         cmax = d.cols > cmax ? d.cols : cmax;

@@ -406,6 +406,45 @@ def test_uneven_jobs_interleaved(E, shape):
     b.close()
 
 
+@pytest.mark.parametrize("shape", [(1, 2, 1), (2, 4, 1), (1, 2, 2)])
+def test_mixed_row_counts_widen_items(E, shape):
+    """Jobs of 40,000, 20,000, 10,000 and 1,000 rows in one launch: the
+    larger jobs' items are widened to at most four per individual (ten and
+    five 4,096-row chunks here) so the small job's workgroups carry no idle
+    waves; every job equals the oracle, archives included (the 40,000-row
+    job on a sample)."""
+    specs = [(40000, 48, 300, True), (20000, 40, 200, False), (10000, 30, 150, True),
+             (1000, 25, 120, True)]
+    jobs, data = [], []
+    for n, (R, C, P, with_arch) in enumerate(specs):
+        X = synth.planted_matrix(R, C, background="lognormal", n_planted=3,
+                                 rows_range=(R // 50, R // 10), cols_range=(4, 10), sigma=0.1,
+                                 seed=70 + n).X
+        rng = np.random.default_rng(80 + n)
+        seqs = [list(map(int, rng.permutation(C)[:int(rng.integers(2, 17))])) for _ in range(P)]
+        kw = _kw(approx_permille=(850, 700, 900, 800)[n], negative_trends=(1, 0, 1, 1)[n])
+        m = _matrix(E, X)
+        pop = E.ebic_population_upload(seqs, C)
+        E.set_order(pop, E.longest_first(seqs))
+        arch = oarch = None
+        if with_arch:
+            ev = oracle.evaluate(X, seqs[:60], params=oracle.make_params(**kw), nthreads=NCPU)
+            top = [int(i) for i in np.argsort(-ev.score, kind="stable")[:8]]
+            series = [seqs[i] for i in top]
+            arch = E.make_archive(E.flags_to_support(ev.support[top], m.words), series)
+            oarch = oracle.Archive(ev.support[top], series)
+        jobs.append(E.make_job(m, pop, arch, E.make_params(**kw)))
+        data.append((X, seqs, kw, oarch))
+    b = E.Batch(jobs)
+    b.set_tuning(*shape)
+    b.run()
+    torch.cuda.synchronize()
+    for n, (job, (X, seqs, kw, oarch)) in enumerate(zip(jobs, data)):
+        sample = np.arange(0, len(seqs), 5) if n == 0 else None
+        _check_job(E, job, X, seqs, kw, oarch, sample=sample)
+    b.close()
+
+
 def test_graph_replays_track_new_contents(E):
     """A graph-backed batch replayed over populations rewritten in place
     (same lengths, new columns): every replay equals the oracle."""
