@@ -1614,12 +1614,16 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         return EBIC_OK;
     };
     // One generation queued: score population gi (buffer gi % 2), update the
-    // list, keys, the fill's first chunks, pack the next population. Every
+    // list, keys, the fill's first nq chunks, pack the next population. Every
     // kernel does nothing once the run is over or a fill has stalled.
-    // chunks queued per generation: enough for half as many attempts again
-    // as the population (tabu hits and children of the wrong length)
-    const int kChunksQueued = std::max(1, (P + P / 2 + 64 + kChunkMax - 1) / kChunkMax);
-    auto queue_generation = [&](int gi) -> int {
+    // Chunks queued per generation: first enough for a quarter more attempts
+    // than the population; after a fill has needed more (many tabu hits or
+    // children of the wrong length), enough for half as many again. A chunk
+    // queued beyond the fill's need still costs its five launches.
+    const int per_chunk = std::min(kChunkMax, P + P / 2 + 64);
+    const int nq_lo = std::max(1, (P + P / 4 + 64 + per_chunk - 1) / per_chunk);
+    const int nq_hi = std::max(nq_lo, (P + P / 2 + 64 + kChunkMax - 1) / kChunkMax);
+    auto queue_generation = [&](int gi, int nq) -> int {
         const int cur = gi & 1, Pn = gi == 0 ? Pn0 : P;
         hipLaunchKernelGGL(dl_patch_kernel, dim3(1), dim3(64), 0, stream, B, f_size, f_len);
         DL_HIP(hipGetLastError());
@@ -1633,8 +1637,8 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         hipLaunchKernelGGL(dl_keys_kernel, dim3((std::max(Pn, C / 64 + 1) + 3) / 4), dim3(256), 0,
                            stream, q, B, cur, Pn);
         DL_HIP(hipGetLastError());
-        for (int c = 0; c < kChunksQueued; c++) {
-            int r = chunk(cur, Pn, P, c == kChunksQueued - 1);
+        for (int c = 0; c < nq; c++) {
+            int r = chunk(cur, Pn, P, c == nq - 1);
             if (r) return r;
         }
         hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P, 1);
@@ -1643,41 +1647,51 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         DL_HIP(hipGetLastError());
         return EBIC_OK;
     };
-    // Generations after the first replay one of two captured graphs (by the
-    // population's parity: every kernel argument is the same otherwise),
-    // which saves the launch cost of a generation's kernels; without them
-    // (capture unavailable) the kernels are launched one by one.
+    // Generations after the first replay captured graphs, one per
+    // population parity (every kernel argument is the same otherwise) and
+    // chunk count, captured when first needed; this saves the launch cost of
+    // a generation's kernels. Without them (capture unavailable) the kernels
+    // are launched one by one.
     struct Graphs {
-        hipGraph_t g[2] = {nullptr, nullptr};
-        hipGraphExec_t x[2] = {nullptr, nullptr};
+        hipGraph_t g[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+        hipGraphExec_t x[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
         ~Graphs() {
-            for (int i = 0; i < 2; i++) {
-                if (x[i]) (void)hipGraphExecDestroy(x[i]);
-                if (g[i]) (void)hipGraphDestroy(g[i]);
-            }
+            for (int i = 0; i < 2; i++)
+                for (int v = 0; v < 2; v++) {
+                    if (x[i][v]) (void)hipGraphExecDestroy(x[i][v]);
+                    if (g[i][v]) (void)hipGraphDestroy(g[i][v]);
+                }
         }
     } graphs;
     bool use_graphs = Pn0 == P && stream != nullptr && q.G > 2;
-    for (int par = 0; par < 2 && use_graphs; par++) {
-        if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-            use_graphs = false;
-            break;
+    auto capture = [&](int v) {
+        for (int par = 0; par < 2 && use_graphs; par++) {
+            if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+                use_graphs = false;
+                break;
+            }
+            // any generation after the first of this parity
+            const int r = queue_generation(2 + par, v ? nq_hi : nq_lo);
+            hipGraph_t gr = nullptr;
+            const hipError_t e = hipStreamEndCapture(stream, &gr);
+            graphs.g[par][v] = gr;
+            if (r || e != hipSuccess || !gr ||
+                hipGraphInstantiate(&graphs.x[par][v], gr, nullptr, nullptr, 0) != hipSuccess)
+                use_graphs = false;
         }
-        const int r = queue_generation(2 + par);  // any generation after the first of this parity
-        hipGraph_t gr = nullptr;
-        const hipError_t e = hipStreamEndCapture(stream, &gr);
-        graphs.g[par] = gr;
-        if (r || e != hipSuccess || !gr ||
-            hipGraphInstantiate(&graphs.x[par], gr, nullptr, nullptr, 0) != hipSuccess)
-            use_graphs = false;
-    }
-    (void)hipGetLastError();  // a refused capture leaves nothing for later calls
+        (void)hipGetLastError();  // a refused capture leaves nothing for later calls
+    };
+    int variant = 0;  // 1 once a fill has stalled: nq_hi chunks from then on
+    capture(0);
     auto queue = [&](int gi) -> int {
         if (gi > 0 && use_graphs) {
-            DL_HIP(hipGraphLaunch(graphs.x[gi & 1], stream));
-            return EBIC_OK;
+            if (!graphs.x[gi & 1][variant]) capture(variant);
+            if (use_graphs) {
+                DL_HIP(hipGraphLaunch(graphs.x[gi & 1][variant], stream));
+                return EBIC_OK;
+            }
         }
-        return queue_generation(gi);
+        return queue_generation(gi, variant ? nq_hi : nq_lo);
     };
     // generations are queued a few at a time; the host reads the state
     // between groups
@@ -1691,7 +1705,9 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         if (hs.p->error) return fail(EBIC_ERR_CAPACITY, "device loop: the tabu set is full");
         if (hs.p->over) break;
         if (hs.p->stalled) {
-            // finish the stalled fill chunk by chunk, then go on
+            // finish the stalled fill chunk by chunk, then go on, queueing
+            // more chunks per generation
+            variant = 1;
             const int cur = (hs.p->g - 1) & 1;
             dl_resume_kernel<<<1, 64, 0, stream>>>(B);
             for (;;) {
