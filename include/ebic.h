@@ -435,7 +435,11 @@ void ebic_session_free(ebic_session *s);
  * scheduler keeps ticking; a prepared job joins at the next tick. Each tick
  * scores the current populations of the jobs that want scores in one
  * batched launch; each job's host steps then run as a task of their own, and
- * the job joins the next tick once they are done. A finished job frees its memory and slot, and
+ * the job joins the next tick once they are done. If asked for, a job with a
+ * large population (device_loop_population) instead goes to a runner thread,
+ * which sets it up and runs its generations on the device as
+ * ebic_run_device does (its host steps would hold the ticks back); its
+ * footprint then also counts the device loop's memory. A finished job frees its memory and slot, and
  * queued jobs are admitted at the next tick. Each job's result is identical to ebic_run with the same
  * matrix, parameters and seed. */
 typedef struct ebic_server ebic_server;
@@ -443,6 +447,10 @@ typedef struct ebic_server ebic_server;
 typedef struct ebic_server_config {
     size_t hbm_budget;      /* bytes of device memory jobs may hold; 0 = 80% of free */
     int32_t max_active;     /* jobs resident at once; 0 = 64                         */
+    int32_t device_loop_population; /* jobs with at least this population (and
+                               within ebic_run_device's limits) run as device
+                               loops on runner threads; 0 = none              */
+    int32_t device_loop_runners;    /* runner threads (each with a stream); 0 = 2 */
 } ebic_server_config;
 
 typedef struct ebic_server_metrics {
@@ -459,6 +467,8 @@ typedef struct ebic_server_metrics {
     double host_s;              /* jobs' host steps (summed over worker tasks) */
     double setup_s;             /* admitted jobs' setup, beside the ticks      */
     double release_s;           /* ended jobs' frees                           */
+    int64_t device_loop_jobs;   /* jobs admitted to the runners                */
+    double device_loop_s;       /* runners' time on their jobs, summed         */
 } ebic_server_metrics;
 
 /* Creates the server on the current device; the scheduler and each

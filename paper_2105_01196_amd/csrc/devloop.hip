@@ -1354,6 +1354,28 @@ size_t chain_lds(int S, int E) {
 
 }  // namespace
 
+namespace {
+// Device memory of a run's loop: the tabu set (cap series in an arena, a
+// table of `slots`), two populations with their packed copies, supports,
+// keys and use counts, the list's slots, one chunk's attempts, the span
+// and the trace.
+size_t loop_bytes(int64_t cap, size_t slots, int P, int K, int kmax, int W, int G) {
+    return (size_t)cap * (2 * kmax + 4) + slots * 12 +
+           (size_t)P * (2 * 2 * kmax + 8 + 2 * kmax + 4 + 8 + 4 + 8 * W + 8) +
+           (size_t)(K + 2) * (2 * kmax + 8 * W) * 2 +
+           (size_t)kChunkMax * (2 * kmax + 4 + 4 + 4 + 8 + 4) + kSpanMax + (size_t)G * 32;
+}
+}  // namespace
+
+size_t devloop_bytes(int32_t rows, int32_t cols, const ebic_params &p) {
+    (void)cols;
+    const int P = p.population, G = p.generations > 1 ? p.generations : 1;
+    // the first population's series and one per slot of every later generation
+    const int64_t cap = (int64_t)P * G + 1;
+    return loop_bytes(cap, pow2_at_least((size_t)(2 * cap)), P, p.archive_size, p.k_max,
+                      rows_padded(rows) / 64, G);
+}
+
 int devloop_check(int32_t cols, const ebic_params &p) {
     (void)cols;
     if (p.tournament > kDlMaxT)
@@ -1405,11 +1427,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     q.tabu_mask = slots - 1;
     if (cap > INT32_MAX / 4) return fail(EBIC_ERR_CAPACITY, "tabu set of %lld series", (long long)cap);
     q.tabu_cap = (int32_t)cap;
-    const size_t bytes = (size_t)cap * (2 * kmax + 4) + slots * 12 +
-                         (size_t)P * (2 * 2 * kmax + 8 + 2 * kmax + 4 + 8 + 4 + 8 * W + 8) +
-                         (size_t)(K + 2) * (2 * kmax + 8 * W) * 2 +
-                         (size_t)kChunkMax * (2 * kmax + 4 + 4 + 4 + 8 + 4) + kSpanMax +
-                         (size_t)q.G * 32;
+    const size_t bytes = loop_bytes(cap, slots, P, K, kmax, W, q.G);
     size_t free_b = 0, total_b = 0;
     DL_HIP(hipMemGetInfo(&free_b, &total_b));
     if (bytes > free_b / 2)

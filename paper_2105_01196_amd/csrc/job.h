@@ -439,6 +439,10 @@ class Job {
 int check_run_params(int32_t rows, int32_t cols, const ebic_params *p);
 // The device loop's own limits on the run parameters.
 int devloop_check(int32_t cols, const ebic_params &p);
+// Device memory the device loop of such a run takes beside the job's own
+// (an upper bound: the tabu set as if every slot of every generation
+// brought a new series).
+size_t devloop_bytes(int32_t rows, int32_t cols, const ebic_params &p);
 // Runs a started job's generations on the device (devloop.hip), scoring
 // each population with *batch; on return the job is in its final step.
 int devloop_run(Job &job, Batch **batch, hipStream_t stream);

@@ -31,6 +31,8 @@ namespace {
 
 // Threads (each with a stream) setting admitted jobs up beside the ticks.
 constexpr int kPreparers = 3;
+// Runner threads when device loops are asked for.
+constexpr int kRunners = 2;
 // Longest wait, in microseconds, for more jobs to join a tick.
 constexpr int kGather = 500;
 
@@ -109,6 +111,7 @@ struct ServerJob {
     ebic_params params{};
     uint64_t seed = 0;
     bool pairs = false;
+    bool device_loop = false;  // runs on a runner thread (generations on the device)
     size_t footprint = 0;
     std::unique_ptr<Job> job;
     double t_submit = 0, t_done = 0;
@@ -148,6 +151,7 @@ class Server {
 
     void loop();
     void prepare_loop(hipStream_t stream);
+    void runner_loop(hipStream_t stream);
     void tick(std::vector<std::shared_ptr<ServerJob>> &jobs, Slot &sl);
     void finish_job(const std::shared_ptr<ServerJob> &j, int status, const char *err);
     void release_loop();
@@ -158,30 +162,34 @@ class Server {
                              std::vector<size_t> *at);
 
     std::mutex mu_;
-    std::condition_variable cv_work_, cv_done_, cv_prep_, cv_rel_;
+    std::condition_variable cv_work_, cv_done_, cv_prep_, cv_rel_, cv_run_;
     std::deque<std::shared_ptr<ServerJob>> queue_;
     // admitted, waiting for the preparer; prepared, waiting for a tick;
     // ended, waiting for their memory to be freed
     std::deque<std::shared_ptr<ServerJob>> prep_q_, ready_, rel_q_;
+    std::deque<std::shared_ptr<ServerJob>> run_q_;  // admitted device-loop jobs
     std::deque<std::shared_ptr<ServerJob>> host_done_;  // host step finished
     std::unordered_map<int64_t, std::shared_ptr<ServerJob>> jobs_;
     std::vector<double> latencies_;
     int64_t next_id_ = 1, submitted_ = 0, completed_ = 0, failed_ = 0, evaluations_ = 0;
-    int64_t ticks_ = 0;
+    int64_t ticks_ = 0, device_loop_jobs_ = 0;
+    int32_t dl_population_ = 0;  // 0: no device loops
     int64_t n_active_ = 0;  // admitted, result not yet published
     int64_t n_held_ = 0;    // admitted, memory not yet freed (the slots in use)
     bool rel_quit_ = false;
     double busy_s_ = 0, stage_s_ = 0, device_s_ = 0, host_s_ = 0, setup_s_ = 0, release_s_ = 0;
+    double device_loop_s_ = 0;
     size_t budget_ = 0, in_use_ = 0;
     int32_t max_active_ = 64;
     bool stop_ = false;
     int device_ = 0;
     hipStream_t stream_ = nullptr;
     std::vector<hipStream_t> prep_streams_;  // one per preparer thread
+    std::vector<hipStream_t> run_streams_;   // one per runner thread
     Slot slots_[kSlots];
     std::unique_ptr<WorkerPool> pool_;
     std::thread thread_, rel_thread_;
-    std::vector<std::thread> prep_threads_;
+    std::vector<std::thread> prep_threads_, run_threads_;
 };
 
 int Server::init(const ebic_server_config *cfg) {
@@ -190,6 +198,10 @@ int Server::init(const ebic_server_config *cfg) {
     EBIC_HIP(hipMemGetInfo(&free_b, &total_b));
     budget_ = (cfg && cfg->hbm_budget) ? cfg->hbm_budget : free_b / 10 * 8;
     max_active_ = (cfg && cfg->max_active > 0) ? cfg->max_active : 64;
+    if (cfg && cfg->device_loop_population > 0) dl_population_ = cfg->device_loop_population;
+    const int runners = dl_population_ <= 0 ? 0
+                        : (cfg && cfg->device_loop_runners > 0) ? cfg->device_loop_runners
+                                                                : kRunners;
     EBIC_HIP(hipStreamCreateWithFlags(&stream_, hipStreamNonBlocking));
     for (int w = 0; w < kPreparers; w++) {
         hipStream_t st = nullptr;
@@ -198,7 +210,13 @@ int Server::init(const ebic_server_config *cfg) {
     }
     const unsigned hw = std::thread::hardware_concurrency();
     pool_.reset(new WorkerPool((int)std::max(1u, std::min(hw ? hw : 1u, 16u))));
+    for (int r = 0; r < runners; r++) {
+        hipStream_t st = nullptr;
+        EBIC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        run_streams_.push_back(st);
+    }
     for (hipStream_t st : prep_streams_) prep_threads_.emplace_back([this, st] { prepare_loop(st); });
+    for (hipStream_t st : run_streams_) run_threads_.emplace_back([this, st] { runner_loop(st); });
     rel_thread_ = std::thread([this] { release_loop(); });
     thread_ = std::thread([this] { loop(); });
     return EBIC_OK;
@@ -211,10 +229,12 @@ Server::~Server() {
     }
     cv_work_.notify_all();
     cv_prep_.notify_all();
+    cv_run_.notify_all();
     // the scheduler ends once every admitted job is done, so the preparers
-    // have nothing left when they are told to stop
+    // and runners have nothing left when they are told to stop
     if (thread_.joinable()) thread_.join();
     for (auto &t : prep_threads_) t.join();
+    for (auto &t : run_threads_) t.join();
     {
         std::lock_guard<std::mutex> lk(mu_);
         rel_quit_ = true;  // nothing ends any more; free what is left
@@ -226,6 +246,7 @@ Server::~Server() {
         if (sl.batch) batch_destroy(sl.batch);
     if (stream_) (void)hipStreamDestroy(stream_);
     for (hipStream_t st : prep_streams_) (void)hipStreamDestroy(st);
+    for (hipStream_t st : run_streams_) (void)hipStreamDestroy(st);
     for (auto &kv : jobs_) delete kv.second->result;
 }
 
@@ -248,6 +269,17 @@ int Server::submit(const float *h_x, int32_t rows, int32_t cols, const ebic_para
         const size_t pb = Job::pair_table_bytes(rows, cols, *p);
         j->pairs = pb > 0 && pb <= budget_ / 8;
         j->footprint = Job::footprint(rows, cols, *p, j->pairs);
+        j->device_loop = !run_streams_.empty() && dl_population_ > 0 &&
+                         p->population >= dl_population_ &&
+                         devloop_check(cols, *p) == EBIC_OK;
+        if (j->device_loop) {
+            // the device loop's memory, and staging of the job's own for the
+            // final step (inputs, scores, counts and supports)
+            const size_t W = (size_t)rows_padded(rows) / 64;
+            j->footprint += devloop_bytes(rows, cols, *p) +
+                            (size_t)std::max(p->population, p->archive_size) *
+                                (4 + 2 * (size_t)p->k_max + 8 + 4 + 8 * W);
+        }
         j->id = next_id_++;
         j->t_submit = now_s();
         jobs_[j->id] = j;
@@ -305,6 +337,8 @@ void Server::stats(ebic_server_metrics *st) {
     st->release_s = release_s_;
     st->hbm_in_use = in_use_;
     st->hbm_budget = budget_;
+    st->device_loop_jobs = device_loop_jobs_;
+    st->device_loop_s = device_loop_s_;
 }
 
 // Called with mu_ held.
@@ -583,6 +617,66 @@ void Server::prepare_loop(hipStream_t stream) {
     }
 }
 
+// A runner takes admitted device-loop jobs one at a time, sets each up as
+// a preparer does, runs its generations on the device (devloop_run) and its
+// final step with a batch of its own, all on the runner's stream, and ends
+// it; its result is the job's ebic_run result, as from the ticks.
+void Server::runner_loop(hipStream_t stream) {
+    (void)hipSetDevice(device_);
+    Batch *batch = nullptr;
+    for (;;) {
+        std::shared_ptr<ServerJob> j;
+        {
+            std::unique_lock<std::mutex> lk(mu_);
+            cv_run_.wait(lk, [&] { return stop_ || !run_q_.empty(); });
+            if (run_q_.empty()) break;  // stopping, and nothing admitted is left
+            j = run_q_.front();
+            run_q_.pop_front();
+        }
+        const double t0 = now_s();
+        j->job.reset(new Job(j->params, j->seed, stream));
+        j->job->set_host_matrix(j->x.data());
+        Job &job = *j->job;
+        // staging buffers of its own: the final step is staged and fetched
+        // as in a session, not packed by a tick
+        int rc = job.setup(j->x.data(), j->rows, j->cols, j->pairs, true);
+        if (rc == EBIC_OK) {
+            const hipError_t e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
+        }
+        if (rc == EBIC_OK) {
+            job.start();
+            rc = devloop_run(job, &batch, stream);
+        }
+        while (rc == EBIC_OK && !job.done()) {  // the final step (step 9)
+            ebic_job view;
+            rc = job.stage(&view);
+            if (rc == EBIC_OK) rc = batch_set(&batch, &view, 1, stream, job.allocator());
+            if (rc == EBIC_OK) rc = batch_run(batch, stream);
+            if (rc == EBIC_OK) rc = job.fetch();
+            if (rc == EBIC_OK) {
+                const hipError_t e = hipStreamSynchronize(stream);
+                if (e != hipSuccess) rc = check_hip(e, "hipStreamSynchronize");
+            }
+            if (rc == EBIC_OK) rc = job.fetch_first();
+            if (rc == EBIC_OK) rc = job.advance();
+        }
+        if (rc == EBIC_OK) {
+            j->result = job.take_result();
+        } else {
+            j->end_status = rc;
+            j->end_error = ebic_last_error();
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            device_loop_s_ += now_s() - t0;
+        }
+        end_jobs({j});
+        cv_work_.notify_all();
+    }
+    if (batch) batch_destroy(batch);
+}
+
 void Server::loop() {
     (void)hipSetDevice(device_);
     std::vector<std::shared_ptr<ServerJob>> idle;  // scores wanted: prepared or stepped
@@ -620,10 +714,18 @@ void Server::loop() {
                 in_use_ += j->footprint;
                 n_active_++;  // admitted jobs count as active
                 n_held_++;
-                prep_q_.push_back(j);
+                if (j->device_loop) {
+                    run_q_.push_back(j);
+                    device_loop_jobs_++;
+                } else {
+                    prep_q_.push_back(j);
+                }
                 admitted = true;
             }
-            if (admitted) cv_prep_.notify_all();
+            if (admitted) {
+                cv_prep_.notify_all();
+                cv_run_.notify_all();
+            }
             while (!ready_.empty()) {
                 idle.push_back(ready_.front());
                 ready_.pop_front();

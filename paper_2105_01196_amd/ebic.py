@@ -94,7 +94,8 @@ class ebic_result(ctypes.Structure):
 
 
 class ebic_server_config(ctypes.Structure):
-    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", _i32)]
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("max_active", _i32),
+                ("device_loop_population", _i32), ("device_loop_runners", _i32)]
 
 
 class ebic_server_metrics(ctypes.Structure):
@@ -106,7 +107,8 @@ class ebic_server_metrics(ctypes.Structure):
                 ("busy_s", ctypes.c_double), ("hbm_in_use", ctypes.c_size_t),
                 ("hbm_budget", ctypes.c_size_t), ("stage_s", ctypes.c_double),
                 ("device_s", ctypes.c_double), ("host_s", ctypes.c_double),
-                ("setup_s", ctypes.c_double), ("release_s", ctypes.c_double)]
+                ("setup_s", ctypes.c_double), ("release_s", ctypes.c_double),
+                ("device_loop_jobs", ctypes.c_int64), ("device_loop_s", ctypes.c_double)]
 
 
 EBIC_STOP_GENERATIONS = 1
@@ -728,10 +730,14 @@ class Session:
 
 
 class Server:
-    """Job server (ebic_server_*): continuous batching of runs on one GPU."""
+    """Job server (ebic_server_*): continuous batching of runs on one GPU;
+    jobs of at least device_loop_population individuals (0: none) run as
+    device loops on device_loop_runners threads (0: 2)."""
 
-    def __init__(self, hbm_budget: int = 0, max_active: int = 0):
-        cfg = ebic_server_config(hbm_budget, max_active)
+    def __init__(self, hbm_budget: int = 0, max_active: int = 0,
+                 device_loop_population: int = 0, device_loop_runners: int = 0):
+        cfg = ebic_server_config(hbm_budget, max_active, device_loop_population,
+                                 device_loop_runners)
         h = _vp()
         _check(lib().ebic_server_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.handle = h

@@ -78,6 +78,26 @@ def test_alone_equals_mix(E):
         np.testing.assert_array_equal(x.cols, y.cols)
 
 
+def test_device_loop_jobs_in_the_mix(E):
+    """With a low population threshold the server runs the larger jobs as
+    device loops on its runner threads and the rest in ticks; a job beyond
+    the device loop's limits (tournament of 20) stays in the ticks. Every
+    result equals ebic_run alone."""
+    jobs = _mix()
+    X, kw, seed = jobs[1]
+    jobs.append((X, dict(kw, tournament=20), 777))
+    alone = [E.ebic_run(x, E.make_params(**k), sd) for x, k, sd in jobs]
+    srv = E.Server(device_loop_population=150, device_loop_runners=2)
+    ids = [srv.submit(x, E.make_params(**k), sd) for x, k, sd in jobs]
+    for a, i in zip(alone, ids):
+        _same(a, srv.wait(i))
+    st = srv.stats()
+    # populations 256, 192 and 256 within the limits; 256 with a tournament of 20 is not
+    assert st["device_loop_jobs"] == 3 and st["completed"] == len(jobs) and st["failed"] == 0
+    assert st["ticks"] > 0 and st["device_loop_s"] > 0
+    srv.close()
+
+
 def test_many_clashing_candidates_in_the_mix(E):
     """Top-rank list updates that walk past the candidates whose supports
     a tick gathers (no overlap allowed, 12 columns) give the same result as
