@@ -438,22 +438,54 @@ __global__ void __launch_bounds__(kBlock) dl_list_kernel(DlParams q, DlBufs B, i
     // only if the list falls short of full after tier 1 (an admission can
     // remove several members). Each tier is sorted when it is reached.
     const int nA0 = nA;
-    for (int i = tid; i < Ppad; i += nt) {
+    // every length and count of this thread's candidates loaded first, all
+    // in flight together
+    constexpr int kPer = kDlMaxP / kBlock;
+    int klen[kPer], kcnt[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        const int i = tid + r * nt;
+        klen[r] = i < Pn ? plen[i] : 0;
+        kcnt[r] = i < Pn ? B.cnt[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        const int i = tid + r * nt;
+        if (i >= Ppad) break;
         int t = 0;
         if (i < Pn) {
-            const int k = plen[i];
+            const int k = klen[r];
             const uint16_t *si = pop + (size_t)i * kmax;
-            const double sc = score_of(i);
+            const double sc = (kcnt[r] >= q.min_rows && k >= q.k_score_min)
+                                  ? ldexp((double)kcnt[r], k) : 0.0;
             bool cand = sc > 0.0;
             if (cand) {
-                const bool rv = q.neg && reverse_smaller_seq(si, k);
+                // a series already listed (or its reverse) has the member's
+                // length and, being the same rows, its score: only such
+                // members are compared column by column
+                int rv = -1;  // the series' canonical direction, found when first needed
                 for (int j = 0; j < nA && cand; j++) {
                     const int sl = s_list[j];
-                    if (s_alen[sl] != k) continue;
+                    if (s_alen[sl] != k || s_asc[sl] != sc) continue;
+                    if (rv < 0) rv = q.neg && reverse_smaller_seq(si, k);
                     const uint16_t *ms = mcols(sl);
-                    int e = 0;
-                    while (e < k && canon_at(si, k, rv, e) == canon_at(ms, k, s_arev[j] != 0, e)) e++;
-                    if (e == k) cand = false;
+                    // sixteen columns at a time, their loads in flight together
+                    // (the population's copies of the members match to the
+                    // end); positions past the series repeat its last one
+                    bool same = true;
+                    const bool mrev = s_arev[j] != 0;
+                    for (int e0 = 0; e0 < k && same; e0 += 16) {
+                        int ca[16], cb[16];
+#pragma unroll
+                        for (int u = 0; u < 16; u++) {
+                            const int e = e0 + u < k ? e0 + u : k - 1;
+                            ca[u] = canon_at(si, k, rv != 0, e);
+                            cb[u] = canon_at(ms, k, mrev, e);
+                        }
+#pragma unroll
+                        for (int u = 0; u < 16; u++) same &= ca[u] == cb[u];
+                    }
+                    if (same) cand = false;
                 }
             }
             if (cand) {
