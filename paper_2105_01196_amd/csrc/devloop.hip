@@ -834,10 +834,25 @@ __global__ void __launch_bounds__(kBlock) dl_chain_kernel(DlParams q, DlBufs B, 
         s_total = 0;
     }
     __syncthreads();
-    for (int o = tid; o < S; o += nt) {
-        const int c = B.span[o];
-        s_c[o] = (uint8_t)c;
-        if (c >= E) s_bad = 1;
+    // the draw counts into LDS, 16 bytes per load (a byte per load would
+    // take one round trip per 1,024 offsets)
+    {
+        const uint4 *sp4 = reinterpret_cast<const uint4 *>(B.span);
+        int bad = 0;
+        for (int v = tid; v * 16 < S; v += nt) {
+            const uint4 x = sp4[v];
+            const uint32_t wd[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int b = 0; b < 16; b++) {
+                const int o = v * 16 + b;
+                const int c = (int)((wd[b >> 2] >> ((b & 3) * 8)) & 0xFFu);
+                if (o < S) {
+                    s_c[o] = (uint8_t)c;
+                    bad |= c >= E;
+                }
+            }
+        }
+        if (bad) s_bad = 1;
     }
     __syncthreads();
     if (!s_bad) {
@@ -1124,6 +1139,21 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
     if (!fill_active(st)) return;
     const int A = st->chunk_n;
     constexpr uint32_t kMask = kDedupSlots - 1;
+    // each thread takes a contiguous range of attempts; their flags, hashes
+    // and lengths are loaded once, all in flight together, and kept in
+    // registers
+    constexpr int kPer = (kChunkMax + kBlock - 1) / kBlock;
+    const int per = (A + nt - 1) / nt, lo = tid * per, hi = lo + per < A ? lo + per : A;
+    uint32_t fl[kPer];
+    uint64_t hh[kPer];
+    int cl[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        const bool in = lo + r < hi;
+        fl[r] = in ? B.cflag[lo + r] : 0u;
+        hh[r] = in ? B.chash[lo + r] : 0ull;
+        cl[r] = in ? B.clen[lo + r] : 0;
+    }
     for (int x = tid; x < kDedupSlots; x += nt) {
         s_th[x] = 0;
         s_ti[x] = 0xFFFFFFFFu;
@@ -1134,52 +1164,61 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
     // attempt index; a child whose entry holds a smaller index with the same
     // canonical series repeats it (a different series under the same hash,
     // vanishingly rare, falls back to comparing every earlier child)
-    for (int i = tid; i < A; i += nt) {
-        if (!(B.cflag[i] & kValid)) continue;
-        const uint64_t h = B.chash[i];
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        if (!(fl[r] & kValid)) continue;
+        const uint64_t h = hh[r];
         uint32_t slot = (uint32_t)h & kMask;
         for (;;) {
             const unsigned long long prev = atomicCAS(
                 reinterpret_cast<unsigned long long *>(&s_th[slot]), 0ull, (unsigned long long)h);
             if (prev == 0ull || prev == h) {
-                atomicMin(&s_ti[slot], (uint32_t)i);
+                atomicMin(&s_ti[slot], (uint32_t)(lo + r));
                 break;
             }
             slot = (slot + 1) & kMask;
         }
     }
     __syncthreads();
-    auto same_series = [&](int i, int j) {
-        const int li = B.clen[i];
+    auto same_series = [&](int i, int li, int j) {
         if (B.clen[j] != li) return false;
+        if (li <= 0) return true;
         const bool ri = (B.cflag[i] & kRev) != 0, rj = (B.cflag[j] & kRev) != 0;
         const uint16_t *ci = B.child + (size_t)i * kmax, *cj = B.child + (size_t)j * kmax;
-        int e = 0;
-        while (e < li && canon_at(ci, li, ri, e) == canon_at(cj, li, rj, e)) e++;
-        return e == li;
+        // sixteen columns per round of loads (a repeated child matches to
+        // the end); positions past the series repeat its last one
+        bool same = true;
+        for (int e0 = 0; e0 < li && same; e0 += 16) {
+            int ca[16], cb[16];
+#pragma unroll
+            for (int u = 0; u < 16; u++) {
+                const int e = e0 + u < li ? e0 + u : li - 1;
+                ca[u] = canon_at(ci, li, ri, e);
+                cb[u] = canon_at(cj, li, rj, e);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; u++) same &= ca[u] == cb[u];
+        }
+        return same;
     };
-    for (int i = tid; i < A; i += nt) {
-        const uint32_t f = B.cflag[i];
-        if (!(f & kValid)) continue;
-        const uint64_t h = B.chash[i];
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+        const int i = lo + r;
+        if (!(fl[r] & kValid)) continue;
+        const uint64_t h = hh[r];
         uint32_t slot = (uint32_t)h & kMask;
         while (s_th[slot] != h) slot = (slot + 1) & kMask;
         const int m = (int)s_ti[slot];
         if (m >= i) continue;
-        bool dup = same_series(i, m);
+        bool dup = same_series(i, cl[r], m);
         for (int j = 0; j < i && !dup; j++)
-            if (j != m && (B.cflag[j] & kValid) && B.chash[j] == h && same_series(i, j)) dup = true;
-        if (dup) B.cflag[i] = f | kDup;
+            if (j != m && (B.cflag[j] & kValid) && B.chash[j] == h && same_series(i, cl[r], j))
+                dup = true;
+        if (dup) fl[r] |= kDup;  // only this kernel reads it
     }
     __syncthreads();
     const int Nn0 = st->Nn, att0 = st->att, tabu0 = st->tabu_n;
     const int64_t hits0 = st->hits;
-    // each thread takes a contiguous range of attempts, its flags in registers
-    constexpr int kPer = (kChunkMax + kBlock - 1) / kBlock;
-    const int per = (A + nt - 1) / nt, lo = tid * per, hi = lo + per < A ? lo + per : A;
-    uint32_t fl[kPer];
-#pragma unroll
-    for (int r = 0; r < kPer; r++) fl[r] = lo + r < hi ? B.cflag[lo + r] : 0u;
     auto is_hit = [&](uint32_t f) { return (f & kValid) && (f & (kInSet | kDup)); };
     auto is_acc = [&](uint32_t f) { return (f & kValid) && !(f & (kInSet | kDup)); };
     int nacc = 0, nhit = 0, last = -1;
@@ -1238,7 +1277,7 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
             if (!is_acc(fl[r])) continue;
             B.cslot[i] = Nn0 + acc;
             B.carena[i] = tabu0 + acc;
-            B.plen[nxt][Nn0 + acc] = B.clen[i];
+            B.plen[nxt][Nn0 + acc] = cl[r];
             B.cflag[i] = fl[r] | kAccept;
             acc++;
             uacc++;
@@ -1489,7 +1528,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     DL_HIP(arch_off.alloc(K + 3, al, stream));
     DL_HIP(arch_cols.alloc((size_t)(K + 2) * kmax, al, stream));
     DL_HIP(arch_sup.alloc((size_t)(K + 2) * W, al, stream));
-    DL_HIP(span.alloc(kSpanMax, al, stream));
+    DL_HIP(span.alloc(kSpanMax + 16, al, stream));  // whole 16-byte loads past the last offset
     DL_HIP(att_off.alloc(kChunkMax, al, stream));
     DL_HIP(att_end.alloc(kChunkMax, al, stream));
     DL_HIP(child.alloc((size_t)kChunkMax * kmax, al, stream));
