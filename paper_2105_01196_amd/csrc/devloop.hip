@@ -1131,8 +1131,10 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
                                                            const int32_t *att_end, int cur,
                                                            int last_chunk) {
     extern __shared__ uint64_t s_dyn[];
-    uint64_t *s_th = s_dyn;                                          // hash, 0 = empty
-    uint32_t *s_ti = reinterpret_cast<uint32_t *>(s_dyn + kDedupSlots);  // smallest attempt
+    // the table: a 32-bit tag of each hash (its high half, odd; 0 = empty)
+    // in the slot its low bits pick, and the smallest attempt with that tag
+    uint32_t *s_th = reinterpret_cast<uint32_t *>(s_dyn);
+    uint32_t *s_ti = s_th + kDedupSlots;
     __shared__ int s_tmp[33];
     DlState *st = B.st;
     const int tid = threadIdx.x, nt = blockDim.x, kmax = q.kmax;
@@ -1160,19 +1162,20 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
     }
     __syncthreads();
     // a chunk's children that repeat an earlier child of the chunk: every
-    // valid child enters a table keyed by its hash, keeping the smallest
-    // attempt index; a child whose entry holds a smaller index with the same
-    // canonical series repeats it (a different series under the same hash,
-    // vanishingly rare, falls back to comparing every earlier child)
+    // valid child enters a table keyed by its hash's tag, keeping the
+    // smallest attempt index; a child whose entry holds a smaller index with
+    // the same canonical series repeats it (a different series under the
+    // same tag, vanishingly rare, falls back to comparing every earlier
+    // child with the same hash)
+    auto tag_of = [](uint64_t h) { return (uint32_t)(h >> 32) | 1u; };
 #pragma unroll
     for (int r = 0; r < kPer; r++) {
         if (!(fl[r] & kValid)) continue;
-        const uint64_t h = hh[r];
-        uint32_t slot = (uint32_t)h & kMask;
+        const uint32_t tg = tag_of(hh[r]);
+        uint32_t slot = (uint32_t)hh[r] & kMask;
         for (;;) {
-            const unsigned long long prev = atomicCAS(
-                reinterpret_cast<unsigned long long *>(&s_th[slot]), 0ull, (unsigned long long)h);
-            if (prev == 0ull || prev == h) {
+            const uint32_t prev = atomicCAS(&s_th[slot], 0u, tg);
+            if (prev == 0u || prev == tg) {
                 atomicMin(&s_ti[slot], (uint32_t)(lo + r));
                 break;
             }
@@ -1206,8 +1209,9 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
         const int i = lo + r;
         if (!(fl[r] & kValid)) continue;
         const uint64_t h = hh[r];
+        const uint32_t tg = tag_of(h);
         uint32_t slot = (uint32_t)h & kMask;
-        while (s_th[slot] != h) slot = (slot + 1) & kMask;
+        while (s_th[slot] != tg) slot = (slot + 1) & kMask;
         const int m = (int)s_ti[slot];
         if (m >= i) continue;
         bool dup = same_series(i, cl[r], m);
@@ -1650,7 +1654,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)chain_lds(kSpanMax, q.span_e)));
     DL_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(dl_accept_kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, kDedupSlots * 12));
+                               hipFuncAttributeMaxDynamicSharedMemorySize, kDedupSlots * 8));
     auto read_state = [&]() -> int {
         DL_HIP(hipMemcpyAsync(hs.p, st.p, sizeof(DlState), hipMemcpyDeviceToHost, stream));
         DL_HIP(hipStreamSynchronize(stream));
@@ -1693,7 +1697,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
                            q, B, att_end.p, cur, Pn, S, A_target);
         hipLaunchKernelGGL(dl_child_kernel, dim3((A_target + kChildWaves - 1) / kChildWaves),
                            dim3(kChildWaves * kWave), 0, stream, q, B, cur, Pn);
-        hipLaunchKernelGGL(dl_accept_kernel, dim3(1), dim3(kBlock), (size_t)kDedupSlots * 12,
+        hipLaunchKernelGGL(dl_accept_kernel, dim3(1), dim3(kBlock), (size_t)kDedupSlots * 8,
                            stream, q, B, (const int32_t *)att_end.p, cur, last);
         hipLaunchKernelGGL(dl_insert_kernel, dim3((A_target + kInsertWaves - 1) / kInsertWaves),
                            dim3(kInsertWaves * kWave), 0, stream, q, B, (const uint16_t *)child.p,
