@@ -527,8 +527,34 @@ __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, const uint
 //    pass with all loads issued together; then count, overlap and fitness.
 // When the size score is 0 the fitness is 0 whatever the penalty, so the
 // members are only visited for the overlap output.
+// Staging copies to LDS, kStageRound values per lane and round (each wave a
+// block of kStageRound x 64 consecutive values): a round's loads are all
+// issued before the first of them is waited on, one memory round trip per
+// round rather than one per value. A lane past the end loads and writes the
+// last value again (the same value to the same place), so that no load
+// depends on a branch.
+constexpr int kStageRound = 8;
+template <class T, class F>
+__device__ __forceinline__ void stage_round(const T *src, int n, int q0, F &put) {
+    T v[kStageRound];
+#pragma unroll
+    for (int u = 0; u < kStageRound; u++) {
+        const int q = q0 + u * kWave;
+        v[u] = gmem(src)[q < n ? q : n - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kStageRound; u++) {
+        const int q = q0 + u * kWave;
+        put(q < n ? q : n - 1, v[u]);
+    }
+}
+
+// At most 80 scalar registers: from 81 on, gfx950 holds only 7 waves per
+// SIMD (the compiler's occupancy estimate still says 8), and the item shapes
+// are sized for 8 (the compiler keeps a value or two in vector-register lanes
+// instead).
 template <int KB, int WPL, bool TWO>
-__global__ void __launch_bounds__(kMaxWaves * kWave)
+__global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_sgpr(80)))
     batch_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
                  int32_t njobs, int64_t ph1, int32_t sup_words, int32_t bits_words,
                  int32_t acol_words) {
@@ -579,46 +605,75 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
     const uint32_t rel = slot - (uint32_t)st, m = (uint32_t)(njobs - p);
     const DevJob &J = jobs[rel % m];
     const int32_t oi = (int32_t)(rd + rel / m);
-    const int32_t ind = J.order ? gmem(J.order)[oi] : oi;
-    if (ind < 0 || ind >= J.pop_size) return;  // whole workgroup: not a permutation
-    const int32_t beg = gmem(J.pop_off)[ind], end = gmem(J.pop_off)[ind + 1];
+    // the job fields the staging reads, all loaded before the first of them
+    // is used (one scalar round trip instead of one per branch that first
+    // needs a field): a job the host built never fails this check
+    const int32_t *const j_order = J.order, *const j_off = J.pop_off;
+    const uint16_t *const j_cols = J.pop_cols;
+    const int32_t j_psize = J.pop_size, j_plen = J.pop_len, j_ncols = J.cols,
+                  j_pstride = J.pstride, j_mode = J.mode, j_tie = J.tie_rule,
+                  j_apx = J.approx_permille, j_asize = J.arch_size;
+    if ((j_psize | j_plen | j_ncols | j_pstride | j_mode | j_tie | j_apx | j_asize) < 0 ||
+        !j_off || !j_cols)
+        return;
+    const int32_t ind = j_order ? gmem(j_order)[oi] : oi;
+    if (ind < 0 || ind >= j_psize) return;  // whole workgroup: not a permutation
+    const int32_t beg = gmem(j_off)[ind], end = gmem(j_off)[ind + 1];
     const int k = end - beg;
-    const bool bad0 = !(beg >= 0 && end <= J.pop_len && k >= 2 && k <= EBIC_MAX_K);
-    const int t = bad0 ? 0 : tol(k, J.approx_permille);
+    const bool bad0 = !(beg >= 0 && end <= j_plen && k >= 2 && k <= EBIC_MAX_K);
+    const int t = bad0 ? 0 : tol(k, j_apx);
     // pair table when the batch has one, it serves the tie rule and the
     // counters fit; else gather
-    const bool two = TWO && J.tie_rule != EBIC_TIE_INDEX;  // both tables
-    const bool use_pairs = J.mode == 1 && t <= PairLimit<KB, WPL>::T &&
-                           (J.tie_rule == EBIC_TIE_INDEX || (TWO && J.pairs_strict));
+    const bool two = TWO && j_tie != EBIC_TIE_INDEX;  // both tables
+    const bool use_pairs = j_mode == 1 && t <= PairLimit<KB, WPL>::T &&
+                           (j_tie == EBIC_TIE_INDEX || (TWO && J.pairs_strict));
     // one table below 4 GB: descriptors hold byte offsets into it
-    const int64_t tbytes = (int64_t)J.cols * (J.cols - 1) / 2 * J.pstride * 8;
+    const int64_t tbytes = (int64_t)j_ncols * (j_ncols - 1) / 2 * j_pstride * 8;
     const bool flat = use_pairs && !two && tbytes <= (int64_t)0xFFFFFFFF;
 
-    // 1. stage and validate the series
+    // 1. stage and validate the series. This thread's first column of the
+    // series (and the one before it) is loaded first, then the archive's
+    // offsets and columns (for the reduction), so that all of these loads
+    // are in flight together
+    const int K = j_asize;
+    const bool arch_lds = K > 0 && J.arch_len <= acol_words;
+    const int j0 = threadIdx.x;
+    int c0 = 0, a0 = 0;
+    if (!bad0 && j0 < k) {
+        c0 = gmem(j_cols)[beg + j0];
+        if (j0 > 0) a0 = gmem(j_cols)[beg + j0 - 1];
+    }
+    if (arch_lds && !bad0) {
+        // the offsets (K + 1 <= 2 x 64 values, two per thread) and the first
+        // round of columns, loaded together; then any further rounds
+        const int32_t *const aoff = J.arch_off;
+        const uint16_t *const acols = J.arch_cols;
+        const int j_alen = J.arch_len;
+        const int bd = blockDim.x;
+        const int qa = (int)threadIdx.x < K ? (int)threadIdx.x : K;
+        const int qb = (int)threadIdx.x + bd < K ? (int)threadIdx.x + bd : K;
+        const int32_t oa = gmem(aoff)[qa], ob = gmem(aoff)[qb];
+        auto put_col = [&](int q, uint16_t c) { s_acols[q] = c; };
+        const int q0 = (int)(threadIdx.x / kWave) * (kStageRound * kWave) + (int)(threadIdx.x % kWave);
+        if (j_alen > 0) stage_round(acols, j_alen, q0, put_col);
+        s_aoff[qa] = oa < 0 ? 0 : (oa > j_alen ? j_alen : oa);
+        s_aoff[qb] = ob < 0 ? 0 : (ob > j_alen ? j_alen : ob);
+        for (int q = q0 + kStageRound * bd; q < j_alen; q += kStageRound * bd)
+            stage_round(acols, j_alen, q, put_col);
+    }
     if (threadIdx.x == 0) {
         s_bad = bad0;
         s_done = 0;
         s_n = 0;
     }
     if (!bad0)
-        for (int q = threadIdx.x; q < (J.cols + 31) / 32; q += blockDim.x) s_bits[q] = 0;
+        for (int q = threadIdx.x; q < (j_ncols + 31) / 32; q += blockDim.x) s_bits[q] = 0;
     __syncthreads();
-    // the archive's offsets and columns, for the reduction (independent loads
-    // in flight with the series')
-    const int K = J.arch_size;
-    const bool arch_lds = K > 0 && J.arch_len <= acol_words;
-    if (arch_lds && !bad0) {
-        for (int q = threadIdx.x; q <= K; q += blockDim.x) {
-            const int32_t o = gmem(J.arch_off)[q];
-            s_aoff[q] = o < 0 ? 0 : (o > J.arch_len ? J.arch_len : o);
-        }
-        for (int q = threadIdx.x; q < J.arch_len; q += blockDim.x) s_acols[q] = gmem(J.arch_cols)[q];
-    }
     if (!bad0) {
         int lbad = 0;
         for (int j = threadIdx.x; j < k; j += blockDim.x) {
-            const int c = gmem(J.pop_cols)[beg + j];
-            if (c >= J.cols) {
+            const int c = j == j0 ? c0 : gmem(j_cols)[beg + j];
+            if (c >= j_ncols) {
                 lbad = 1;
             } else {
                 const uint32_t bit = 1u << (c % 32);
@@ -626,11 +681,11 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
             }
             if (use_pairs) {
                 if (j > 0) {
-                    const int a = gmem(J.pop_cols)[beg + j - 1];
+                    const int a = j == j0 ? a0 : gmem(j_cols)[beg + j - 1];
                     const int lo = a < c ? a : c, hi = a < c ? c : a;
-                    if (hi < J.cols) {
-                        const int64_t pi = pair_index(lo, hi, J.cols);
-                        s_pd[j] = flat ? (int32_t)((uint32_t)(pi * J.pstride * 8) | (a > c ? 1u : 0u))
+                    if (hi < j_ncols) {
+                        const int64_t pi = pair_index(lo, hi, j_ncols);
+                        s_pd[j] = flat ? (int32_t)((uint32_t)(pi * j_pstride * 8) | (a > c ? 1u : 0u))
                                        : (int32_t)pi | (a > c ? (int32_t)0x80000000 : 0);
                     }
                 }
@@ -639,6 +694,15 @@ __global__ void __launch_bounds__(kMaxWaves * kWave)
             }
         }
         if (lbad) s_bad = 1;
+    }
+    {
+        // the fields the waves read first after the barrier, loaded before it
+        // (together, while the other waves finish staging)
+        const int32_t w64 = J.w64, ipi = J.ipi, cpi = J.cpi, nch = J.nchunks,
+                      neg = J.negative_trends;
+        const uint64_t *const pairs = J.pairs;
+        uint64_t *const sup = J.support;
+        asm volatile("" ::"s"(w64), "s"(ipi), "s"(cpi), "s"(nch), "s"(neg), "s"(pairs), "s"(sup));
     }
     __syncthreads();
     const bool bad = s_bad != 0;
