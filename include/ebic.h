@@ -240,8 +240,8 @@ typedef struct ebic_job {
 typedef struct ebic_batch ebic_batch;
 
 /* Batched evaluation (Sec. 2.4, steps 2-3 and 7, for several populations
- * at once): every individual of every job in one kernel launch (a
- * workgroup per individual, counting and reducing it), each job with its own
+ * at once): every individual of every job in one kernel launch (its own
+ * waves of a workgroup count and reduce each individual), each job with its own
  * matrix (pair-table form when the matrix has a table, else the gather
  * form), archive and parameters. Results are identical, bit for bit, to
  * ebic_evaluate on each job alone. create copies the job table to the

@@ -18,10 +18,10 @@ FLAGS = [
     # no packed-FP32 instructions; no FMA contraction (every FP result is an
     # exact ldexp of an integer)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-ffp-contract=off",
-    # the first 11 argument dwords arrive in scalar registers at wave start
+    # the first 14 argument dwords arrive in scalar registers at wave start
     # (the batched kernel's explicit arguments), not by a load from the
     # argument segment
-    "-mllvm", "-amdgpu-kernarg-preload-count=11",
+    "-mllvm", "-amdgpu-kernarg-preload-count=14",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 

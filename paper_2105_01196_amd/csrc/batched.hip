@@ -69,6 +69,16 @@ constexpr int kHWords = 3;        // support words per lane and pass when counti
 constexpr int kArchLdsCols = 8192;  // largest archive whose columns are copied to LDS (16 KB)
 constexpr int kSchedBatch = 4;   // schedule phases loaded together
 constexpr int kSupLdsWords = 2048;  // longest support kept in LDS for the reduction (16 KB)
+// Individuals per workgroup: as many as keep the workgroup at kGroupWaves
+// waves or fewer (at most kMaxIpw) and its LDS at kGroupLds bytes or fewer.
+// A workgroup's individuals are slots a grid apart (g, g + G, ...): on the
+// 10,000-row workload (two waves per individual) pairing slot g with slot
+// g + 2,048 took a launch from 22.5 to 20.5 us, while pairing neighbours
+// (g, g + 1) made it 0.4 us slower and pairing g with the mirror slot 2G-1-g
+// 1.7 us slower; workgroups of eight waves were slower still.
+constexpr int kGroupWaves = 4;
+constexpr int kMaxIpw = 4;  // 1, 2 or 4 (ceil(total / ipw) by shifts in the kernel)
+constexpr size_t kGroupLds = 65536;
 
 // Segment of a flat index (a job's individuals, a phase of the item
 // schedule): count the segment starts after the first at or below it. The
@@ -505,12 +515,13 @@ __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, const uint
                                                              w, fit);
 }
 
-// One workgroup per individual, one wave per item (a few 4096-row chunks of
-// the individual's rows); the last wave of the workgroup to finish reduces
-// the individual. Workgroups follow a round-robin schedule over the jobs'
-// individuals (phase p interleaves the first njobs - p jobs of the job table,
-// which is sorted by population size, descending), so each job's
-// longest-first processing order holds across the batch.
+// One or more individuals per workgroup (ipw, each with its own waves and
+// LDS), one wave per item (a few 4096-row chunks of the individual's rows);
+// the last of an individual's waves to finish reduces it. Slots follow a
+// round-robin schedule over the jobs' individuals (phase p interleaves the
+// first njobs - p jobs of the job table, which is sorted by population size,
+// descending), so each job's longest-first processing order holds across the
+// batch.
 //
 // 1. All threads stage the series in LDS (one pair descriptor per step, or
 //    each column's byte offset for the gather form) and mark its columns in
@@ -527,6 +538,17 @@ __device__ __forceinline__ void pairs_dispatch(const uint64_t *pairs, const uint
 //    pass with all loads issued together; then count, overlap and fitness.
 // When the size score is 0 the fitness is 0 whatever the penalty, so the
 // members are only visited for the overlap output.
+// LDS bytes of one individual (the workgroup holds ipw of these, each at a
+// 16-byte boundary): support, step descriptors, column bitmap, archive
+// offsets, archive columns, 8 bytes of alignment slack, their hit masks.
+__host__ __device__ constexpr size_t lds_ind_bytes(int32_t sup_words, int32_t bits_words,
+                                                   int32_t acol_words) {
+    return ((size_t)sup_words * 8 + (size_t)EBIC_MAX_K * 4 + (size_t)bits_words * 4 +
+            (size_t)(EBIC_MAX_ARCHIVE + 1) * 4 + (size_t)acol_words * 2 + 8 +
+            (size_t)(acol_words + kWave - 1) / kWave * 8 + 15) /
+           16 * 16;
+}
+
 // Staging copies to LDS, kStageRound values per lane and round (each wave a
 // block of kStageRound x 64 consecutive values): a round's loads are all
 // issued before the first of them is waited on, one memory round trip per
@@ -557,11 +579,23 @@ template <int KB, int WPL, bool TWO>
 __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_sgpr(80)))
     batch_kernel(const DevJob *__restrict__ jobs, const int64_t *__restrict__ sched,
                  int32_t njobs, int64_t ph1, int32_t sup_words, int32_t bits_words,
-                 int32_t acol_words) {
+                 int32_t acol_words, int32_t ipw, int32_t wpi, int32_t total) {
+    // ipw individuals per workgroup (slots a grid apart), each with its own
+    // wpi waves and its own part of the LDS. The wave's index is made
+    // uniform (a scalar), and so is everything derived from it; its
+    // individual is found by subtraction (ipw <= kMaxIpw), not a division
+    const int gw = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    int sub = 0;
+    for (int r = gw - wpi; r >= 0 && sub < kMaxIpw - 1; r -= wpi) sub++;
+    const int wave = gw - sub * wpi, lane = threadIdx.x % kWave;
+    const int nwaves = wpi;
+    const int bdim = wpi * kWave;                    // threads per individual
+    const int tid = (int)threadIdx.x - sub * bdim;   // thread among them
     // dynamic LDS: the support words (sup_words, 0 when they stay in global
     // memory only), the series' step descriptors, the column bitmap, the
     // archive's offsets and columns (acol_words, 0 when they stay global)
-    extern __shared__ uint64_t s_dyn[];
+    extern __shared__ uint64_t s_lds[];
+    uint64_t *const s_dyn = s_lds + (size_t)sub * (lds_ind_bytes(sup_words, bits_words, acol_words) / 8);
     uint64_t *s_sup = s_dyn;
     int32_t *s_pd = reinterpret_cast<int32_t *>(s_dyn + sup_words);
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(s_pd + EBIC_MAX_K);
@@ -573,11 +607,17 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
     uint64_t *s_ahit =
         s_dyn + ((size_t)sup_words * 8 + EBIC_MAX_K * 4 + (size_t)bits_words * 4 +
                  (EBIC_MAX_ARCHIVE + 1) * 4 + (size_t)acol_words * 2 + 7) / 8;
-    __shared__ int32_t s_bad, s_done, s_n;
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int nwaves = blockDim.x / kWave;
-    // the grid has exactly total_ind workgroups
-    const uint32_t slot = blockIdx.x;
+    __shared__ int32_t s_bad_i[kMaxIpw], s_done_i[kMaxIpw], s_n_i[kMaxIpw];
+    int32_t &s_bad = s_bad_i[sub], &s_done = s_done_i[sub], &s_n = s_n_i[sub];
+    // the workgroup's individuals are slots a grid apart (g, g + G, ...), so
+    // that the longest individuals, first in slot order, spread over the
+    // grid rather than pairing up. Slots past the last (total) stay idle:
+    // they pass the workgroup's barriers, then end; their loads below read
+    // the last slot's
+    const int32_t G = ipw == 1 ? total : ipw == 2 ? (total + 1) >> 1 : (total + 3) >> 2;  // ceil(total / ipw)
+    const int64_t slot0 = (int64_t)blockIdx.x + (int64_t)sub * G;
+    bool idle = slot0 >= total;
+    const uint32_t slot = idle ? (uint32_t)(total - 1) : (uint32_t)slot0;
     // phase of this slot: the last phase start at or below it. Phase 0
     // (every job, from round 0) ends at ph1, a kernel argument, so its slots
     // (all of them when the jobs have equal populations) load nothing; past
@@ -612,15 +652,21 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
     const uint16_t *const j_cols = J.pop_cols;
     const int32_t j_psize = J.pop_size, j_plen = J.pop_len, j_ncols = J.cols,
                   j_pstride = J.pstride, j_mode = J.mode, j_tie = J.tie_rule,
-                  j_apx = J.approx_permille, j_asize = J.arch_size;
-    if ((j_psize | j_plen | j_ncols | j_pstride | j_mode | j_tie | j_apx | j_asize) < 0 ||
-        !j_off || !j_cols)
-        return;
-    const int32_t ind = j_order ? gmem(j_order)[oi] : oi;
-    if (ind < 0 || ind >= j_psize) return;  // whole workgroup: not a permutation
-    const int32_t beg = gmem(j_off)[ind], end = gmem(j_off)[ind + 1];
+                  j_apx = J.approx_permille, j_asize = J.arch_size, j_alen = J.arch_len;
+    if ((j_psize | j_plen | j_ncols | j_pstride | j_mode | j_tie | j_apx | j_asize | j_alen) < 0 ||
+        !j_off || !j_cols || ((uintptr_t)j_order & 3u))
+        idle = true;
+    int32_t ind = 0, beg = 0, end = 0;
+    if (!idle) {
+        ind = j_order ? gmem(j_order)[oi] : oi;
+        if (ind < 0 || ind >= j_psize) idle = true;  // not a permutation: no output
+    }
+    if (!idle) {
+        beg = gmem(j_off)[ind];
+        end = gmem(j_off)[ind + 1];
+    }
     const int k = end - beg;
-    const bool bad0 = !(beg >= 0 && end <= j_plen && k >= 2 && k <= EBIC_MAX_K);
+    const bool bad0 = idle || !(beg >= 0 && end <= j_plen && k >= 2 && k <= EBIC_MAX_K);
     const int t = bad0 ? 0 : tol(k, j_apx);
     // pair table when the batch has one, it serves the tie rule and the
     // counters fit; else gather
@@ -636,8 +682,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
     // offsets and columns (for the reduction), so that all of these loads
     // are in flight together
     const int K = j_asize;
-    const bool arch_lds = K > 0 && J.arch_len <= acol_words;
-    const int j0 = threadIdx.x;
+    const bool arch_lds = K > 0 && j_alen <= acol_words;
+    const int j0 = tid;
     int c0 = 0, a0 = 0;
     if (!bad0 && j0 < k) {
         c0 = gmem(j_cols)[beg + j0];
@@ -648,30 +694,29 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
         // round of columns, loaded together; then any further rounds
         const int32_t *const aoff = J.arch_off;
         const uint16_t *const acols = J.arch_cols;
-        const int j_alen = J.arch_len;
-        const int bd = blockDim.x;
-        const int qa = (int)threadIdx.x < K ? (int)threadIdx.x : K;
-        const int qb = (int)threadIdx.x + bd < K ? (int)threadIdx.x + bd : K;
+        const int bd = bdim;
+        const int qa = tid < K ? tid : K;
+        const int qb = tid + bd < K ? tid + bd : K;
         const int32_t oa = gmem(aoff)[qa], ob = gmem(aoff)[qb];
         auto put_col = [&](int q, uint16_t c) { s_acols[q] = c; };
-        const int q0 = (int)(threadIdx.x / kWave) * (kStageRound * kWave) + (int)(threadIdx.x % kWave);
+        const int q0 = wave * (kStageRound * kWave) + lane;
         if (j_alen > 0) stage_round(acols, j_alen, q0, put_col);
         s_aoff[qa] = oa < 0 ? 0 : (oa > j_alen ? j_alen : oa);
         s_aoff[qb] = ob < 0 ? 0 : (ob > j_alen ? j_alen : ob);
         for (int q = q0 + kStageRound * bd; q < j_alen; q += kStageRound * bd)
             stage_round(acols, j_alen, q, put_col);
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         s_bad = bad0;
         s_done = 0;
         s_n = 0;
     }
     if (!bad0)
-        for (int q = threadIdx.x; q < (j_ncols + 31) / 32; q += blockDim.x) s_bits[q] = 0;
+        for (int q = tid; q < (j_ncols + 31) / 32; q += bdim) s_bits[q] = 0;
     __syncthreads();
     if (!bad0) {
         int lbad = 0;
-        for (int j = threadIdx.x; j < k; j += blockDim.x) {
+        for (int j = tid; j < k; j += bdim) {
             const int c = j == j0 ? c0 : gmem(j_cols)[beg + j];
             if (c >= j_ncols) {
                 lbad = 1;
@@ -705,6 +750,7 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
         asm volatile("" ::"s"(w64), "s"(ipi), "s"(cpi), "s"(nch), "s"(neg), "s"(pairs), "s"(sup));
     }
     __syncthreads();
+    if (idle) return;  // after the workgroup's last barrier
     const bool bad = s_bad != 0;
     const bool sup_lds = J.w64 <= sup_words;
 
@@ -931,10 +977,12 @@ struct Batch {
     int64_t total_ind = 0;
     int64_t ph1 = 0;           // first slot past phase 0 (kernel argument, kept alive for a graph)
     int32_t njobs = 0;
-    int waves = 1;             // waves per workgroup: the largest items per individual
-    int32_t sup_words = 0;     // LDS support words per workgroup (0: global only)
-    int32_t bits_words = 1;    // LDS column-bitmap words per workgroup
-    int32_t acol_words = 0;    // LDS archive columns per workgroup (0: global only)
+    int waves = 1;             // waves per individual: the largest items per individual
+    int32_t ipw = 1;           // individuals per workgroup
+    int32_t total32 = 0;       // total_ind as a kernel argument
+    int32_t sup_words = 0;     // LDS support words per individual (0: global only)
+    int32_t bits_words = 1;    // LDS column-bitmap words per individual
+    int32_t acol_words = 0;    // LDS archive columns per individual (0: global only)
     int kb = 2;                // pair-bitmap loads in flight (template)
     int wpl = 1;               // 64-row words per lane (template)
     int cpi = 1;               // chunk groups (of wpl chunks) per item
@@ -1012,11 +1060,12 @@ DevJob make_devjob(const ebic_job &j, int32_t flags) {
 // partition and the grid.
 struct Layout {
     bool two = false;        // some job reads both pair tables
-    int waves = 1;           // waves per workgroup: the largest items per individual
-    int32_t sup_words = 0;   // LDS support words per workgroup (0: global only)
-    int32_t bits_words = 1;  // LDS column-bitmap words per workgroup
-    int32_t acol_words = 0;  // LDS archive columns per workgroup (0: global only)
-    int64_t total_ind = 0;   // workgroups
+    int waves = 1;           // waves per individual: the largest items per individual
+    int32_t ipw = 1;         // individuals per workgroup
+    int32_t sup_words = 0;   // LDS support words per individual (0: global only)
+    int32_t bits_words = 1;  // LDS column-bitmap words per individual
+    int32_t acol_words = 0;  // LDS archive columns per individual (0: global only)
+    int64_t total_ind = 0;   // individuals (slots)
     int64_t ph1 = 0;         // first slot past phase 0
 };
 
@@ -1076,6 +1125,10 @@ Layout lay_out(DevJob *jobs, int32_t n, int cpi, int wpl, int *perm, char *h) {
     L.sup_words = wmax <= kSupLdsWords ? wmax : 0;
     L.bits_words = (cmax + 31) / 32;
     L.acol_words = amax <= kArchLdsCols ? amax : 0;
+    const size_t ind_lds = lds_ind_bytes(L.sup_words, L.bits_words, L.acol_words);
+    while (L.ipw * 2 <= kMaxIpw && L.ipw * 2 * L.waves <= kGroupWaves &&
+           (size_t)L.ipw * 2 * ind_lds <= kGroupLds)
+        L.ipw *= 2;
     // Individuals of all jobs are interleaved round-robin, so that each
     // job's longest-first order holds across the batch: with the jobs stored
     // by population size, descending, phase p takes one individual of each
@@ -1113,6 +1166,7 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
     b->cpi = cpi;
     const int32_t n = b->njobs;
     const size_t bytes = table_bytes(n);
+    const bool moved = n > b->cap_jobs;  // a new device table
     if (n > b->cap_jobs) {
         if (b->d_jobs) device_release(b->al, b->d_jobs, b->al_stream);
         if (b->h_stage) (void)hipHostFree(b->h_stage);
@@ -1128,7 +1182,11 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
     b->perm.resize(n);
     const Layout L =
         lay_out(b->jobs.data(), n, cpi, b->wpl, b->perm.data(), static_cast<char *>(b->h_stage));
-    if (L.two != b->two) {  // another kernel: a graph of the old one is rebuilt on the next run
+    if (moved || L.two != b->two || L.waves != b->waves || L.ipw != b->ipw ||
+        L.total_ind != b->total_ind || L.ph1 != b->ph1 || L.sup_words != b->sup_words ||
+        L.bits_words != b->bits_words || L.acol_words != b->acol_words) {
+        // another kernel, grid or argument: a graph of the old launch is
+        // rebuilt on the next run
         if (b->exec) (void)hipGraphExecDestroy(b->exec);
         if (b->graph) (void)hipGraphDestroy(b->graph);
         b->exec = nullptr;
@@ -1136,10 +1194,12 @@ int upload_table(Batch *b, int cpi, hipStream_t stream) {
         b->two = L.two;
     }
     b->waves = L.waves;
+    b->ipw = L.ipw;
     b->sup_words = L.sup_words;
     b->bits_words = L.bits_words;
     b->acol_words = L.acol_words;
     b->total_ind = L.total_ind;
+    b->total32 = (int32_t)(L.total_ind < INT32_MAX ? L.total_ind : INT32_MAX);
     b->ph1 = L.ph1;
     b->d_sched = reinterpret_cast<int64_t *>(reinterpret_cast<char *>(b->d_jobs) +
                                              sizeof(DevJob) * n);
@@ -1162,20 +1222,20 @@ void *kernel_fn(const Batch *b, int kb, int wpl) {
     return b->two ? kernel_fn<true>(kb, wpl) : kernel_fn<false>(kb, wpl);
 }
 
-size_t lds_bytes(int32_t sup_words, int32_t bits_words, int32_t acol_words) {
-    // support, step descriptors, column bitmap, archive offsets, archive
-    // columns, 8 bytes of alignment slack, their hit masks
-    return (size_t)sup_words * 8 + (size_t)EBIC_MAX_K * 4 + (size_t)bits_words * 4 +
-           (size_t)(EBIC_MAX_ARCHIVE + 1) * 4 + (size_t)acol_words * 2 + 8 +
-           (size_t)(acol_words + kWave - 1) / kWave * 8;
+size_t lds_bytes(int32_t ipw, int32_t sup_words, int32_t bits_words, int32_t acol_words) {
+    return (size_t)ipw * lds_ind_bytes(sup_words, bits_words, acol_words);
 }
-size_t lds_bytes(const Batch *b) { return lds_bytes(b->sup_words, b->bits_words, b->acol_words); }
+size_t lds_bytes(const Batch *b) {
+    return lds_bytes(b->ipw, b->sup_words, b->bits_words, b->acol_words);
+}
+// workgroups: ipw slots each (g, g + G, ...)
+unsigned groups(int64_t total_ind, int32_t ipw) { return (unsigned)((total_ind + ipw - 1) / ipw); }
 
 int launch_batch(Batch *b, hipStream_t stream) {
-    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->ph1, &b->sup_words,
-                    &b->bits_words, &b->acol_words};
-    EBIC_HIP(hipLaunchKernel(kernel_fn(b, b->kb, b->wpl), dim3((unsigned)b->total_ind),
-                             dim3(b->waves * kWave), args, lds_bytes(b), stream));
+    void *args[] = {&b->d_jobs,     &b->d_sched, &b->njobs, &b->ph1,    &b->sup_words,
+                    &b->bits_words, &b->acol_words, &b->ipw, &b->waves, &b->total32};
+    EBIC_HIP(hipLaunchKernel(kernel_fn(b, b->kb, b->wpl), dim3(groups(b->total_ind, b->ipw)),
+                             dim3(b->ipw * b->waves * kWave), args, lds_bytes(b), stream));
     return EBIC_OK;
 }
 
@@ -1186,12 +1246,12 @@ int build_graph(Batch *b) {
     b->graph = nullptr;
     // one kernel node (no stream capture)
     hipGraphNode_t node = nullptr;
-    void *args[] = {&b->d_jobs, &b->d_sched, &b->njobs, &b->ph1, &b->sup_words,
-                    &b->bits_words, &b->acol_words};
+    void *args[] = {&b->d_jobs,     &b->d_sched, &b->njobs, &b->ph1,    &b->sup_words,
+                    &b->bits_words, &b->acol_words, &b->ipw, &b->waves, &b->total32};
     hipKernelNodeParams pk{};
     pk.func = kernel_fn(b, b->kb, b->wpl);
-    pk.gridDim = dim3((unsigned)b->total_ind);
-    pk.blockDim = dim3(b->waves * kWave);
+    pk.gridDim = dim3(groups(b->total_ind, b->ipw));
+    pk.blockDim = dim3(b->ipw * b->waves * kWave);
     pk.sharedMemBytes = (unsigned)lds_bytes(b);
     pk.kernelParams = args;
     hipError_t e = hipGraphCreate(&b->graph, 0);
@@ -1375,6 +1435,12 @@ int batch_set(Batch **bp, const ebic_job *jobs, int32_t njobs, hipStream_t strea
     }
     b->jobs.clear();
     for (int i = 0; i < njobs; i++) b->jobs.push_back(make_devjob(jobs[i], 0));
+    // new jobs: a graph of the old launch (its job count among the
+    // arguments) is rebuilt on the next run
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
     b->njobs = njobs;
     return upload_table(b, b->cpi, stream);
 }
@@ -1424,6 +1490,8 @@ int batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, Batch **out
 int batch_run(Batch *b, hipStream_t stream) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (b->total_ind == 0) return EBIC_OK;
+    if (b->total_ind > INT32_MAX)
+        return fail(EBIC_ERR_INVALID_ARG, "%lld individuals in one launch", (long long)b->total_ind);
     if ((b->flags & EBIC_BATCH_TUNE) && !b->tuned) {
         int rc = tune(b, stream);
         if (rc) return rc;
@@ -1597,11 +1665,14 @@ int batch_run_noalloc(const ebic_job *jobs, int32_t njobs, hipStream_t stream) {
     int64_t *d_sched = reinterpret_cast<int64_t *>(static_cast<char *>(base) +
                                                    sizeof(DevJob) * njobs);
     int32_t n = njobs;
-    void *args[] = {&d_jobs, &d_sched, &n, &L.ph1, &L.sup_words, &L.bits_words,
-                    &L.acol_words};
+    int32_t total = (int32_t)L.total_ind;
+    int32_t ipw = L.ipw, wpi = L.waves;
+    void *args[] = {&d_jobs,       &d_sched,      &n,   &L.ph1, &L.sup_words,
+                    &L.bits_words, &L.acol_words, &ipw, &wpi,   &total};
     void *fn = L.two ? kernel_fn<true>(kb, wpl) : kernel_fn<false>(kb, wpl);
-    EBIC_HIP(hipLaunchKernel(fn, dim3((unsigned)L.total_ind), dim3(L.waves * kWave), args,
-                             lds_bytes(L.sup_words, L.bits_words, L.acol_words), stream));
+    EBIC_HIP(hipLaunchKernel(fn, dim3(groups(L.total_ind, L.ipw)),
+                             dim3(L.ipw * L.waves * kWave), args,
+                             lds_bytes(L.ipw, L.sup_words, L.bits_words, L.acol_words), stream));
     // the next call may rewrite the array only after this launch has read it
     EBIC_HIP(hipStreamSynchronize(stream));
     return EBIC_OK;

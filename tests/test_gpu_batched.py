@@ -445,6 +445,46 @@ def test_mixed_row_counts_widen_items(E, shape):
     b.close()
 
 
+@pytest.mark.parametrize("R,shape", [(1000, (1, 2, 1)), (6000, (1, 2, 1)), (6000, (2, 4, 1)),
+                                     (12000, (1, 4, 1)), (1000, (1, 2, 2))])
+def test_several_individuals_per_workgroup(E, R, shape):
+    """Rows of one or two 4,096-row chunks put four or two individuals in a
+    workgroup (consecutive slots, each with its own waves and LDS, barriers
+    shared), three chunks one; populations of 1-13 individuals leave the last
+    workgroup partly idle, and two jobs share each launch, so a workgroup
+    can hold individuals of both. Every job equals the oracle, archives and
+    processing orders included."""
+    case = synth.planted_matrix(R, 30, background="lognormal", n_planted=2,
+                                rows_range=(20, 200), cols_range=(4, 12), sigma=0.1,
+                                seed=77 + R)
+    m = _matrix(E, case.X, pairs=True)
+    for n, (P1, P2) in enumerate([(1, 2), (3, 5), (6, 1), (13, 7)]):
+        jobs, data = [], []
+        for j, P in enumerate((P1, P2)):
+            seqs = synth.population(case.C, P, 2, 20, seed=synth.POP_SEED + 900 + 10 * n + j,
+                                    truth=case.truth, planted_frac=0.3)
+            kw = _kw(approx_permille=(850, 700)[j], negative_trends=j)
+            pop = E.ebic_population_upload(seqs, case.C)
+            E.set_order(pop, E.longest_first(seqs))
+            arch = oarch = None
+            if j == 0:
+                ev = oracle.evaluate(case.X, seqs, params=oracle.make_params(**kw), nthreads=NCPU)
+                top = [int(i) for i in np.argsort(-ev.score, kind="stable")[:min(4, P)]]
+                series = [seqs[i] for i in top]
+                arch = E.make_archive(E.flags_to_support(ev.support[top], m.words), series)
+                oarch = oracle.Archive(ev.support[top], series)
+            jobs.append(E.make_job(m, pop, arch, E.make_params(**kw)))
+            data.append((seqs, kw, oarch))
+        b = E.Batch(jobs, graph=n % 2 == 1)  # every other batch replays a graph
+        b.set_tuning(*shape)
+        for _ in range(2):
+            b.run()
+            torch.cuda.synchronize()
+            for job, (seqs, kw, oarch) in zip(jobs, data):
+                _check_job(E, job, case.X, seqs, kw, oarch)
+        b.close()
+
+
 def test_graph_replays_track_new_contents(E):
     """A graph-backed batch replayed over populations rewritten in place
     (same lengths, new columns): every replay equals the oracle."""
