@@ -261,8 +261,11 @@ int ebic_batch_create(const ebic_job *jobs, int32_t njobs, int32_t flags, ebic_b
  * shape on the batch's own inputs, waits for the timings (that run is
  * synchronous), keeps the fastest, and caches the choice per batch shape in
  * the process and, when the environment variable EBIC_TUNE_CACHE names a
- * file, in that JSON file. ebic_batch_tuning reports the shape in use; any
- * output pointer may be NULL. */
+ * file, in that JSON file. Before tuning or pinning, a batch takes four
+ * loads in flight, one word per lane and, per job, one chunk group per item
+ * up to two chunks, two up to four, else four; ebic_batch_tuning reports that
+ * default as chunks_per_item 0. ebic_batch_tuning reports the shape in use;
+ * any output pointer may be NULL. */
 int ebic_batch_tuning(ebic_batch *b, int32_t *chunks_per_item, int32_t *loads_in_flight,
                       int32_t *words_per_lane);
 /* Pins the item shape, e.g. one reported by ebic_batch_tuning in an earlier

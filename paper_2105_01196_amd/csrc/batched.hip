@@ -983,7 +983,7 @@ struct Batch {
     int32_t sup_words = 0;     // LDS support words per individual (0: global only)
     int32_t bits_words = 1;    // LDS column-bitmap words per individual
     int32_t acol_words = 0;    // LDS archive columns per individual (0: global only)
-    int kb = 2;                // pair-bitmap loads in flight (template)
+    int kb = 4;                // pair-bitmap loads in flight (template)
     int wpl = 1;               // 64-row words per lane (template)
     int cpi = 1;               // chunk groups (of wpl chunks) per item
     bool tuned = false;
@@ -997,8 +997,11 @@ struct Batch {
 namespace {
 
 // Chunk groups per item before any tuning (ebic_batch_set_tuning or
-// EBIC_BATCH_TUNE change it).
-constexpr int kDefaultCpi = 1;
+// EBIC_BATCH_TUNE change it): 0 = chosen per job, one chunk per item up to
+// two chunks, two up to four, else four (with one word per lane), so that a
+// 10,000-row individual takes two waves and shares its workgroup with
+// another; the shapes the tuner picks for 10,000 and 40,000 rows.
+constexpr int kDefaultCpi = 0;
 
 int check_job(const ebic_job *j, int idx) {
     const ebic_matrix *m = &j->matrix;
@@ -1076,11 +1079,11 @@ size_t table_bytes(int32_t n) { return table_bytes_max(n); }
 // Size of the array behind the allocation-free batched evaluation.
 constexpr size_t kNoAllocScratchBytes = 16384;
 
-// Lay the items out for `cpi` groups of `wpl` chunks per item (more when an
-// individual would need more than kMaxWaves items) and write the job table
-// (jobs by population size, descending) and the schedule (phase starts,
-// phase rounds) to h, table_bytes(n) bytes. `perm` is scratch for n ints.
-// Allocates nothing.
+// Lay the items out for `cpi` groups of `wpl` chunks per item (0: chosen per
+// job, as for kDefaultCpi; more when an individual would need more than
+// kMaxWaves items) and write the job table (jobs by population size,
+// descending) and the schedule (phase starts, phase rounds) to h,
+// table_bytes(n) bytes. `perm` is scratch for n ints. Allocates nothing.
 Layout lay_out(DevJob *jobs, int32_t n, int cpi, int wpl, int *perm, char *h) {
     Layout L;
     for (int32_t i = 0; i < n; i++) {
@@ -1095,7 +1098,7 @@ Layout lay_out(DevJob *jobs, int32_t n, int cpi, int wpl, int *perm, char *h) {
     // kMixedWaves per individual.
     auto items = [&](DevJob &d, int32_t waves_max) {
         // whole groups per item, so that no two items share a group
-        int32_t cpc = cpi * wpl;
+        int32_t cpc = cpi > 0 ? cpi * wpl : d.nchunks <= 2 ? 1 : d.nchunks <= 4 ? 2 : 4;
         const int32_t need = (d.nchunks + waves_max - 1) / waves_max;
         if (cpc < need) cpc = (need + wpl - 1) / wpl * wpl;
         d.cpi = cpc < d.nchunks ? cpc : d.nchunks;
@@ -1649,7 +1652,7 @@ int batch_run_noalloc(const ebic_job *jobs, int32_t njobs, hipStream_t stream) {
     int perm[EBIC_NOALLOC_MAX_JOBS];
     alignas(16) char h[table_bytes_max(EBIC_NOALLOC_MAX_JOBS)];
     for (int i = 0; i < njobs; i++) dj[i] = make_devjob(jobs[i], 0);
-    constexpr int kb = 2, wpl = 1;  // the shape ebic_evaluate_batched runs untuned
+    constexpr int kb = 4, wpl = 1;  // the shape ebic_evaluate_batched runs untuned
     Layout L = lay_out(dj, njobs, kDefaultCpi, wpl, perm, h);
     if (L.total_ind == 0) return EBIC_OK;
     if (L.total_ind > INT32_MAX)

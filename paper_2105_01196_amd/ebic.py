@@ -497,7 +497,8 @@ class Batch:
         _check(lib().ebic_batch_run(self.handle, _stream(stream)))
 
     def tuning(self):
-        """(chunk groups per item, loads in flight, words per lane) in use."""
+        """(chunk groups per item, loads in flight, words per lane) in use;
+        chunk groups 0 = the untuned default, chosen per job."""
         a, b, c = _i32(), _i32(), _i32()
         _check(lib().ebic_batch_tuning(self.handle, ctypes.byref(a), ctypes.byref(b),
                                        ctypes.byref(c)))
