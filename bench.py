@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--populations", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain-path leg")
+    ap.add_argument("--legs", action="store_true",
+                    help="also time the same step as a graph replay and in the gather form")
     ap.add_argument("--overlap", action="store_true",
                     help="also write each individual's per-member overlap counts (the "
                          "penalty itself never needs this output)")
@@ -218,6 +220,33 @@ def main():
         plain = {"value": P / (ms_plain / 1e3), "ms_per_step": ms_plain,
                  "launches_per_step": npop, "bit_exact_vs_batched": bool(same)}
 
+    legs = None
+    if args.legs:
+        # the same step replayed from a HIP graph (same item shape), and in
+        # the gather form (no pair table); both write the same outputs
+        ref = [(j.out.count.clone(), j.out.fitness.clone(), j.out.support.clone()) for j in jobs]
+        legs = {}
+        for name, kw in (("graph", {"graph": True}), ("gather", {"gather": True})):
+            b2 = E.Batch(jobs, **kw)
+            if name == "graph":
+                b2.set_tuning(cpi, kb, wpl)
+            for _ in range(args.warmup):
+                b2.run(stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for _ in range(args.steps):
+                b2.run(stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            same = all(torch.equal(r[0], j.out.count) and torch.equal(r[1], j.out.fitness)
+                       and torch.equal(r[2], j.out.support) for r, j in zip(ref, jobs))
+            legs[name] = {"ms_per_step": e0.elapsed_time(e1) / args.steps,
+                          "tuning": list(b2.tuning()), "bit_exact_vs_batched": bool(same)}
+            b2.close()
+        legs["direct_ms_per_step"] = kern
+
     value = P / (ms_batched / 1e3)
     # Algorithmic bytes of the kernel: per individual, one R-bit pair bitmap
     # per step ((k-1) R/8), its CSR entry (4 + 2k), its support bitmap
@@ -249,6 +278,7 @@ def main():
         "pair_table": {"bytes": int(m.pairs.numel() * 8), "build_ms": table_ms},
         "plain": plain,
         "speedup_vs_plain": (plain["ms_per_step"] / ms_batched) if plain else None,
+        "legs": legs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "achieved_kind": "effective: algorithmic bytes over kernel time, every "
