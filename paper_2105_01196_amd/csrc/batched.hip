@@ -595,7 +595,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
     // memory only), the series' step descriptors, the column bitmap, the
     // archive's offsets and columns (acol_words, 0 when they stay global)
     extern __shared__ uint64_t s_lds[];
-    uint64_t *const s_dyn = s_lds + (size_t)sub * (lds_ind_bytes(sup_words, bits_words, acol_words) / 8);
+    uint64_t *const s_dyn =
+        s_lds + (size_t)sub * (lds_ind_bytes(sup_words, bits_words, acol_words) / 8);
     uint64_t *s_sup = s_dyn;
     int32_t *s_pd = reinterpret_cast<int32_t *>(s_dyn + sup_words);
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(s_pd + EBIC_MAX_K);
@@ -614,7 +615,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
     // grid rather than pairing up. Slots past the last (total) stay idle:
     // they pass the workgroup's barriers, then end; their loads below read
     // the last slot's
-    const int32_t G = ipw == 1 ? total : ipw == 2 ? (total + 1) >> 1 : (total + 3) >> 2;  // ceil(total / ipw)
+    // G = ceil(total / ipw), ipw being 1, 2 or 4
+    const int32_t G = ipw == 1 ? total : ipw == 2 ? (total + 1) >> 1 : (total + 3) >> 2;
     const int64_t slot0 = (int64_t)blockIdx.x + (int64_t)sub * G;
     bool idle = slot0 >= total;
     const uint32_t slot = idle ? (uint32_t)(total - 1) : (uint32_t)slot0;
@@ -730,7 +732,8 @@ __global__ void __launch_bounds__(kMaxWaves * kWave) __attribute__((amdgpu_num_s
                     const int lo = a < c ? a : c, hi = a < c ? c : a;
                     if (hi < j_ncols) {
                         const int64_t pi = pair_index(lo, hi, j_ncols);
-                        s_pd[j] = flat ? (int32_t)((uint32_t)(pi * j_pstride * 8) | (a > c ? 1u : 0u))
+                        s_pd[j] = flat ? (int32_t)((uint32_t)(pi * j_pstride * 8) |
+                                                   (a > c ? 1u : 0u))
                                        : (int32_t)pi | (a > c ? (int32_t)0x80000000 : 0);
                     }
                 }
@@ -1494,7 +1497,8 @@ int batch_run(Batch *b, hipStream_t stream) {
     if (!b) return fail(EBIC_ERR_INVALID_ARG, "batch is NULL");
     if (b->total_ind == 0) return EBIC_OK;
     if (b->total_ind > INT32_MAX)
-        return fail(EBIC_ERR_INVALID_ARG, "%lld individuals in one launch", (long long)b->total_ind);
+        return fail(EBIC_ERR_INVALID_ARG, "%lld individuals in one launch",
+                    (long long)b->total_ind);
     if ((b->flags & EBIC_BATCH_TUNE) && !b->tuned) {
         int rc = tune(b, stream);
         if (rc) return rc;
