@@ -477,10 +477,12 @@ typedef struct ebic_server_metrics {
 /* Creates the server on the current device; the scheduler and each
  * preparer thread use a stream of their own. Errors: EBIC_ERR_INVALID_ARG, EBIC_ERR_DEVICE. */
 int ebic_server_create(const ebic_server_config *cfg, ebic_server **out);
-/* Queues a job (the host matrix is copied; parameters validated as for
- * ebic_run); never waits for the GPU. *job_id identifies it. Errors:
- * EBIC_ERR_INVALID_ARG. A job whose footprint exceeds the whole budget fails
- * with EBIC_ERR_CAPACITY when the scheduler reaches it. */
+/* Queues a job (the host matrix is copied before the call returns, by
+ * several threads when it is large; parameters validated as for ebic_run);
+ * never waits for the GPU. *job_id identifies it. Errors:
+ * EBIC_ERR_INVALID_ARG, EBIC_ERR_OOM (no host memory for the copy). A job
+ * whose footprint exceeds the whole budget fails with EBIC_ERR_CAPACITY when
+ * the scheduler reaches it. */
 int ebic_server_submit(ebic_server *s, const float *h_x, int32_t rows, int32_t cols,
                        const ebic_params *p, uint64_t seed, int64_t *job_id);
 /* EBIC_PENDING while the job is queued or running; EBIC_OK with *out set

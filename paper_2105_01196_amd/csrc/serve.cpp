@@ -14,8 +14,11 @@
 // job waits for the slowest one; the tick's buffers (one of a few slots)
 // stay reserved until those steps have read them. Finished jobs release
 // their device memory and slot.
+#include <sys/mman.h>
+
 #include <algorithm>
 #include <chrono>
+#include <cstring>
 #include <condition_variable>
 #include <deque>
 #include <functional>
@@ -104,9 +107,55 @@ class WorkerPool {
     bool quit_ = false;
 };
 
+// The server's own copy of a submitted matrix, made before submit returns
+// (the caller may free theirs then). Fresh pages fault in on first write,
+// which made one thread's copy of the serving mix's 1.75 GB take 0.39 s, so
+// a large matrix is copied by several threads, into memory that may use
+// 2 MB pages.
+class HostCopy {
+  public:
+    HostCopy() = default;
+    HostCopy(const HostCopy &) = delete;
+    HostCopy &operator=(const HostCopy &) = delete;
+    ~HostCopy() { clear(); }
+    bool assign(const float *src, size_t n) {
+        clear();
+        const size_t bytes = n * sizeof(float);
+        void *m = mmap(nullptr, bytes, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+        if (m == MAP_FAILED) return false;
+        (void)madvise(m, bytes, MADV_HUGEPAGE);  // a hint: refused where not enabled
+        p_ = static_cast<float *>(m);
+        bytes_ = bytes;
+        // slices of at least kSlice bytes, at most kThreads of them
+        constexpr size_t kSlice = size_t(32) << 20;
+        constexpr size_t kThreads = 16;
+        const size_t parts = std::min(kThreads, std::max<size_t>(1, bytes / kSlice));
+        const size_t per = (n + parts - 1) / parts;
+        auto copy = [&](size_t q) {
+            const size_t b = q * per, e = std::min(n, b + per);
+            if (b < e) std::memcpy(p_ + b, src + b, (e - b) * sizeof(float));
+        };
+        std::vector<std::thread> th;
+        for (size_t q = 1; q < parts; q++) th.emplace_back(copy, q);
+        copy(0);
+        for (auto &t : th) t.join();
+        return true;
+    }
+    float *data() { return p_; }
+    void clear() {
+        if (p_) munmap(p_, bytes_);
+        p_ = nullptr;
+        bytes_ = 0;
+    }
+
+  private:
+    float *p_ = nullptr;
+    size_t bytes_ = 0;
+};
+
 struct ServerJob {
     int64_t id = 0;
-    std::vector<float> x;
+    HostCopy x;
     int32_t rows = 0, cols = 0;
     ebic_params params{};
     uint64_t seed = 0;
@@ -259,7 +308,8 @@ int Server::submit(const float *h_x, int32_t rows, int32_t cols, const ebic_para
         (int64_t)cols * rows_padded(rows) > INT32_MAX)
         return fail(EBIC_ERR_INVALID_ARG, "matrix shape %d x %d not supported", rows, cols);
     auto j = std::make_shared<ServerJob>();
-    j->x.assign(h_x, h_x + (size_t)rows * cols);
+    if (!j->x.assign(h_x, (size_t)rows * cols))
+        return fail(EBIC_ERR_OOM, "host copy of a %d x %d matrix", rows, cols);
     j->rows = rows;
     j->cols = cols;
     j->params = *p;
@@ -556,7 +606,6 @@ void Server::release_loop() {
         for (auto &j : gone) {
             j->job.reset();
             j->x.clear();
-            j->x.shrink_to_fit();
         }
         {
             std::lock_guard<std::mutex> lk(mu_);
