@@ -17,6 +17,7 @@
 #include <sys/mman.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <condition_variable>
@@ -46,7 +47,8 @@ double now_s() {
 
 // Fixed pool of host threads. Jobs' host steps are queued as tasks (each job
 // runs its own as soon as its scores are in); parallel(n, fn) runs fn(0..n-1)
-// ahead of the queued tasks and returns when all n are done.
+// on the calling thread and on workers ahead of the queued tasks, and
+// returns when all n are done.
 class WorkerPool {
   public:
     explicit WorkerPool(int n) {
@@ -67,23 +69,41 @@ class WorkerPool {
         }
         cv_.notify_one();
     }
+    // fn(0) .. fn(n - 1), the calling thread among the workers: it takes
+    // items itself, so a pool busy with long tasks does not hold it up.
+    // Helpers go to the front of the queue; one that starts after every item
+    // is taken returns without touching fn (its state is shared, not on the
+    // caller's stack).
     void parallel(size_t n, const std::function<void(size_t)> &fn) {
         if (n == 0) return;
-        std::mutex m;
-        std::condition_variable done;
-        size_t left = n;
-        {
-            std::lock_guard<std::mutex> lk(mu_);
-            for (size_t i = n; i-- > 0;)  // front of the queue, fn(0) first
-                tasks_.push_front([&, i] {
-                    fn(i);
-                    std::lock_guard<std::mutex> l(m);
-                    if (--left == 0) done.notify_all();
-                });
+        struct State {
+            std::atomic<size_t> next{0};
+            std::mutex m;
+            std::condition_variable done;
+            size_t finished = 0;
+            const std::function<void(size_t)> *fn = nullptr;
+        };
+        auto st = std::make_shared<State>();
+        st->fn = &fn;
+        auto body = [](State &s, size_t n) {
+            for (size_t i; (i = s.next.fetch_add(1)) < n;) {
+                (*s.fn)(i);
+                std::lock_guard<std::mutex> l(s.m);
+                if (++s.finished == n) s.done.notify_all();
+            }
+        };
+        const size_t helpers = std::min(n - 1, threads_.size());
+        if (helpers > 0) {
+            {
+                std::lock_guard<std::mutex> lk(mu_);
+                for (size_t h = 0; h < helpers; h++)
+                    tasks_.push_front([st, n, body] { body(*st, n); });
+            }
+            cv_.notify_all();
         }
-        cv_.notify_all();
-        std::unique_lock<std::mutex> l(m);
-        done.wait(l, [&] { return left == 0; });
+        body(*st, n);
+        std::unique_lock<std::mutex> l(st->m);
+        st->done.wait(l, [&] { return st->finished == n; });
     }
 
   private:
@@ -409,7 +429,9 @@ namespace {
 template <typename T>
 int grow(PinnedArray<T> &h, DeviceArray<T> &d, size_t count) {
     if (count <= h.n && h.p) return EBIC_OK;
-    const size_t room = count + count / 4 + 512;
+    // doubling: every regrowth frees (device-synchronizing) and allocates
+    // pinned memory, and a tick's buffers grow as more jobs join them
+    const size_t room = 2 * count + 512;
     EBIC_HIP(h.alloc(room));
     EBIC_HIP(d.alloc(room));
     return EBIC_OK;
@@ -417,7 +439,7 @@ int grow(PinnedArray<T> &h, DeviceArray<T> &d, size_t count) {
 template <typename T>
 int grow(DeviceArray<T> &d, size_t count) {
     if (count <= d.n && d.p) return EBIC_OK;
-    EBIC_HIP(d.alloc(count + count / 4 + 512));
+    EBIC_HIP(d.alloc(2 * count + 512));
     return EBIC_OK;
 }
 }  // namespace
