@@ -1380,10 +1380,17 @@ __global__ void dl_resume_kernel(DlBufs B) {
 }
 
 // The population in buffer `which` packed as CSR for the evaluator (with
-// `check`, only while the run goes on). One workgroup.
+// `check`, only while the run goes on). One workgroup. With size_field set
+// it first does dl_patch_kernel's work for the next evaluation (the list is
+// final for the generation by then), whether or not the run goes on.
 __global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, int which, int n,
-                                                         int check) {
+                                                         int check, int32_t *size_field,
+                                                         int32_t *len_field) {
     __shared__ int s_tmp[33];
+    if (size_field && threadIdx.x == 0) {
+        *size_field = B.st->nA;
+        *len_field = B.st->arch_len;
+    }
     if (check && (B.st->over || B.st->stalled)) return;
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (n + nt - 1) / nt, lo = tid * per, hi = lo + per < n ? lo + per : n;
@@ -1638,7 +1645,8 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             DL_HIP(hipStreamSynchronize(stream));  // before the host copies go out of scope
         }
         if (Pn0 > 0) {
-            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, 0, Pn0, 0);
+            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, 0, Pn0, 0,
+                               (int32_t *)nullptr, (int32_t *)nullptr);
             hipLaunchKernelGGL(dl_copy_kernel, dim3((Pn0 + 3) / 4), dim3(256), 0, stream, q, B, 0,
                                Pn0, 0);
             DL_HIP(hipGetLastError());
@@ -1661,8 +1669,10 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         return EBIC_OK;
     };
 
-    // The evaluator's batch, laid out once for the largest list; before each
-    // evaluation a kernel copies the list's size and length into its table.
+    // The evaluator's batch, laid out once for the largest list; the list's
+    // size and length go into its table before each evaluation: before the
+    // first from a kernel of their own, later from the previous generation's
+    // pack kernel.
     {
         ebic_job v{};
         v.matrix = job.m_;
@@ -1718,8 +1728,11 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     const int nq_hi = std::max(nq_lo, (P + P / 2 + 64 + kChunkMax - 1) / kChunkMax);
     auto queue_generation = [&](int gi, int nq) -> int {
         const int cur = gi & 1, Pn = gi == 0 ? Pn0 : P;
-        hipLaunchKernelGGL(dl_patch_kernel, dim3(1), dim3(64), 0, stream, B, f_size, f_len);
-        DL_HIP(hipGetLastError());
+        // later generations take the list's size from the previous one's pack
+        if (gi == 0) {
+            hipLaunchKernelGGL(dl_patch_kernel, dim3(1), dim3(64), 0, stream, B, f_size, f_len);
+            DL_HIP(hipGetLastError());
+        }
         if (Pn > 0) {
             int r = batch_run(*batch, stream);
             if (r) return r;
@@ -1734,7 +1747,8 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             int r = chunk(cur, Pn, P, c == nq - 1);
             if (r) return r;
         }
-        hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P, 1);
+        hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P, 1,
+                           f_size, f_len);
         hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B, cur ^ 1, P,
                            1);
         DL_HIP(hipGetLastError());
@@ -1811,7 +1825,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             }
             if (hs.p->over) break;
             hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P,
-                               1);
+                               1, f_size, f_len);
             hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B,
                                cur ^ 1, P, 1);
             DL_HIP(hipGetLastError());
