@@ -762,19 +762,11 @@ __global__ void __launch_bounds__(kBlock) dl_list_kernel(DlParams q, DlBufs B, i
 }
 
 // Step 5, tournament keys: each fitness halved once per column of the
-// individual that more individuals hold than ceil(sum k / C). Two grid-wide
-// kernels, a wave per individual: the column use counts (into the count
-// array of the population's parity), then the keys (the counts of the other
-// parity are cleared for the next generation).
-__global__ void __launch_bounds__(256) dl_use_kernel(DlParams q, DlBufs B, int cur, int Pn) {
-    if (B.st->over || B.st->stalled) return;
-    const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
-    if (i >= Pn) return;
-    const int k = B.plen[cur][i];
-    const uint16_t *s = B.pop[cur] + (size_t)i * q.kmax;
-    for (int e = lane; e < k; e += kWave) atomicAdd(&B.use[cur][s[e]], 1);
-}
-
+// individual that more individuals hold than ceil(sum k / C). The column use
+// counts (into the count array of the population's parity) are taken when
+// the population is copied for the evaluator (dl_copy_kernel); this kernel,
+// a wave per individual, makes the keys and clears the counts of the other
+// parity for the next population.
 __global__ void __launch_bounds__(256) dl_keys_kernel(DlParams q, DlBufs B, int cur, int Pn) {
     if (B.st->over || B.st->stalled) return;
     const int gt = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1406,7 +1398,9 @@ __global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, i
 }
 
 // The columns of the packed population, a wave per individual (after
-// dl_pack_kernel).
+// dl_pack_kernel), and their use counts for the crowding keys (the counts of
+// buffer `which` were cleared by the keys kernel of the generation before;
+// a population is copied once).
 __global__ void __launch_bounds__(256) dl_copy_kernel(DlParams q, DlBufs B, int which, int n,
                                                       int check) {
     if (check && (B.st->over || B.st->stalled)) return;
@@ -1414,7 +1408,11 @@ __global__ void __launch_bounds__(256) dl_copy_kernel(DlParams q, DlBufs B, int 
     if (i >= n) return;
     const int k = B.plen[which][i], o = B.csr_off[i];
     const uint16_t *s = B.pop[which] + (size_t)i * q.kmax;
-    for (int e = lane; e < k; e += kWave) B.csr_cols[o + e] = s[e];
+    for (int e = lane; e < k; e += kWave) {
+        const uint16_t c = s[e];
+        B.csr_cols[o + e] = c;
+        atomicAdd(&B.use[which][c], 1);
+    }
 }
 
 // ---- host driver ----
@@ -1739,7 +1737,6 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         }
         hipLaunchKernelGGL(dl_list_kernel, dim3(1), dim3(kBlock), lds_list, stream, q, B, cur, Pn,
                            Ppad);
-        hipLaunchKernelGGL(dl_use_kernel, dim3((Pn + 3) / 4), dim3(256), 0, stream, q, B, cur, Pn);
         hipLaunchKernelGGL(dl_keys_kernel, dim3((std::max(Pn, C / 64 + 1) + 3) / 4), dim3(256), 0,
                            stream, q, B, cur, Pn);
         DL_HIP(hipGetLastError());
