@@ -1111,6 +1111,9 @@ __global__ void __launch_bounds__(kChildWaves *kWave) dl_child_kernel(DlParams q
     }
 }
 
+// (defined with dl_pack_kernel below)
+__device__ void pack_offsets(DlBufs B, int which, int n, int *s_tmp);
+
 // Steps 5-6 in attempt order, for the chunk: a child repeating an earlier
 // child of the chunk (same canonical series) or one in the tabu set is a tabu
 // hit; a child of the wrong length (or none) fails; the rest fill the
@@ -1308,6 +1311,10 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
         // the rest of it
         if (last_chunk && st->need_more && !st->stop) st->stalled = 1;
     }
+    // the fill is complete: the next population's offsets for the evaluator
+    // (every length is written: the elites' by the list update, the
+    // children's above, before the scans' barriers)
+    if (kind == 2) pack_offsets(B, cur ^ 1, q.P, s_tmp);
 }
 
 // Inserts canonical series into the tabu set, a wave each: the chunk's
@@ -1371,19 +1378,9 @@ __global__ void dl_resume_kernel(DlBufs B) {
     if (threadIdx.x == 0) B.st->stalled = 0;
 }
 
-// The population in buffer `which` packed as CSR for the evaluator (with
-// `check`, only while the run goes on). One workgroup. With size_field set
-// it first does dl_patch_kernel's work for the next evaluation (the list is
-// final for the generation by then), whether or not the run goes on.
-__global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, int which, int n,
-                                                         int check, int32_t *size_field,
-                                                         int32_t *len_field) {
-    __shared__ int s_tmp[33];
-    if (size_field && threadIdx.x == 0) {
-        *size_field = B.st->nA;
-        *len_field = B.st->arch_len;
-    }
-    if (check && (B.st->over || B.st->stalled)) return;
+// The population in buffer `which` packed as CSR for the evaluator: its
+// offsets, by one workgroup (s_tmp holds 33 ints).
+__device__ void pack_offsets(DlBufs B, int which, int n, int *s_tmp) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int per = (n + nt - 1) / nt, lo = tid * per, hi = lo + per < n ? lo + per : n;
     int sum = 0;
@@ -1397,12 +1394,29 @@ __global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, i
     if (tid == 0) B.csr_off[n] = total;
 }
 
-// The columns of the packed population, a wave per individual (after
-// dl_pack_kernel), and their use counts for the crowding keys (the counts of
+// pack_offsets as a kernel of its own (with `check`, only while the run goes
+// on): for the first population and after a stalled fill; the acceptance
+// kernel packs the population whose fill it completes.
+__global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, int which, int n,
+                                                         int check) {
+    __shared__ int s_tmp[33];
+    if (check && (B.st->over || B.st->stalled)) return;
+    pack_offsets(B, which, n, s_tmp);
+}
+
+// The columns of the packed population, a wave per individual (after its
+// offsets), and their use counts for the crowding keys (the counts of
 // buffer `which` were cleared by the keys kernel of the generation before;
-// a population is copied once).
+// a population is copied once). With size_field set it first does
+// dl_patch_kernel's work for the next evaluation (the list is final for the
+// generation by then), whether or not the run goes on.
 __global__ void __launch_bounds__(256) dl_copy_kernel(DlParams q, DlBufs B, int which, int n,
-                                                      int check) {
+                                                      int check, int32_t *size_field,
+                                                      int32_t *len_field) {
+    if (size_field && blockIdx.x == 0 && threadIdx.x == 0) {
+        *size_field = B.st->nA;
+        *len_field = B.st->arch_len;
+    }
     if (check && (B.st->over || B.st->stalled)) return;
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     if (i >= n) return;
@@ -1643,10 +1657,9 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             DL_HIP(hipStreamSynchronize(stream));  // before the host copies go out of scope
         }
         if (Pn0 > 0) {
-            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, 0, Pn0, 0,
-                               (int32_t *)nullptr, (int32_t *)nullptr);
+            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, 0, Pn0, 0);
             hipLaunchKernelGGL(dl_copy_kernel, dim3((Pn0 + 3) / 4), dim3(256), 0, stream, q, B, 0,
-                               Pn0, 0);
+                               Pn0, 0, (int32_t *)nullptr, (int32_t *)nullptr);
             DL_HIP(hipGetLastError());
         }
         DL_HIP(hipStreamSynchronize(stream));
@@ -1670,7 +1683,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     // The evaluator's batch, laid out once for the largest list; the list's
     // size and length go into its table before each evaluation: before the
     // first from a kernel of their own, later from the previous generation's
-    // pack kernel.
+    // copy kernel.
     {
         ebic_job v{};
         v.matrix = job.m_;
@@ -1726,7 +1739,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     const int nq_hi = std::max(nq_lo, (P + P / 2 + 64 + kChunkMax - 1) / kChunkMax);
     auto queue_generation = [&](int gi, int nq) -> int {
         const int cur = gi & 1, Pn = gi == 0 ? Pn0 : P;
-        // later generations take the list's size from the previous one's pack
+        // later generations take the list's size from the previous one's copy
         if (gi == 0) {
             hipLaunchKernelGGL(dl_patch_kernel, dim3(1), dim3(64), 0, stream, B, f_size, f_len);
             DL_HIP(hipGetLastError());
@@ -1744,10 +1757,9 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             int r = chunk(cur, Pn, P, c == nq - 1);
             if (r) return r;
         }
-        hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P, 1,
-                           f_size, f_len);
+        // (the acceptance kernel that completes the fill packs the offsets)
         hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B, cur ^ 1, P,
-                           1);
+                           1, f_size, f_len);
         DL_HIP(hipGetLastError());
         return EBIC_OK;
     };
@@ -1822,9 +1834,9 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             }
             if (hs.p->over) break;
             hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P,
-                               1, f_size, f_len);
+                               1);
             hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B,
-                               cur ^ 1, P, 1);
+                               cur ^ 1, P, 1, f_size, f_len);
             DL_HIP(hipGetLastError());
         }
         if (hs.p->g >= q.G) return fail(EBIC_ERR_DEVICE, "device loop: no stop after %d generations",
