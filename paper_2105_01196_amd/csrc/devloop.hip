@@ -1697,9 +1697,10 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     int32_t *f_size = nullptr, *f_len = nullptr;
     rc = batch_archive_fields(*batch, 0, &f_size, &f_len);
     if (rc) return rc;
-    // The generations run on a stream of their own when the caller's is the
-    // null stream (which cannot be captured into a graph); everything before
-    // is finished first, and the loop ends with its stream synchronized.
+    // The generations run on a stream of their own (non-blocking) when the
+    // caller's is the null stream, which would wait on other streams' work
+    // between launches; everything before is finished first, and the loop
+    // ends with its stream synchronized.
     struct OwnStream {
         hipStream_t s = nullptr;
         ~OwnStream() {
@@ -1763,52 +1764,12 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
         DL_HIP(hipGetLastError());
         return EBIC_OK;
     };
-    // Generations after the first replay captured graphs, one per
-    // population parity (every kernel argument is the same otherwise) and
-    // chunk count, captured when first needed; this saves the launch cost of
-    // a generation's kernels. Without them (capture unavailable) the kernels
-    // are launched one by one.
-    struct Graphs {
-        hipGraph_t g[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-        hipGraphExec_t x[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
-        ~Graphs() {
-            for (int i = 0; i < 2; i++)
-                for (int v = 0; v < 2; v++) {
-                    if (x[i][v]) (void)hipGraphExecDestroy(x[i][v]);
-                    if (g[i][v]) (void)hipGraphDestroy(g[i][v]);
-                }
-        }
-    } graphs;
-    bool use_graphs = Pn0 == P && stream != nullptr && q.G > 2;
-    auto capture = [&](int v) {
-        for (int par = 0; par < 2 && use_graphs; par++) {
-            if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
-                use_graphs = false;
-                break;
-            }
-            // any generation after the first of this parity
-            const int r = queue_generation(2 + par, v ? nq_hi : nq_lo);
-            hipGraph_t gr = nullptr;
-            const hipError_t e = hipStreamEndCapture(stream, &gr);
-            graphs.g[par][v] = gr;
-            if (r || e != hipSuccess || !gr ||
-                hipGraphInstantiate(&graphs.x[par][v], gr, nullptr, nullptr, 0) != hipSuccess)
-                use_graphs = false;
-        }
-        (void)hipGetLastError();  // a refused capture leaves nothing for later calls
-    };
+    // Each generation's kernels are launched one by one, a few generations
+    // ahead of the GPU: on batched-10000x500, replaying each generation from
+    // a captured graph (one per population parity and chunk count) took
+    // 262-265 us a generation against 252-256 us launched directly.
     int variant = 0;  // 1 once a fill has stalled: nq_hi chunks from then on
-    capture(0);
-    auto queue = [&](int gi) -> int {
-        if (gi > 0 && use_graphs) {
-            if (!graphs.x[gi & 1][variant]) capture(variant);
-            if (use_graphs) {
-                DL_HIP(hipGraphLaunch(graphs.x[gi & 1][variant], stream));
-                return EBIC_OK;
-            }
-        }
-        return queue_generation(gi, variant ? nq_hi : nq_lo);
-    };
+    auto queue = [&](int gi) -> int { return queue_generation(gi, variant ? nq_hi : nq_lo); };
     // generations are queued a few at a time; the host reads the state
     // between groups
     constexpr int kAhead = 8;
