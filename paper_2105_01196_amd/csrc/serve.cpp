@@ -156,7 +156,12 @@ class HostCopy {
             if (b < e) std::memcpy(p_ + b, src + b, (e - b) * sizeof(float));
         };
         std::vector<std::thread> th;
-        for (size_t q = 1; q < parts; q++) th.emplace_back(copy, q);
+        size_t q = 1;
+        try {
+            for (; q < parts; q++) th.emplace_back(copy, q);
+        } catch (...) {  // no thread to be had: this one copies the rest
+        }
+        for (size_t r = q; r < parts; r++) copy(r);
         copy(0);
         for (auto &t : th) t.join();
         return true;
