@@ -77,6 +77,9 @@ struct DlState {
     int32_t pending;      // the chunk's accepted children await insertion
     int32_t stalled;      // a fill needs more chunks than were queued: kernels
                           // wait (do nothing) until the host has finished it
+    int32_t packed;       // the chunk's acceptance completed the fill and packed
+                          // its offsets: its insert kernel copies the population
+    int32_t chunk_first;  // slots filled before the chunk (Nn at its start)
     int32_t slot[EBIC_MAX_ARCHIVE + 2];   // the list in rank order: slot ids
     int32_t a_len[EBIC_MAX_ARCHIVE + 2];  // per slot id: length, rows, score
     int32_t a_n[EBIC_MAX_ARCHIVE + 2];
@@ -1306,6 +1309,8 @@ __global__ void __launch_bounds__(kBlock) dl_accept_kernel(DlParams q, DlBufs B,
         st->tabu_n = tabu0 + used_acc;
         if (tabu0 + used_acc > q.tabu_cap) st->error = 1;
         st->pending = 1;
+        st->packed = kind == 2;
+        st->chunk_first = Nn0;
         if (st->stop) st->over = 1;
         // the queued chunks are used up and the fill goes on: the host runs
         // the rest of it
@@ -1325,9 +1330,30 @@ constexpr int kInsertWaves = 4;
 
 __global__ void __launch_bounds__(kInsertWaves *kWave)
     dl_insert_kernel(DlParams q, DlBufs B, const uint16_t *cols, const int32_t *lens,
-                     const uint32_t *flags, const uint64_t *hashes, int n, int nxt) {
+                     const uint32_t *flags, const uint64_t *hashes, int n, int nxt,
+                     int32_t *size_field, int32_t *len_field) {
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int i = blockIdx.x * kInsertWaves + wave;
+    // the list's size and length into the evaluator's table (final for the
+    // generation by now), whether or not the run goes on
+    if (size_field && blockIdx.x == 0 && threadIdx.x == 0) {
+        *size_field = B.st->nA;
+        *len_field = B.st->arch_len;
+    }
+    // a fill completed by this chunk: the population packed for the
+    // evaluator with its columns' use counts (dl_copy_kernel's work), the
+    // slots filled before the chunk from the population, the chunk's
+    // children below from their source
+    const bool pack = flags && B.st->pending && B.st->packed;
+    if (pack && i < B.st->chunk_first) {
+        const int k = B.plen[nxt][i], o = B.csr_off[i];
+        const uint16_t *src = B.pop[nxt] + (size_t)i * q.kmax;
+        for (int e = lane; e < k; e += kWave) {
+            const uint16_t c = src[e];
+            B.csr_cols[o + e] = c;
+            atomicAdd(&B.use[nxt][c], 1);
+        }
+    }
     if (i >= n) return;
     const int kmax = q.kmax;
     const int len = lens[i];
@@ -1342,6 +1368,13 @@ __global__ void __launch_bounds__(kInsertWaves *kWave)
         h = hashes[i];
         const int slot = B.cslot[i];
         for (int j = lane; j < len; j += kWave) B.pop[nxt][(size_t)slot * kmax + j] = s[j];
+        if (pack) {
+            const int o = B.csr_off[slot];
+            for (int j = lane; j < len; j += kWave) {
+                B.csr_cols[o + j] = s[j];
+                atomicAdd(&B.use[nxt][s[j]], 1);
+            }
+        }
     } else {
         uint64_t hl = 0;
         for (int j = lane; j < len; j += kWave) hl ^= col_hash(s[j], j, len);
@@ -1395,8 +1428,8 @@ __device__ void pack_offsets(DlBufs B, int which, int n, int *s_tmp) {
 }
 
 // pack_offsets as a kernel of its own (with `check`, only while the run goes
-// on): for the first population and after a stalled fill; the acceptance
-// kernel packs the population whose fill it completes.
+// on), for the first population; the acceptance kernel packs each later
+// population, the one whose fill it completes.
 __global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, int which, int n,
                                                          int check) {
     __shared__ int s_tmp[33];
@@ -1404,19 +1437,11 @@ __global__ void __launch_bounds__(kBlock) dl_pack_kernel(DlParams q, DlBufs B, i
     pack_offsets(B, which, n, s_tmp);
 }
 
-// The columns of the packed population, a wave per individual (after its
-// offsets), and their use counts for the crowding keys (the counts of
-// buffer `which` were cleared by the keys kernel of the generation before;
-// a population is copied once). With size_field set it first does
-// dl_patch_kernel's work for the next evaluation (the list is final for the
-// generation by then), whether or not the run goes on.
+// The columns of the first population packed for the evaluator, a wave per
+// individual (after its offsets), and their use counts for the crowding keys
+// (later populations: the insert kernel of the chunk that completes a fill).
 __global__ void __launch_bounds__(256) dl_copy_kernel(DlParams q, DlBufs B, int which, int n,
-                                                      int check, int32_t *size_field,
-                                                      int32_t *len_field) {
-    if (size_field && blockIdx.x == 0 && threadIdx.x == 0) {
-        *size_field = B.st->nA;
-        *len_field = B.st->arch_len;
-    }
+                                                      int check) {
     if (check && (B.st->over || B.st->stalled)) return;
     const int i = (blockIdx.x * blockDim.x + threadIdx.x) / kWave, lane = threadIdx.x % kWave;
     if (i >= n) return;
@@ -1652,14 +1677,14 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
                                   stream));
             hipLaunchKernelGGL(dl_insert_kernel, dim3((nt + kInsertWaves - 1) / kInsertWaves),
                                dim3(kInsertWaves * kWave), 0, stream, q, B, dtc.p, dtl.p, nullptr,
-                               nullptr, nt, 0);
+                               nullptr, nt, 0, (int32_t *)nullptr, (int32_t *)nullptr);
             DL_HIP(hipGetLastError());
             DL_HIP(hipStreamSynchronize(stream));  // before the host copies go out of scope
         }
         if (Pn0 > 0) {
             hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, 0, Pn0, 0);
             hipLaunchKernelGGL(dl_copy_kernel, dim3((Pn0 + 3) / 4), dim3(256), 0, stream, q, B, 0,
-                               Pn0, 0, (int32_t *)nullptr, (int32_t *)nullptr);
+                               Pn0, 0);
             DL_HIP(hipGetLastError());
         }
         DL_HIP(hipStreamSynchronize(stream));
@@ -1683,7 +1708,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     // The evaluator's batch, laid out once for the largest list; the list's
     // size and length go into its table before each evaluation: before the
     // first from a kernel of their own, later from the previous generation's
-    // copy kernel.
+    // insert kernels.
     {
         ebic_job v{};
         v.matrix = job.m_;
@@ -1721,10 +1746,12 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
                            dim3(kChildWaves * kWave), 0, stream, q, B, cur, Pn);
         hipLaunchKernelGGL(dl_accept_kernel, dim3(1), dim3(kBlock), (size_t)kDedupSlots * 8,
                            stream, q, B, (const int32_t *)att_end.p, cur, last);
-        hipLaunchKernelGGL(dl_insert_kernel, dim3((A_target + kInsertWaves - 1) / kInsertWaves),
+        // a wave per attempt, and per individual for the population's copy
+        const int waves = std::max(A_target, P);
+        hipLaunchKernelGGL(dl_insert_kernel, dim3((waves + kInsertWaves - 1) / kInsertWaves),
                            dim3(kInsertWaves * kWave), 0, stream, q, B, (const uint16_t *)child.p,
                            (const int32_t *)clen.p, (const uint32_t *)cflag.p,
-                           (const uint64_t *)chash.p, A_target, cur ^ 1);
+                           (const uint64_t *)chash.p, A_target, cur ^ 1, f_size, f_len);
         DL_HIP(hipGetLastError());
         return EBIC_OK;
     };
@@ -1740,7 +1767,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
     const int nq_hi = std::max(nq_lo, (P + P / 2 + 64 + kChunkMax - 1) / kChunkMax);
     auto queue_generation = [&](int gi, int nq) -> int {
         const int cur = gi & 1, Pn = gi == 0 ? Pn0 : P;
-        // later generations take the list's size from the previous one's copy
+        // later generations take the list's size from the previous one's insert
         if (gi == 0) {
             hipLaunchKernelGGL(dl_patch_kernel, dim3(1), dim3(64), 0, stream, B, f_size, f_len);
             DL_HIP(hipGetLastError());
@@ -1758,10 +1785,8 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
             int r = chunk(cur, Pn, P, c == nq - 1);
             if (r) return r;
         }
-        // (the acceptance kernel that completes the fill packs the offsets)
-        hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B, cur ^ 1, P,
-                           1, f_size, f_len);
-        DL_HIP(hipGetLastError());
+        // (the acceptance kernel that completes the fill packs the offsets,
+        // the chunk's insert kernel the columns)
         return EBIC_OK;
     };
     // Each generation's kernels are launched one by one, a few generations
@@ -1794,11 +1819,7 @@ int DevLoopAccess::run(Job &job, Batch **batch, hipStream_t stream) {
                 if (!hs.p->need_more || hs.p->stop) break;
             }
             if (hs.p->over) break;
-            hipLaunchKernelGGL(dl_pack_kernel, dim3(1), dim3(kBlock), 0, stream, q, B, cur ^ 1, P,
-                               1);
-            hipLaunchKernelGGL(dl_copy_kernel, dim3((P + 3) / 4), dim3(256), 0, stream, q, B,
-                               cur ^ 1, P, 1, f_size, f_len);
-            DL_HIP(hipGetLastError());
+            // the chunk that completed the fill has packed the population
         }
         if (hs.p->g >= q.G) return fail(EBIC_ERR_DEVICE, "device loop: no stop after %d generations",
                                          hs.p->g);
